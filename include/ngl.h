@@ -1,0 +1,255 @@
+/*
+ * ngl.h -- C ABI of the MI355X (gfx950) neural geometric LOD library.
+ *
+ * The library evaluates a neural signed distance function stored as a
+ * sparse voxel octree of corner feature vectors (Takikawa et al., "Neural
+ * Geometric Level of Detail", arXiv 2101.10994, Sec. 3.2) and sphere-traces
+ * rays through it (Sec. 3.4).  Entry points follow the paper's statement of
+ * the problem: build the octree from occupancy, query the SDF at a discrete
+ * or continuous LOD, trace rays, take a training step.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ *  - Feature level l (1-based, l = 1..L) has grid resolution 4 * 2^(l-1)
+ *    and lives at octree depth l+1; depth d has resolution 2^d; the root
+ *    (depth 0) is the box [-1,1]^3 (App. A.1: the rendering octree starts at
+ *    1^3, features start at resolution 4).
+ *  - Canonical layout: at every depth voxels are numbered by increasing
+ *    Morton code (bit 3k = x, 3k+1 = y, 3k+2 = z); corners of a feature level
+ *    by the Morton code of their lattice point.  Child c of a voxel is cell
+ *    2*ijk + (c&1, c>>1&1, c>>2&1); corner slot j of a voxel is lattice
+ *    point ijk + (j&1, j>>1&1, j>>2&1).
+ *  - Points and rays are structure-of-arrays float32: x[3][P] means the P
+ *    x-coordinates, then the P y's, then the P z's.
+ *  - Pointers named "device" must point to GPU memory (any hipMalloc'd or
+ *    torch allocation on the current device); "host" pointers to CPU memory.
+ *    The caller owns every buffer; the library never allocates or frees
+ *    device memory and never synchronises the stream except where stated.
+ *  - `stream` is a hipStream_t (NULL = the null stream); all GPU work of a
+ *    call is enqueued on it in order.
+ *  - Every function returns an ngl_status; nothing throws across the ABI.
+ *    On error, ngl_last_error() returns a thread-local description.
+ *    Per-point and per-ray outcomes (a point outside the octree, a ray that
+ *    misses) are data, not errors.
+ */
+#ifndef NGL_H
+#define NGL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NGL_MAX_LODS 8
+#define NGL_MAX_DEPTH (NGL_MAX_LODS + 2)
+#define NGL_MAX_FEAT_DIM 64
+#define NGL_MAX_HIDDEN 256
+
+typedef enum {
+  NGL_OK = 0,
+  NGL_E_INVALID = 1,     /* bad argument (null pointer, size, lod, dtype) */
+  NGL_E_CAPACITY = 2,    /* a caller-sized buffer is too small; see the call */
+  NGL_E_HIP = 3,         /* a HIP runtime call failed */
+  NGL_E_UNSUPPORTED = 4  /* valid but unsupported combination */
+} ngl_status;
+
+typedef enum { NGL_F32 = 0, NGL_F16 = 1, NGL_BF16 = 2 } ngl_dtype;
+
+/* Per-ray outcome of ngl_sphere_trace. */
+typedef enum {
+  NGL_RAY_MISS = 0,      /* ran out of voxels along the ray */
+  NGL_RAY_HIT = 1,       /* SDF fell below the hit threshold */
+  NGL_RAY_MAX_STEPS = 2, /* step budget exhausted */
+  NGL_RAY_FAR = 3,       /* passed the far plane */
+  NGL_RAY_STALLED = 4,   /* oscillation rule fired (only if enabled) */
+  NGL_RAY_INVALID = 5    /* non-finite origin or direction */
+} ngl_ray_status;
+
+const char* ngl_status_str(int status);
+const char* ngl_last_error(void);
+int ngl_version(void);
+
+/* ------------------------------------------------------------------ */
+/* 1. Octree from occupancy (Sec. 3.2: a voxel exists only where there   */
+/*    is surface; Sec. 3.4: parents always exist, and the voxel-to-corner */
+/*    pointers are precomputed in an initialisation pass).  Host-side.    */
+/* ------------------------------------------------------------------ */
+
+/* Sizes of the octree built from `n` occupied finest cells ijk[n][3]
+ * (host, int32, each coordinate in [0, 2^(num_lods+1))), duplicates allowed.
+ * Depth-d voxels are the parent closure {cell >> (D-d)}, D = num_lods+1.
+ * Writes nvox[num_lods+2] (voxels per depth 0..D) and ncorner[num_lods]
+ * (distinct corner lattice points per feature level), both host.
+ * NGL_E_INVALID if num_lods is outside 1..NGL_MAX_LODS or a cell is out of
+ * range. */
+int ngl_octree_plan(const int32_t* ijk, int64_t n, int32_t num_lods, int64_t* nvox, int64_t* ncorner);
+
+/* Host output buffers of ngl_octree_fill, sized from ngl_octree_plan.
+ * Index d is a depth (0..D), index l-1 a feature level l (1..num_lods).
+ * Any pointer may be NULL to skip that array. */
+typedef struct {
+  uint32_t* cell[NGL_MAX_DEPTH];        /* [nvox[d]] packed cell x | y<<10 | z<<20 */
+  uint8_t* child_mask[NGL_MAX_DEPTH];   /* [nvox[d]] bit c set iff child c exists */
+  int32_t* first_child[NGL_MAX_DEPTH];  /* [nvox[d]] index of the first child at d+1 (-1: none) */
+  int32_t* parent[NGL_MAX_DEPTH];       /* [nvox[d]] index of the parent at d-1 (-1 at the root) */
+  int32_t* corners[NGL_MAX_LODS];       /* [nvox[l+1]][8] corner index of slot j */
+  int32_t* corner_cell[NGL_MAX_LODS];   /* [ncorner[l-1]][3] lattice point of each corner */
+} ngl_octree_host;
+
+/* Fill the canonical layout (same inputs as ngl_octree_plan). */
+int ngl_octree_fill(const int32_t* ijk, int64_t n, int32_t num_lods, const ngl_octree_host* out);
+
+/* ------------------------------------------------------------------ */
+/* Device view of a model: octree + corner features + per-LOD decoders.  */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int32_t num_lods;   /* L: feature levels, 1..NGL_MAX_LODS (octree depth L+1) */
+  int32_t feat_dim;   /* m: feature width, multiple of 8, <= NGL_MAX_FEAT_DIM */
+  int32_t hidden;     /* h: decoder hidden width, multiple of 16, <= NGL_MAX_HIDDEN */
+  int32_t with_xyz;   /* 1: decoder input is [x, y, z, z_0..z_{m-1}] (Eq. 2); 0: [z] */
+  int32_t feat_dtype; /* ngl_dtype of feat[] (F32, F16 or BF16) */
+  int32_t w_dtype;    /* ngl_dtype of W1[] (F32 or BF16); b1, w2, b2 are always F32 */
+  int64_t nvox[NGL_MAX_DEPTH];               /* voxels per depth 0..L+1 */
+  int64_t ncorner[NGL_MAX_LODS];             /* corners per level */
+  const uint32_t* cell[NGL_MAX_DEPTH];       /* device, packed cells per depth */
+  const uint8_t* child_mask[NGL_MAX_DEPTH];  /* device, depths 0..L */
+  const int32_t* first_child[NGL_MAX_DEPTH]; /* device, depths 0..L */
+  const int32_t* parent[NGL_MAX_DEPTH];      /* device, depths 1..L+1 */
+  const int32_t* corners[NGL_MAX_LODS];      /* device, [nvox[l+1]][8] */
+  const void* feat[NGL_MAX_LODS];            /* device, [ncorner[l-1]][m], feat_dtype */
+  const void* W1[NGL_MAX_LODS];              /* device, [h][din] row-major, w_dtype */
+  const float* b1[NGL_MAX_LODS];             /* device, [h] */
+  const float* w2[NGL_MAX_LODS];             /* device, [h] */
+  const float* b2;                           /* device, [L] */
+} ngl_model;
+
+/* ------------------------------------------------------------------ */
+/* 2. SDF query (Sec. 3.2, Eq. 2; continuous LOD, Eq. 3)                  */
+/* ------------------------------------------------------------------ */
+
+/* For each point x_p (device x[3][P]) the voxel containing it is found at
+ * every level l <= L' (L' = lod, or lod+1 when blending): cells are
+ * half-open [lo, hi) per axis with x = +1 in the last cell, computed
+ * exactly; points outside [-1,1]^3 have no voxel.  psi_l is the trilinear
+ * interpolation of the voxel's 8 corner features (0 if the voxel is absent),
+ * z_L = sum_{l<=L} psi_l, and sdf = f_{theta_L}([x, z_L]) (one hidden ReLU
+ * layer, linear output).  With alpha > 0 (scalar) or alpha_pp (device [P],
+ * nullable, values in [0,1)), sdf = (1-a) f_L + a f_{L+1} (needs
+ * lod < num_lods).
+ * Outputs (device): sdf[P]; valid[P] (nullable): 1 iff the level-L' voxel
+ * exists; vox_out[L'][P] (nullable): voxel index per level, -1 if absent.
+ * The decoder's first layer runs in FP32 when w_dtype is F32 and on the
+ * BF16 matrix cores with FP32 accumulation when w_dtype is BF16.
+ * Errors: NGL_E_INVALID for lod outside 1..num_lods, alpha outside [0,1),
+ * blending at lod == num_lods, or null required pointers. */
+int ngl_query_sdf(const ngl_model* m, const float* x, int64_t P, int32_t lod, float alpha,
+                  const float* alpha_pp, float* sdf, uint8_t* valid, int32_t* vox_out, void* stream);
+
+/* All discrete LODs at once: sdf_all[L][P] (device) with sdf_all[L-1][p] =
+ * f_{theta_L}([x_p, z_L(x_p)]) for L = 1..num_lods (the forward of Eq. 4). */
+int ngl_query_sdf_all_lods(const ngl_model* m, const float* x, int64_t P, float* sdf_all, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* 3. Rays: camera, ray-octree intersection (Sec. 3.4, Alg. 1, App. C),  */
+/*    adaptive-stepping sphere tracing (Sec. 3.4, Fig. 3, App. A.4)      */
+/* ------------------------------------------------------------------ */
+
+/* Pinhole primary rays of a width x height image (ray i = row*width+col,
+ * row 0 at the top) through pixel centres, vertical field of view fov_y
+ * (degrees).  Basis f = normalize(target-eye), r = normalize(f x up),
+ * u = r x f; dir = normalize(f + sx*tan(fov/2)*aspect*r + sy*tan(fov/2)*u),
+ * sx = 2(col+0.5)/width - 1, sy = 1 - 2(row+0.5)/height.
+ * eye/target/up: host float[3]; o, d: device float[3][width*height]. */
+int ngl_camera_rays(const float* eye, const float* target, const float* up, float fov_y_deg,
+                    int32_t width, int32_t height, float* o, float* d, void* stream);
+
+/* Bytes of device workspace needed by ngl_trace_octree for R rays and a
+ * capacity of `pair_capacity` ray-voxel pairs per level. */
+int ngl_trace_octree_workspace(int64_t R, int64_t pair_capacity, size_t* bytes);
+
+/* Breadth-first ray-octree intersection (Alg. 1).  Starting from the pairs
+ * (i, root) for every ray, each depth 0..target_depth runs Decide (FP32
+ * slab test of the ray against the voxel's closed box; D = 1 at the target
+ * depth, the number of occupied children otherwise, 0 on a miss),
+ * ExclusiveSum of D, then Subdivide (children written front to back at the
+ * exclusive-sum offset) or, at the target depth, Compactify.  Children are
+ * ordered k = 0..7 as child k XOR oct, oct_a = 1 iff o_a > centre_a of the
+ * parent voxel; this is front-to-back order (App. C).
+ * The slab test per axis: inv = 1/d (correctly rounded); if inv is
+ * infinite the axis passes iff lo <= o <= hi; else t0 = (lo-o)*inv,
+ * t1 = (hi-o)*inv, near/far by compare-and-select; tmin = max near,
+ * tmax = min far; hit iff tmax >= max(tmin, 0).
+ * Inputs (device): o, d [3][R].  Outputs (device, capacity pair_capacity):
+ * pair_ray, pair_vox, t_in = max(tmin, 0), t_out = tmax, ordered by ray
+ * then front to back; ray_off[R+1] (int32): ray i owns [ray_off[i],
+ * ray_off[i+1]).  counts (device int64[2]): counts[0] = final pair count,
+ * counts[1] = the largest pair list needed at any depth.  If counts[1] >
+ * pair_capacity the outputs are incomplete; the call cannot know this
+ * without synchronising, so the caller checks counts after the stream
+ * completes and retries with pair_capacity >= counts[1].  Lists deeper than
+ * the first overflowing depth are built from a truncated list, so after an
+ * overflow counts[1] is a lower bound: repeat until counts[1] fits.  No
+ * buffer is ever written beyond pair_capacity entries.
+ * ws: device workspace of ngl_trace_octree_workspace bytes.  NGL_E_INVALID
+ * if target_depth is outside 0..num_lods+1 or buffers are null. */
+int ngl_trace_octree(const ngl_model* m, const float* o, const float* d, int64_t R,
+                     int32_t target_depth, int64_t pair_capacity, void* ws, size_t ws_bytes,
+                     int32_t* pair_ray, int32_t* pair_vox, float* t_in, float* t_out,
+                     int32_t* ray_off, int64_t* counts, void* stream);
+
+typedef struct {
+  int32_t max_steps;  /* SDF evaluations per ray (App. A.4 uses 200) */
+  float delta;        /* hit threshold: stop when sdf < delta (App. A.4: 3e-4) */
+  float t_far;        /* far-plane clip distance (App. A.4: 5) */
+  int32_t osc_check;  /* 1: stop (STALLED) when |d_k - d_{k-1}| < 6 delta */
+  int32_t analytic;   /* 1: replace the model by the exact SDF of `sphere` */
+  float sphere[4];    /* cx, cy, cz, radius for analytic mode */
+} ngl_trace_params;
+
+/* Adaptive-stepping sphere trace (Sec. 3.4, Fig. 3) over the hit lists of
+ * ngl_trace_octree at depth L'+1 (L' = lod, or lod+1 if alpha > 0).  Per
+ * ray, with cursor p over its pairs and t starting at the first t_in:
+ * skip pairs whose t_out < t (empty space: next voxel; none left: MISS);
+ * if t < t_in[p] advance t to it; t > t_far: FAR; step budget spent:
+ * MAX_STEPS; otherwise evaluate the SDF at o + t d from voxel pair_vox[p]
+ * and its ancestors (local coordinates clamped to the voxel), and stop
+ * with HIT when it is below delta, else t += sdf.  t accumulates in FP32.
+ * Outputs (device, [R]): t_hit (t at termination), status (ngl_ray_status),
+ * steps (SDF evaluations), hit_vox (pair voxel at HIT, else -1). */
+int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t R, int32_t lod,
+                     float alpha, const int32_t* pair_vox, const float* t_in, const float* t_out,
+                     const int32_t* ray_off, const ngl_trace_params* params, float* t_hit,
+                     uint8_t* status, int32_t* steps, int32_t* hit_vox, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* 4. Training (Sec. 3.3, Eq. 4)                                        */
+/* ------------------------------------------------------------------ */
+
+/* Bytes of device workspace for the backward / training step on P points. */
+int ngl_train_workspace(const ngl_model* m, int64_t P, size_t* bytes);
+
+/* Gradient of sum_{L,p} grad_sdf[L-1][p] * sdf_all[L-1][p] with respect to
+ * every parameter, given the upstream gradient grad_sdf (device [L][P]).
+ * Feature gradients are accumulated without atomics (points are sorted by
+ * voxel, then each corner gathers its contributions in a fixed order), so
+ * results are bitwise reproducible.  Outputs (device, float32, overwritten):
+ * dfeat[l] [ncorner][m], dW1[l] [h][din], db1[l] [h], dw2[l] [h], db2 [L].
+ * Requires feat_dtype == F32 and w_dtype == F32. */
+int ngl_backward_all_lods(const ngl_model* m, const float* x, int64_t P, const float* grad_sdf,
+                          float* const* dfeat, float* const* dW1, float* const* db1,
+                          float* const* dw2, float* db2, void* ws, size_t ws_bytes, void* stream);
+
+/* One training forward+backward of Eq. 4: loss = (1/P) sum_p sum_L
+ * (sdf_L(x_p) - target_p)^2 written to loss (device float[1]), sdf_all
+ * (device [L][P], nullable) and gradients as in ngl_backward_all_lods. */
+int ngl_train_fwd_bwd(const ngl_model* m, const float* x, const float* target, int64_t P,
+                      float* loss, float* sdf_all, float* const* dfeat, float* const* dW1,
+                      float* const* db1, float* const* dw2, float* db2, void* ws,
+                      size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NGL_H */

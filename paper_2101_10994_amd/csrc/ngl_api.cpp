@@ -1,0 +1,69 @@
+// Status strings, thread-local error text and model validation for the C ABI.
+#include "ngl_common.h"
+
+namespace ngl {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+}
+
+int check_model(const ngl_model* m, bool need_features) {
+  NGL_REQUIRE(m != nullptr, "model is null");
+  NGL_REQUIRE(m->num_lods >= 1 && m->num_lods <= NGL_MAX_LODS, "num_lods %d outside 1..%d", m->num_lods,
+              NGL_MAX_LODS);
+  const int D = m->num_lods + 1;
+  for (int d = 0; d <= D; ++d) {
+    NGL_REQUIRE(m->nvox[d] >= 0 && m->nvox[d] < (int64_t(1) << 31), "nvox[%d] out of range", d);
+    if (m->nvox[d] > 0) {
+      NGL_REQUIRE(m->cell[d] != nullptr, "cell[%d] is null", d);
+      if (d < D) NGL_REQUIRE(m->child_mask[d] && m->first_child[d], "child arrays of depth %d are null", d);
+      if (d > 0) NGL_REQUIRE(m->parent[d] != nullptr, "parent[%d] is null", d);
+    }
+  }
+  if (!need_features) return NGL_OK;
+  NGL_REQUIRE(m->feat_dim >= 8 && m->feat_dim <= NGL_MAX_FEAT_DIM && m->feat_dim % 8 == 0,
+              "feat_dim %d must be a multiple of 8 in 8..%d", m->feat_dim, NGL_MAX_FEAT_DIM);
+  NGL_REQUIRE(m->hidden >= 16 && m->hidden <= NGL_MAX_HIDDEN && m->hidden % 16 == 0,
+              "hidden %d must be a multiple of 16 in 16..%d", m->hidden, NGL_MAX_HIDDEN);
+  NGL_REQUIRE(m->feat_dtype == NGL_F32 || m->feat_dtype == NGL_F16 || m->feat_dtype == NGL_BF16,
+              "unknown feat_dtype %d", m->feat_dtype);
+  NGL_REQUIRE(m->w_dtype == NGL_F32 || m->w_dtype == NGL_BF16, "w_dtype %d must be F32 or BF16", m->w_dtype);
+  NGL_REQUIRE(m->with_xyz == 0 || m->with_xyz == 1, "with_xyz must be 0 or 1");
+  NGL_REQUIRE(m->b2 != nullptr, "b2 is null");
+  for (int l = 1; l <= m->num_lods; ++l) {
+    NGL_REQUIRE(m->ncorner[l - 1] >= 0 && m->ncorner[l - 1] < (int64_t(1) << 31), "ncorner[%d] out of range",
+                l - 1);
+    if (m->nvox[l + 1] > 0)
+      NGL_REQUIRE(m->corners[l - 1] && m->feat[l - 1], "corner table or features of level %d are null", l);
+    NGL_REQUIRE(m->W1[l - 1] && m->b1[l - 1] && m->w2[l - 1], "decoder %d is null", l);
+  }
+  return NGL_OK;
+}
+
+}  // namespace ngl
+
+extern "C" {
+
+const char* ngl_status_str(int s) {
+  switch (s) {
+    case NGL_OK: return "ok";
+    case NGL_E_INVALID: return "invalid argument";
+    case NGL_E_CAPACITY: return "capacity exceeded";
+    case NGL_E_HIP: return "HIP runtime error";
+    case NGL_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* ngl_last_error(void) { return ngl::g_last_error.c_str(); }
+
+int ngl_version(void) { return 1; }
+
+}  // extern "C"

@@ -1,0 +1,237 @@
+// Device helpers shared by the gfx950 kernels: exact point location, octree
+// descent, the FP32 slab predicate, corner-feature rows and the FP32
+// decoder.  Everything here is __device__ inline; each .hip file is a
+// self-contained code object.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "ngl.h"
+
+namespace ngl {
+
+constexpr int kBlock = 256;
+
+// Pointers read through the scalar cache: the decoder weights are uniform
+// across a wavefront, so loads from this address space become s_load.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+
+template <typename T>
+__device__ inline cptr<T> as_const(const void* p) {
+  return (cptr<T>)(p);
+}
+
+// ---------------------------------------------------------------------------
+// Feature rows (16-byte vector loads; FP32, FP16 or BF16 storage)
+// ---------------------------------------------------------------------------
+struct F32 {};
+struct F16 {};
+struct BF16 {};
+
+__device__ inline float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+__device__ inline float f16_to_f32(uint32_t bits16) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
+}
+
+// acc[k] += w * row[k] for row `c` of a [n][M] feature table.
+template <int M, typename FT>
+__device__ inline void axpy_row(const void* base, int c, float w, float* acc) {
+  if constexpr (std::is_same<FT, F32>::value) {
+    const float4* r = reinterpret_cast<const float4*>(static_cast<const float*>(base) + size_t(c) * M);
+#pragma unroll
+    for (int q = 0; q < M / 4; ++q) {
+      const float4 v = r[q];
+      acc[4 * q + 0] = fmaf(w, v.x, acc[4 * q + 0]);
+      acc[4 * q + 1] = fmaf(w, v.y, acc[4 * q + 1]);
+      acc[4 * q + 2] = fmaf(w, v.z, acc[4 * q + 2]);
+      acc[4 * q + 3] = fmaf(w, v.w, acc[4 * q + 3]);
+    }
+  } else {
+    const uint4* r = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(base) + size_t(c) * M);
+#pragma unroll
+    for (int q = 0; q < M / 8; ++q) {
+      uint4 v = r[q];
+      uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        float lo, hi;
+        if constexpr (std::is_same<FT, BF16>::value) {
+          lo = bf16_to_f32(wv[h] & 0xffffu);
+          hi = bf16_to_f32(wv[h] >> 16);
+        } else {
+          lo = f16_to_f32(wv[h] & 0xffffu);
+          hi = f16_to_f32(wv[h] >> 16);
+        }
+        acc[8 * q + 2 * h] = fmaf(w, lo, acc[8 * q + 2 * h]);
+        acc[8 * q + 2 * h + 1] = fmaf(w, hi, acc[8 * q + 2 * h + 1]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Exact point location
+// ---------------------------------------------------------------------------
+// Half-open cell [lo, hi) of resolution r (power of two, <= 1024) containing
+// x in [-1, 1]; x = +1 lies in the last cell.  The FP32 estimate is within
+// one cell of the answer; one comparison against the exact dyadic bounds
+// corrects it.
+__device__ inline int cell_of(float x, int r) {
+  const float step = 2.0f / float(r);  // exact: r is a power of two
+  int i = int(floorf((x + 1.0f) * (0.5f * float(r))));
+  i = min(max(i, 0), r - 1);
+  if (x < -1.0f + float(i) * step) {
+    i = max(i - 1, 0);
+  } else if (i < r - 1 && x >= -1.0f + float(i + 1) * step) {
+    i = i + 1;
+  }
+  return i;
+}
+
+// a[i] for a runtime i without dynamic register indexing.
+template <int N>
+__device__ inline int pick(const int* a, int i) {
+  int r = a[0];
+#pragma unroll
+  for (int k = 1; k < N; ++k) r = (k == i) ? a[k] : r;
+  return r;
+}
+
+__device__ inline bool in_box(float x, float y, float z) {
+  return x >= -1.0f && x <= 1.0f && y >= -1.0f && y <= 1.0f && z >= -1.0f && z <= 1.0f;
+}
+
+__device__ inline uint32_t pack_cell(int x, int y, int z) { return uint32_t(x) | uint32_t(y) << 10 | uint32_t(z) << 20; }
+__device__ inline int cell_x(uint32_t c) { return int(c & 1023u); }
+__device__ inline int cell_y(uint32_t c) { return int(c >> 10 & 1023u); }
+__device__ inline int cell_z(uint32_t c) { return int(c >> 20 & 1023u); }
+
+// Descend from the root to depth `depth` along the cell (cx,cy,cz) given at
+// that depth; vox[l-1] receives the voxel of feature level l (depth l+1)
+// for l = 1..depth-1, or -1 once a voxel is absent.
+template <int MAXL>
+__device__ inline void descend(const ngl_model& md, int cx, int cy, int cz, int depth, int* vox) {
+  int v = 0;
+  bool alive = md.nvox[0] > 0;
+#pragma unroll
+  for (int d = 0; d < MAXL + 1; ++d) {
+    if (d < depth) {
+      if (alive) {
+        const int s = depth - 1 - d;
+        const int c = ((cx >> s) & 1) | ((cy >> s) & 1) << 1 | ((cz >> s) & 1) << 2;
+        const uint32_t mask = md.child_mask[d][v];
+        if (mask >> c & 1u) {
+          v = md.first_child[d][v] + __popc(mask & ((1u << c) - 1u));
+        } else {
+          alive = false;
+        }
+      }
+      if (d >= 1) vox[d - 1] = alive ? v : -1;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 slab predicate (closed box, t >= 0).  Evaluated operation by
+// operation exactly as stated in the library header so that hit lists are
+// reproducible bit for bit.
+// ---------------------------------------------------------------------------
+__device__ inline bool slab_f32(const float o[3], const float inv[3], const float lo[3], const float hi[3],
+                                float& t_in, float& t_out) {
+#pragma clang fp contract(off)
+  float tmin = -__builtin_inff(), tmax = __builtin_inff();
+  bool ok = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (__builtin_isinf(inv[a])) {
+      ok = ok && (lo[a] <= o[a] && o[a] <= hi[a]);
+    } else {
+      const float d0 = lo[a] - o[a];
+      const float d1 = hi[a] - o[a];
+      const float t0 = d0 * inv[a];
+      const float t1 = d1 * inv[a];
+      const float nr = t0 < t1 ? t0 : t1;
+      const float fr = t0 < t1 ? t1 : t0;
+      tmin = nr > tmin ? nr : tmin;
+      tmax = fr < tmax ? fr : tmax;
+    }
+  }
+  const float t0c = tmin > 0.0f ? tmin : 0.0f;
+  t_in = t0c;
+  t_out = tmax;
+  return ok && (tmax >= t0c);
+}
+
+// Box of cell `c` (packed) at `depth`; exact dyadic bounds.
+__device__ inline void box_of(uint32_t c, int depth, float lo[3], float hi[3]) {
+  const float step = 2.0f / float(1 << depth);
+  const int ijk[3] = {cell_x(c), cell_y(c), cell_z(c)};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = -1.0f + float(ijk[a]) * step;
+    hi[a] = -1.0f + float(ijk[a] + 1) * step;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Trilinear interpolation of one level's corner features (Sec. 3.2)
+// ---------------------------------------------------------------------------
+// acc[k] += sum_j w_j(u) Z[corner(v, j)][k], u = local position of x in
+// the cell (clamped to [0,1]).
+template <int M, typename FT>
+__device__ inline void interp_level(const ngl_model& md, int lvl, int v, int cx, int cy, int cz, const float x[3],
+                                    float* acc) {
+  const int r = 4 << (lvl - 1);
+  const float step = 2.0f / float(r);
+  const float half_r = 0.5f * float(r);
+  float u[3];
+  const int ci[3] = {cx, cy, cz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float lo = -1.0f + float(ci[a]) * step;
+    u[a] = fminf(fmaxf((x[a] - lo) * half_r, 0.0f), 1.0f);
+  }
+  const int4* cp = reinterpret_cast<const int4*>(md.corners[lvl - 1] + size_t(v) * 8);
+  const int4 c0 = cp[0], c1 = cp[1];
+  const int cs[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float w = ((j & 1) ? u[0] : 1.0f - u[0]) * ((j & 2) ? u[1] : 1.0f - u[1]) * ((j & 4) ? u[2] : 1.0f - u[2]);
+    axpy_row<M, FT>(md.feat[lvl - 1], cs[j], w, acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 decoder f_theta_L([x, z]) = b2 + w2 . ReLU(W1 [x; z] + b1)  (Eq. 2)
+// ---------------------------------------------------------------------------
+template <int M, bool XYZ>
+__device__ inline float decode_f32(const ngl_model& md, int L, const float x[3], const float* z) {
+  constexpr int DIN = M + (XYZ ? 3 : 0);
+  constexpr int OFF = XYZ ? 3 : 0;
+  cptr<float> W1 = as_const<float>(md.W1[L - 1]);
+  cptr<float> b1 = as_const<float>(md.b1[L - 1]);
+  cptr<float> w2 = as_const<float>(md.w2[L - 1]);
+  cptr<float> b2 = as_const<float>(md.b2);
+  float out = b2[L - 1];
+  const int H = md.hidden;
+#pragma unroll 2
+  for (int k = 0; k < H; ++k) {
+    cptr<float> row = W1 + k * DIN;
+    float a = b1[k];
+    if constexpr (XYZ) {
+      a = fmaf(row[0], x[0], a);
+      a = fmaf(row[1], x[1], a);
+      a = fmaf(row[2], x[2], a);
+    }
+#pragma unroll
+    for (int i = 0; i < M; ++i) a = fmaf(row[OFF + i], z[i], a);
+    out = fmaf(w2[k], fmaxf(a, 0.0f), out);
+  }
+  return out;
+}
+
+}  // namespace ngl

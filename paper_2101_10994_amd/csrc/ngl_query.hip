@@ -1,0 +1,173 @@
+// SDF queries (Sec. 3.2, Eq. 2; continuous LOD, Eq. 3) on gfx950.
+//
+// One lane per point: exact location of the finest needed cell, one descent
+// of the octree that yields the voxel of every level, the trilinear corner
+// gather summed across levels in registers, then the per-LOD decoder.
+#include "ngl_common.h"
+#include "ngl_device.h"
+
+namespace ngl {
+
+// Locate x at feature levels 1..Lp: vox[l-1] (or -1) and the level's cell.
+template <int MAXL>
+__device__ inline void locate(const ngl_model& md, const float x[3], int Lp, int* vox, int* cx, int* cy, int* cz) {
+  const int Dp = Lp + 1;
+  if (!in_box(x[0], x[1], x[2])) {
+#pragma unroll
+    for (int l = 0; l < MAXL; ++l) vox[l] = -1;
+    *cx = *cy = *cz = 0;
+    return;
+  }
+  const int r = 1 << Dp;
+  *cx = cell_of(x[0], r);
+  *cy = cell_of(x[1], r);
+  *cz = cell_of(x[2], r);
+  descend<MAXL>(md, *cx, *cy, *cz, Dp, vox);
+}
+
+template <int M, typename FT, bool XYZ>
+__global__ __launch_bounds__(kBlock) void k_query(ngl_model md, const float* __restrict__ xs, int64_t P, int lod,
+                                                  float alpha, const float* __restrict__ alpha_pp,
+                                                  float* __restrict__ sdf, uint8_t* __restrict__ valid,
+                                                  int32_t* __restrict__ vox_out) {
+  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (p >= P) return;
+  const float x[3] = {xs[p], xs[P + p], xs[2 * P + p]};
+  const bool blend = alpha_pp != nullptr || alpha > 0.0f;
+  const int Lp = blend ? lod + 1 : lod;
+  const float a = alpha_pp ? alpha_pp[p] : alpha;
+  int vox[NGL_MAX_LODS];
+  int cx, cy, cz;
+  locate<NGL_MAX_LODS>(md, x, Lp, vox, &cx, &cy, &cz);
+  float z[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) z[k] = 0.0f;
+  // Level loops are unrolled over the compile-time maximum so that the
+  // per-level arrays stay in registers.
+#pragma unroll
+  for (int l = 1; l <= NGL_MAX_LODS; ++l)
+    if (l <= lod && vox[l - 1] >= 0) interp_level<M, FT>(md, l, vox[l - 1], cx >> (Lp - l), cy >> (Lp - l), cz >> (Lp - l), x, z);
+  float out = decode_f32<M, XYZ>(md, lod, x, z);
+  if (blend) {
+    // z_{L+1} = z_L + psi_{L+1}
+    const int vn = pick<NGL_MAX_LODS>(vox, lod);
+    if (vn >= 0) interp_level<M, FT>(md, lod + 1, vn, cx, cy, cz, x, z);
+    out = (1.0f - a) * out + a * decode_f32<M, XYZ>(md, lod + 1, x, z);
+  }
+  sdf[p] = out;
+  if (valid) valid[p] = pick<NGL_MAX_LODS>(vox, Lp - 1) >= 0 ? 1 : 0;
+  if (vox_out) {
+#pragma unroll
+    for (int l = 1; l <= NGL_MAX_LODS; ++l)
+      if (l <= Lp) vox_out[int64_t(l - 1) * P + p] = vox[l - 1];
+  }
+}
+
+// All discrete LODs: the level sum is shared, one decoder per LOD.
+template <int M, typename FT, bool XYZ>
+__global__ __launch_bounds__(kBlock) void k_query_all(ngl_model md, const float* __restrict__ xs, int64_t P,
+                                                      float* __restrict__ sdf_all) {
+  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (p >= P) return;
+  const float x[3] = {xs[p], xs[P + p], xs[2 * P + p]};
+  const int Lm = md.num_lods;
+  int vox[NGL_MAX_LODS];
+  int cx, cy, cz;
+  locate<NGL_MAX_LODS>(md, x, Lm, vox, &cx, &cy, &cz);
+  float z[M];
+#pragma unroll
+  for (int k = 0; k < M; ++k) z[k] = 0.0f;
+#pragma unroll
+  for (int l = 1; l <= NGL_MAX_LODS; ++l) {
+    if (l <= Lm) {
+      const int s = Lm - l;
+      if (vox[l - 1] >= 0) interp_level<M, FT>(md, l, vox[l - 1], cx >> s, cy >> s, cz >> s, x, z);
+      sdf_all[int64_t(l - 1) * P + p] = decode_f32<M, XYZ>(md, l, x, z);
+    }
+  }
+}
+
+template <int M, typename FT, bool XYZ>
+static int launch_query(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app,
+                        float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s) {
+  const unsigned grid = unsigned((P + kBlock - 1) / kBlock);
+  k_query<M, FT, XYZ><<<grid, kBlock, 0, s>>>(md, x, P, lod, alpha, app, sdf, valid, vox);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+template <int M, typename FT, bool XYZ>
+static int launch_query_all(const ngl_model& md, const float* x, int64_t P, float* out, hipStream_t s) {
+  const unsigned grid = unsigned((P + kBlock - 1) / kBlock);
+  k_query_all<M, FT, XYZ><<<grid, kBlock, 0, s>>>(md, x, P, out);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+// Dispatch over feature width, feature dtype and decoder input layout.
+template <template <int, typename, bool> class F, typename... Args>
+static int dispatch(const ngl_model& md, Args... args) {
+#define NGL_CASE_XYZ(M_, FT_)                                          \
+  return md.with_xyz ? F<M_, FT_, true>::run(md, args...) : F<M_, FT_, false>::run(md, args...)
+#define NGL_CASE_FT(M_)                                                \
+  switch (md.feat_dtype) {                                             \
+    case NGL_F32: NGL_CASE_XYZ(M_, F32);                               \
+    case NGL_F16: NGL_CASE_XYZ(M_, F16);                               \
+    default: NGL_CASE_XYZ(M_, BF16);                                   \
+  }
+  switch (md.feat_dim) {
+    case 8: NGL_CASE_FT(8);
+    case 16: NGL_CASE_FT(16);
+    case 32: NGL_CASE_FT(32);
+    case 64: NGL_CASE_FT(64);
+    default: NGL_FAIL(NGL_E_UNSUPPORTED, "feat_dim %d not compiled (8, 16, 32, 64)", md.feat_dim);
+  }
+#undef NGL_CASE_FT
+#undef NGL_CASE_XYZ
+}
+
+template <int M, typename FT, bool XYZ>
+struct QueryOp {
+  static int run(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app, float* sdf,
+                 uint8_t* valid, int32_t* vox, hipStream_t s) {
+    return launch_query<M, FT, XYZ>(md, x, P, lod, alpha, app, sdf, valid, vox, s);
+  }
+};
+
+template <int M, typename FT, bool XYZ>
+struct QueryAllOp {
+  static int run(const ngl_model& md, const float* x, int64_t P, float* out, hipStream_t s) {
+    return launch_query_all<M, FT, XYZ>(md, x, P, out, s);
+  }
+};
+
+}  // namespace ngl
+
+extern "C" {
+
+int ngl_query_sdf(const ngl_model* m, const float* x, int64_t P, int32_t lod, float alpha, const float* alpha_pp,
+                  float* sdf, uint8_t* valid, int32_t* vox_out, void* stream) {
+  int rc = ngl::check_model(m, true);
+  if (rc) return rc;
+  NGL_REQUIRE(P >= 0, "negative point count");
+  NGL_REQUIRE(lod >= 1 && lod <= m->num_lods, "lod %d outside 1..%d", lod, m->num_lods);
+  NGL_REQUIRE(alpha >= 0.0f && alpha < 1.0f, "alpha must be in [0,1)");
+  NGL_REQUIRE(!(alpha > 0.0f || alpha_pp) || lod < m->num_lods, "blending needs lod < num_lods");
+  if (P == 0) return NGL_OK;
+  NGL_REQUIRE(x && sdf, "x or sdf is null");
+  if (m->w_dtype != NGL_F32) NGL_FAIL(NGL_E_UNSUPPORTED, "BF16 decoder weights are not supported by this call yet");
+  return ngl::dispatch<ngl::QueryOp>(*m, x, P, int(lod), alpha, alpha_pp, sdf, valid, vox_out,
+                                     (hipStream_t)stream);
+}
+
+int ngl_query_sdf_all_lods(const ngl_model* m, const float* x, int64_t P, float* sdf_all, void* stream) {
+  int rc = ngl::check_model(m, true);
+  if (rc) return rc;
+  NGL_REQUIRE(P >= 0, "negative point count");
+  if (P == 0) return NGL_OK;
+  NGL_REQUIRE(x && sdf_all, "x or sdf_all is null");
+  if (m->w_dtype != NGL_F32) NGL_FAIL(NGL_E_UNSUPPORTED, "BF16 decoder weights are not supported by this call yet");
+  return ngl::dispatch<ngl::QueryAllOp>(*m, x, P, sdf_all, (hipStream_t)stream);
+}
+
+}  // extern "C"

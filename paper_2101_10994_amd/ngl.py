@@ -1,0 +1,426 @@
+"""Python binding of libngl.so (the gfx950 neural geometric LOD library).
+
+Argument marshalling only: every step of the path runs in the library's
+HIP kernels; PyTorch provides device memory and the current stream.  The
+names mirror the C ABI in include/ngl.h.  There is no fallback: if the
+library is not built, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libngl.so")
+
+MAX_LODS = 8
+MAX_DEPTH = MAX_LODS + 2
+F32, F16, BF16 = 0, 1, 2
+MISS, HIT, MAX_STEPS, FAR, STALLED, INVALID = range(6)
+
+_TORCH_DTYPE = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16}
+_DTYPE_CODE = {torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+
+_lock = threading.Lock()
+_lib = None
+
+P = C.c_void_p
+i32 = C.c_int32
+i64 = C.c_int64
+
+
+class NGLError(RuntimeError):
+    pass
+
+
+class ngl_model(C.Structure):
+    _fields_ = [("num_lods", i32), ("feat_dim", i32), ("hidden", i32), ("with_xyz", i32),
+                ("feat_dtype", i32), ("w_dtype", i32),
+                ("nvox", i64 * MAX_DEPTH), ("ncorner", i64 * MAX_LODS),
+                ("cell", P * MAX_DEPTH), ("child_mask", P * MAX_DEPTH), ("first_child", P * MAX_DEPTH),
+                ("parent", P * MAX_DEPTH), ("corners", P * MAX_LODS), ("feat", P * MAX_LODS),
+                ("W1", P * MAX_LODS), ("b1", P * MAX_LODS), ("w2", P * MAX_LODS), ("b2", P)]
+
+
+class ngl_octree_host(C.Structure):
+    _fields_ = [("cell", P * MAX_DEPTH), ("child_mask", P * MAX_DEPTH), ("first_child", P * MAX_DEPTH),
+                ("parent", P * MAX_DEPTH), ("corners", P * MAX_LODS), ("corner_cell", P * MAX_LODS)]
+
+
+class ngl_trace_params(C.Structure):
+    _fields_ = [("max_steps", i32), ("delta", C.c_float), ("t_far", C.c_float), ("osc_check", i32),
+                ("analytic", i32), ("sphere", C.c_float * 4)]
+
+
+EXPORTS = {
+    "ngl_status_str": (C.c_char_p, [C.c_int]),
+    "ngl_last_error": (C.c_char_p, []),
+    "ngl_version": (C.c_int, []),
+    "ngl_octree_plan": (C.c_int, [P, i64, i32, P, P]),
+    "ngl_octree_fill": (C.c_int, [P, i64, i32, P]),
+    "ngl_query_sdf": (C.c_int, [P, P, i64, i32, C.c_float, P, P, P, P, P]),
+    "ngl_query_sdf_all_lods": (C.c_int, [P, P, i64, P, P]),
+    "ngl_camera_rays": (C.c_int, [P, P, P, C.c_float, i32, i32, P, P, P]),
+    "ngl_trace_octree_workspace": (C.c_int, [i64, i64, P]),
+    "ngl_trace_octree": (C.c_int, [P, P, P, i64, i32, i64, P, C.c_size_t, P, P, P, P, P, P, P]),
+    "ngl_sphere_trace": (C.c_int, [P, P, P, i64, i32, C.c_float, P, P, P, P, P, P, P, P, P, P]),
+    "ngl_train_workspace": (C.c_int, [P, i64, P]),
+    "ngl_backward_all_lods": (C.c_int, [P, P, i64, P, P, P, P, P, P, P, C.c_size_t, P]),
+    "ngl_train_fwd_bwd": (C.c_int, [P, P, P, i64, P, P, P, P, P, P, P, P, C.c_size_t, P]),
+}
+
+
+def lib():
+    """Load libngl.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise NGLError("libngl.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_2101_10994_amd.build)")
+            h = C.CDLL(LIB_PATH)
+            for name, (res, args) in EXPORTS.items():
+                f = getattr(h, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = h
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        L = lib()
+        raise NGLError("%s: %s" % (L.ngl_status_str(rc).decode(), L.ngl_last_error().decode()))
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype=None):
+    if not t.is_cuda:
+        raise NGLError("expected a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise NGLError("expected %s, got %s" % (dtype, t.dtype))
+    if not t.is_contiguous():
+        raise NGLError("expected a contiguous tensor")
+    return t
+
+
+# ---------------------------------------------------------------------------
+# 1. Octree
+# ---------------------------------------------------------------------------
+class Octree:
+    """Canonical sparse voxel octree: host arrays from ngl_octree_fill and
+    their device copies."""
+
+    def __init__(self, ijk: np.ndarray, num_lods: int, device="cuda"):
+        L = lib()
+        ijk = np.ascontiguousarray(np.asarray(ijk, dtype=np.int32).reshape(-1, 3))
+        self.num_lods = int(num_lods)
+        self.depth = self.num_lods + 1
+        nv = np.zeros(MAX_DEPTH, np.int64)
+        nc = np.zeros(MAX_LODS, np.int64)
+        _check(L.ngl_octree_plan(_ptr(ijk), ijk.shape[0], self.num_lods, _ptr(nv), _ptr(nc)))
+        self.nvox = nv[: self.depth + 1].copy()
+        self.ncorner = nc[: self.num_lods].copy()
+        D = self.depth
+        self.cell = [np.zeros(int(self.nvox[d]), np.uint32) for d in range(D + 1)]
+        self.child_mask = [np.zeros(int(self.nvox[d]), np.uint8) for d in range(D + 1)]
+        self.first_child = [np.zeros(int(self.nvox[d]), np.int32) for d in range(D + 1)]
+        self.parent = [np.zeros(int(self.nvox[d]), np.int32) for d in range(D + 1)]
+        self.corners = [np.zeros((int(self.nvox[lv + 1]), 8), np.int32) for lv in range(1, D)]
+        self.corner_cell = [np.zeros((int(self.ncorner[lv - 1]), 3), np.int32) for lv in range(1, D)]
+        h = ngl_octree_host()
+        for d in range(D + 1):
+            h.cell[d] = _ptr(self.cell[d])
+            h.child_mask[d] = _ptr(self.child_mask[d])
+            h.first_child[d] = _ptr(self.first_child[d])
+            h.parent[d] = _ptr(self.parent[d])
+        for lv in range(self.num_lods):
+            h.corners[lv] = _ptr(self.corners[lv])
+            h.corner_cell[lv] = _ptr(self.corner_cell[lv])
+        _check(L.ngl_octree_fill(_ptr(ijk), ijk.shape[0], self.num_lods, C.addressof(h)))
+        self.device = device
+        self.d_cell = self.d_child_mask = self.d_first_child = self.d_parent = self.d_corners = None
+        if device is not None:
+            self.to(device)
+
+    def to(self, device):
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        self.d_cell = [t(a.view(np.int32)) for a in self.cell]
+        self.d_child_mask = [t(a) for a in self.child_mask]
+        self.d_first_child = [t(a) for a in self.first_child]
+        self.d_parent = [t(a) for a in self.parent]
+        self.d_corners = [t(a) for a in self.corners]
+        self.device = device
+        return self
+
+    def cell_ijk(self, d: int) -> np.ndarray:
+        c = self.cell[d].astype(np.int64)
+        return np.stack([c & 1023, (c >> 10) & 1023, (c >> 20) & 1023], 1).astype(np.int32)
+
+    def corner_positions(self) -> List[np.ndarray]:
+        return [-1.0 + self.corner_cell[lv].astype(np.float64) * (2.0 / 2 ** (lv + 2))
+                for lv in range(self.num_lods)]
+
+
+# ---------------------------------------------------------------------------
+# Model
+# ---------------------------------------------------------------------------
+class Model:
+    """Octree + corner features + per-LOD decoders as device tensors.
+
+    feats[l]: [ncorner_l][m] (float32/float16/bfloat16); W1[l]: [h][din]
+    (float32 or bfloat16); b1[l], w2[l]: [h] float32; b2: [L] float32."""
+
+    def __init__(self, tree: Octree, feats: Sequence[torch.Tensor], W1: Sequence[torch.Tensor],
+                 b1: Sequence[torch.Tensor], w2: Sequence[torch.Tensor], b2: torch.Tensor, with_xyz: bool = True):
+        self.tree = tree
+        self.num_lods = tree.num_lods
+        assert len(feats) == self.num_lods and len(W1) == self.num_lods
+        self.feats = [_dev(f) for f in feats]
+        self.W1 = [_dev(w) for w in W1]
+        self.b1 = [_dev(b, torch.float32) for b in b1]
+        self.w2 = [_dev(w, torch.float32) for w in w2]
+        self.b2 = _dev(b2, torch.float32)
+        self.m = int(self.feats[0].shape[1])
+        self.hidden = int(self.W1[0].shape[0])
+        self.with_xyz = bool(with_xyz)
+        self.feat_dtype = _DTYPE_CODE[self.feats[0].dtype]
+        self.w_dtype = _DTYPE_CODE[self.W1[0].dtype]
+        din = self.m + (3 if self.with_xyz else 0)
+        for lv in range(self.num_lods):
+            nc = int(tree.ncorner[lv])
+            f = self.feats[lv]
+            if tuple(f.shape) != (nc, self.m) and not (nc == 0 and f.shape[1] == self.m):
+                raise NGLError("feats[%d] has shape %s, expected (%d, %d)" % (lv, tuple(f.shape), nc, self.m))
+            if _DTYPE_CODE[f.dtype] != self.feat_dtype:
+                raise NGLError("all feature levels must share one dtype")
+            if tuple(self.W1[lv].shape) != (self.hidden, din) or _DTYPE_CODE[self.W1[lv].dtype] != self.w_dtype:
+                raise NGLError("W1[%d] must be [%d][%d] of one dtype" % (lv, self.hidden, din))
+            if tuple(self.b1[lv].shape) != (self.hidden,) or tuple(self.w2[lv].shape) != (self.hidden,):
+                raise NGLError("b1[%d]/w2[%d] must have %d entries" % (lv, lv, self.hidden))
+        if tuple(self.b2.shape) != (self.num_lods,):
+            raise NGLError("b2 must have num_lods entries")
+        self._struct = self._make_struct()
+
+    def _make_struct(self):
+        s = ngl_model()
+        t = self.tree
+        s.num_lods, s.feat_dim, s.hidden, s.with_xyz = self.num_lods, self.m, self.hidden, int(self.with_xyz)
+        s.feat_dtype, s.w_dtype = self.feat_dtype, self.w_dtype
+        for d in range(t.depth + 1):
+            s.nvox[d] = int(t.nvox[d])
+            s.cell[d] = _ptr(t.d_cell[d]) if t.nvox[d] else None
+            s.child_mask[d] = _ptr(t.d_child_mask[d]) if t.nvox[d] else None
+            s.first_child[d] = _ptr(t.d_first_child[d]) if t.nvox[d] else None
+            s.parent[d] = _ptr(t.d_parent[d]) if t.nvox[d] else None
+        for lv in range(self.num_lods):
+            s.ncorner[lv] = int(t.ncorner[lv])
+            s.corners[lv] = _ptr(t.d_corners[lv]) if t.nvox[lv + 2] else None
+            s.feat[lv] = _ptr(self.feats[lv]) if self.feats[lv].numel() else None
+            s.W1[lv] = _ptr(self.W1[lv])
+            s.b1[lv] = _ptr(self.b1[lv])
+            s.w2[lv] = _ptr(self.w2[lv])
+        s.b2 = _ptr(self.b2)
+        return s
+
+    @property
+    def ref(self):
+        return C.addressof(self._struct)
+
+    def refresh(self):
+        """Rebuild the C view after parameters were reassigned."""
+        self._struct = self._make_struct()
+
+
+# ---------------------------------------------------------------------------
+# 2. Queries
+# ---------------------------------------------------------------------------
+def query_sdf(model: Model, x: torch.Tensor, lod: int, alpha: float = 0.0, alpha_pp: torch.Tensor = None,
+              want_valid: bool = False, want_vox: bool = False, out: torch.Tensor = None):
+    """SDF at LOD `lod` (+alpha) for points x [3][P] (float32, device)."""
+    _dev(x, torch.float32)
+    Pn = x.shape[1]
+    dev = x.device
+    sdf = out if out is not None else torch.empty(Pn, dtype=torch.float32, device=dev)
+    blend = alpha_pp is not None or alpha > 0.0
+    Lp = lod + 1 if blend else lod
+    valid = torch.empty(Pn, dtype=torch.uint8, device=dev) if want_valid else None
+    vox = torch.empty((Lp, Pn), dtype=torch.int32, device=dev) if want_vox else None
+    if alpha_pp is not None:
+        _dev(alpha_pp, torch.float32)
+    _check(lib().ngl_query_sdf(model.ref, _ptr(x), Pn, int(lod), float(alpha), _ptr(alpha_pp), _ptr(sdf),
+                               _ptr(valid), _ptr(vox), _stream()))
+    res = {"sdf": sdf}
+    if want_valid:
+        res["valid"] = valid
+    if want_vox:
+        res["vox"] = vox
+    return res
+
+
+def query_sdf_all_lods(model: Model, x: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
+    _dev(x, torch.float32)
+    Pn = x.shape[1]
+    o = out if out is not None else torch.empty((model.num_lods, Pn), dtype=torch.float32, device=x.device)
+    _check(lib().ngl_query_sdf_all_lods(model.ref, _ptr(x), Pn, _ptr(o), _stream()))
+    return o
+
+
+# ---------------------------------------------------------------------------
+# 3. Rays
+# ---------------------------------------------------------------------------
+def camera_rays(eye, target, up, fov_y_deg: float, width: int, height: int, device="cuda", out=None):
+    R = width * height
+    if out is None:
+        o = torch.empty((3, R), dtype=torch.float32, device=device)
+        d = torch.empty((3, R), dtype=torch.float32, device=device)
+    else:
+        o, d = out
+    e = np.asarray(eye, np.float32)
+    t = np.asarray(target, np.float32)
+    u = np.asarray(up, np.float32)
+    _check(lib().ngl_camera_rays(_ptr(e), _ptr(t), _ptr(u), float(fov_y_deg), int(width), int(height), _ptr(o),
+                                 _ptr(d), _stream()))
+    return o, d
+
+
+class TraceBuffers:
+    """Workspace and outputs of ngl_trace_octree for R rays at a capacity."""
+
+    def __init__(self, R: int, capacity: int, device="cuda"):
+        nb = C.c_size_t()
+        _check(lib().ngl_trace_octree_workspace(R, capacity, C.addressof(nb)))
+        self.R, self.capacity = R, capacity
+        self.ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=device)
+        self.ray = torch.empty(max(capacity, 1), dtype=torch.int32, device=device)
+        self.vox = torch.empty(max(capacity, 1), dtype=torch.int32, device=device)
+        self.t_in = torch.empty(max(capacity, 1), dtype=torch.float32, device=device)
+        self.t_out = torch.empty(max(capacity, 1), dtype=torch.float32, device=device)
+        self.ray_off = torch.empty(R + 1, dtype=torch.int32, device=device)
+        self.counts = torch.zeros(2, dtype=torch.int64, device=device)
+
+
+def trace_octree_into(model: Model, o, d, target_depth: int, buf: TraceBuffers):
+    """Enqueue the ray-octree intersection into preallocated buffers (no sync)."""
+    R = o.shape[1]
+    assert buf.R == R
+    _check(lib().ngl_trace_octree(model.ref, _ptr(o), _ptr(d), R, int(target_depth), buf.capacity, _ptr(buf.ws),
+                                  buf.ws.numel(), _ptr(buf.ray), _ptr(buf.vox), _ptr(buf.t_in), _ptr(buf.t_out),
+                                  _ptr(buf.ray_off), _ptr(buf.counts), _stream()))
+
+
+def trace_octree(model: Model, o: torch.Tensor, d: torch.Tensor, target_depth: int, capacity: int = None,
+                 buffers: TraceBuffers = None):
+    """Front-to-back hit lists at `target_depth`.  Reads the device counts
+    (one stream synchronisation) and retries with a larger capacity while a
+    list overflowed."""
+    _dev(o, torch.float32)
+    _dev(d, torch.float32)
+    R = o.shape[1]
+    cap = capacity if capacity is not None else max(8 * R, 1 << 16)
+    buf = buffers if buffers is not None and buffers.capacity >= cap else TraceBuffers(R, cap, o.device)
+    trace_octree_into(model, o, d, target_depth, buf)
+    counts = buf.counts.cpu()
+    # After an overflow the sizes of deeper lists are lower bounds: grow
+    # (at least doubling) until every list fits.
+    while int(counts[1]) > buf.capacity:
+        buf = TraceBuffers(R, max(int(counts[1]), 2 * buf.capacity), o.device)
+        trace_octree_into(model, o, d, target_depth, buf)
+        counts = buf.counts.cpu()
+    n = int(counts[0])
+    return dict(ray=buf.ray[:n], vox=buf.vox[:n], t_in=buf.t_in[:n], t_out=buf.t_out[:n], ray_off=buf.ray_off,
+                count=n, max_list=int(counts[1]), buffers=buf)
+
+
+def trace_params(max_steps: int, delta: float, t_far: float = 5.0, osc_check: bool = False, analytic_sphere=None):
+    p = ngl_trace_params()
+    p.max_steps = int(max_steps)
+    p.delta = float(delta)
+    p.t_far = float(t_far)
+    p.osc_check = int(osc_check)
+    p.analytic = int(analytic_sphere is not None)
+    if analytic_sphere is not None:
+        for k in range(4):
+            p.sphere[k] = float(analytic_sphere[k])
+    return p
+
+
+def sphere_trace(model: Model, o, d, lod: int, alpha: float, hits: dict, max_steps: int, delta: float,
+                 t_far: float = 5.0, osc_check: bool = False, analytic_sphere=None, out=None):
+    R = o.shape[1]
+    dev = o.device
+    if out is None:
+        out = dict(t=torch.empty(R, dtype=torch.float32, device=dev),
+                   status=torch.empty(R, dtype=torch.uint8, device=dev),
+                   steps=torch.empty(R, dtype=torch.int32, device=dev),
+                   hit_vox=torch.empty(R, dtype=torch.int32, device=dev))
+    prm = trace_params(max_steps, delta, t_far, osc_check, analytic_sphere)
+    _check(lib().ngl_sphere_trace(model.ref, _ptr(o), _ptr(d), R, int(lod), float(alpha), _ptr(hits["vox"]),
+                                  _ptr(hits["t_in"]), _ptr(hits["t_out"]), _ptr(hits["ray_off"]), C.addressof(prm),
+                                  _ptr(out["t"]), _ptr(out["status"]), _ptr(out["steps"]), _ptr(out["hit_vox"]),
+                                  _stream()))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# 4. Training
+# ---------------------------------------------------------------------------
+class Grads:
+    """FP32 gradient buffers laid out like the model's parameters."""
+
+    def __init__(self, model: Model):
+        dev = model.b2.device
+        self.dfeat = [torch.empty(f.shape, dtype=torch.float32, device=dev) for f in model.feats]
+        self.dW1 = [torch.empty(w.shape, dtype=torch.float32, device=dev) for w in model.W1]
+        self.db1 = [torch.empty_like(b) for b in model.b1]
+        self.dw2 = [torch.empty_like(w) for w in model.w2]
+        self.db2 = torch.empty_like(model.b2)
+        arr = lambda lst: (P * MAX_LODS)(*[_ptr(t) for t in lst])
+        self._pf, self._pw1, self._pb1, self._pw2 = arr(self.dfeat), arr(self.dW1), arr(self.db1), arr(self.dw2)
+
+
+def train_workspace(model: Model, P_: int, device="cuda") -> torch.Tensor:
+    nb = C.c_size_t()
+    _check(lib().ngl_train_workspace(model.ref, int(P_), C.addressof(nb)))
+    return torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=device)
+
+
+def train_fwd_bwd(model: Model, x: torch.Tensor, target: torch.Tensor, grads: Grads = None, ws: torch.Tensor = None,
+                  sdf_all: torch.Tensor = None, loss: torch.Tensor = None):
+    _dev(x, torch.float32)
+    _dev(target, torch.float32)
+    Pn = x.shape[1]
+    g = grads if grads is not None else Grads(model)
+    w = ws if ws is not None else train_workspace(model, Pn, x.device)
+    ls = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=x.device)
+    _check(lib().ngl_train_fwd_bwd(model.ref, _ptr(x), _ptr(target), Pn, _ptr(ls), _ptr(sdf_all), g._pf, g._pw1,
+                                   g._pb1, g._pw2, _ptr(g.db2), _ptr(w), w.numel(), _stream()))
+    return ls, g
+
+
+def backward_all_lods(model: Model, x: torch.Tensor, grad_sdf: torch.Tensor, grads: Grads = None,
+                      ws: torch.Tensor = None) -> Grads:
+    _dev(x, torch.float32)
+    _dev(grad_sdf, torch.float32)
+    Pn = x.shape[1]
+    g = grads if grads is not None else Grads(model)
+    w = ws if ws is not None else train_workspace(model, Pn, x.device)
+    _check(lib().ngl_backward_all_lods(model.ref, _ptr(x), Pn, _ptr(grad_sdf), g._pf, g._pw1, g._pb1, g._pw2,
+                                       _ptr(g.db2), _ptr(w), w.numel(), _stream()))
+    return g

@@ -1,0 +1,66 @@
+"""The C-ABI library loads and exports every symbol include/ngl.h declares;
+host-only entry points (octree build, argument checks) run without a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2101_10994_amd import ngl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ngl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ngl_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ngl.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in ngl.EXPORTS, n
+
+
+def test_status_strings():
+    lib = ngl.lib()
+    assert lib.ngl_status_str(0) == b"ok"
+    assert lib.ngl_status_str(1) == b"invalid argument"
+    assert lib.ngl_version() >= 1
+
+
+def test_struct_layout_matches_header():
+    import ctypes as C
+    # 6 int32 + 10+8 int64 + 6*10 + 5*8 + 1 pointers
+    assert C.sizeof(ngl.ngl_model) == 6 * 4 + 18 * 8 + (4 * 10 + 5 * 8 + 1) * 8
+    assert C.sizeof(ngl.ngl_trace_params) == 4 * 5 + 16
+
+
+def test_plan_rejects_bad_input():
+    lib = ngl.lib()
+    nv = np.zeros(10, np.int64)
+    nc = np.zeros(8, np.int64)
+    bad = np.array([[16, 0, 0]], np.int32)
+    assert lib.ngl_octree_plan(bad.ctypes.data, 1, 3, nv.ctypes.data, nc.ctypes.data) == 1
+    assert b"outside" in lib.ngl_last_error()
+    ok = np.array([[15, 0, 0]], np.int32)
+    assert lib.ngl_octree_plan(ok.ctypes.data, 1, 0, nv.ctypes.data, nc.ctypes.data) == 1
+    assert lib.ngl_octree_plan(ok.ctypes.data, 1, 9, nv.ctypes.data, nc.ctypes.data) == 1
+    assert lib.ngl_octree_plan(ok.ctypes.data, 1, 3, nv.ctypes.data, nc.ctypes.data) == 0
+    assert list(nv[:5]) == [1, 1, 1, 1, 1]
+
+
+def test_device_calls_validate_before_launch():
+    lib = ngl.lib()
+    import ctypes as C
+    m = ngl.ngl_model()
+    m.num_lods = 0
+    assert lib.ngl_query_sdf(C.addressof(m), None, 0, 1, 0.0, None, None, None, None, None) == 1
+    m.num_lods = 2
+    assert lib.ngl_trace_octree(C.addressof(m), None, None, 0, 7, 0, None, 0, None, None, None, None, None, None,
+                                None) == 1
+    assert b"target_depth" in lib.ngl_last_error()

@@ -1,0 +1,52 @@
+"""The library's host octree build (the initialisation pass of Sec. 3.4)
+equals the oracle's independent construction array for array."""
+import numpy as np
+from hypothesis import given, settings, strategies as st
+
+import oracle
+from paper_2101_10994_amd import ngl
+from paper_2101_10994_amd import workloads as W
+
+
+def compare(ijk, L):
+    t = ngl.Octree(ijk, L, device=None)
+    o = oracle.Octree(ijk, L)
+    assert np.array_equal(t.nvox, o.nvox)
+    assert np.array_equal(t.ncorner, o.ncorner)
+    for d in range(L + 2):
+        e = o.export_depth(d)
+        assert np.array_equal(t.cell_ijk(d), e["ijk"])
+        assert np.array_equal(t.child_mask[d], e["child_mask"])
+        if d < L + 1:
+            assert np.array_equal(t.first_child[d], e["first_child"])
+        assert np.array_equal(t.parent[d], e["parent"])
+    for lvl in range(1, L + 1):
+        corners, cijk = o.export_corners(lvl)
+        assert np.array_equal(t.corners[lvl - 1], corners)
+        assert np.array_equal(t.corner_cell[lvl - 1], cijk)
+
+
+def test_tiny_sphere():
+    compare(W.occupancy_ijk(W.tiny_shape(), 16), 3)
+
+
+def test_paper_shape():
+    compare(W.occupancy_ijk(W.paper_shape(0), 64), 5)
+
+
+def test_deep_octree():
+    # 8 LODs (finest res 512) on a sparse random set
+    rng = np.random.default_rng(0)
+    compare(rng.integers(0, 512, size=(3000, 3)).astype(np.int32), 8)
+
+
+def test_empty():
+    t = ngl.Octree(np.zeros((0, 3), np.int32), 2, device=None)
+    assert list(t.nvox) == [0, 0, 0, 0]
+
+
+@settings(max_examples=30, deadline=None)
+@given(st.integers(1, 4), st.integers(0, 2 ** 31 - 1), st.integers(1, 200))
+def test_random(L, seed, n):
+    rng = np.random.default_rng(seed)
+    compare(rng.integers(0, 2 ** (L + 1), size=(n, 3)).astype(np.int32), L)
