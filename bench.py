@@ -1,0 +1,286 @@
+"""Benchmark of the neural geometric LOD hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input on
+the paper-scale workload (union of 8 spheres and a torus, 5 LODs at
+resolutions 4..64, 32-dim corner features, 35->128->1 decoders):
+  * 2^20 SDF queries at LOD 5 (half uniform, half near-surface);
+  * one 1024x1024 frame: camera rays, breadth-first ray-octree
+    intersection down to the finest depth, adaptive-stepping sphere trace
+    (<= 100 SDF evaluations per ray, hit threshold 1e-4);
+  * one training forward+backward of Eq. 4 on 2^19 points (when the library
+    provides it).
+Prints one JSON line.  `value` is octree SDF queries per second of the
+query batch; frame rate and training points per second are reported next
+to it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "octree SDF queries/s, 1024^2 sphere-trace fps, fwd+bwd points/s at fixed err"
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 78.6   # non-packed FP32 FMA: 256 CU x 64 lanes/clk x 2 flop x 2.4 GHz
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup(device):
+    import torch
+    from paper_2101_10994_amd import ngl
+    from paper_2101_10994_amd import workloads as W
+
+    cfg = W.PAPER
+    shape = W.paper_shape(0)
+    res = 2 ** (cfg.num_lods + 1)
+    ijk = W.occupancy_ijk(shape, res)
+    tree = ngl.Octree(ijk, cfg.num_lods, device=device)
+    rs = W.rngs(0)
+    feats = W.embedded_features(rs[W.STREAM_FEAT], shape, tree.corner_positions(), cfg.feat_dim)
+    dec = W.embedded_decoders(rs[W.STREAM_DEC], cfg.num_lods, cfg.feat_dim, cfg.hidden)
+    f32 = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=device)
+    model = ngl.Model(tree, [f32(f) for f in feats], [f32(w) for w in dec["W1"]], [f32(b) for b in dec["b1"]],
+                      [f32(w) for w in dec["w2"]], f32(dec["b2"]))
+    xq = W.soa(W.paper_queries(0, shape, cfg.n_query))
+    xt, tg = W.train_points(1, shape, W.TRAIN.n_query)
+    return dict(cfg=cfg, shape=shape, ijk=ijk, tree=tree, model=model, feats=feats, dec=dec,
+                xq_host=xq, xq=torch.from_numpy(xq).to(device), xt_host=W.soa(xt), tg_host=tg,
+                xt=torch.from_numpy(W.soa(xt)).to(device), tg=torch.from_numpy(tg).to(device))
+
+
+class Timer:
+    """HIP events on the current stream around one component."""
+
+    def __init__(self):
+        self.ms = []
+
+    def __enter__(self):
+        import torch
+        self.a = torch.cuda.Event(enable_timing=True)
+        self.b = torch.cuda.Event(enable_timing=True)
+        self.a.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.b.record()
+        self._pending = (self.a, self.b)
+        self.ms.append(self._pending)
+
+    def values(self):
+        return [a.elapsed_time(b) for a, b in self.ms]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="approximate CPU-baseline budget")
+    ap.add_argument("--only", choices=["query", "frame", "train"], default=None,
+                    help="run a single component (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the hot path is single-GPU (one process per GPU would replicate the "
+              "octree and shard rays/points; no multi-GPU run is part of this build). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2101_10994_amd import ngl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda"
+    S = setup(dev)
+    cfg, model = S["cfg"], S["model"]
+    W_, H_ = cfg.width, cfg.height
+    R = W_ * H_
+    lod = cfg.num_lods
+    eye = cfg.eye
+
+    # buffers
+    sdf = torch.empty(cfg.n_query, dtype=torch.float32, device=dev)
+    o = torch.empty((3, R), dtype=torch.float32, device=dev)
+    d = torch.empty((3, R), dtype=torch.float32, device=dev)
+    ngl.camera_rays(eye, (0, 0, 0), (0, 1, 0), 45.0, W_, H_, out=(o, d))
+    first = ngl.trace_octree(model, o, d, lod + 1)  # sizes the pair lists once
+    buf = ngl.TraceBuffers(R, first["max_list"], dev)
+    hits = dict(vox=buf.vox, t_in=buf.t_in, t_out=buf.t_out, ray_off=buf.ray_off)
+    tr = dict(t=torch.empty(R, dtype=torch.float32, device=dev),
+              status=torch.empty(R, dtype=torch.uint8, device=dev),
+              steps=torch.empty(R, dtype=torch.int32, device=dev),
+              hit_vox=torch.empty(R, dtype=torch.int32, device=dev))
+    have_train = True
+    try:
+        grads = ngl.Grads(model)
+        tws = ngl.train_workspace(model, S["xt"].shape[1], dev)
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+    except ngl.NGLError:
+        have_train = False
+
+    do_q = args.only in (None, "query")
+    do_f = args.only in (None, "frame")
+    do_t = args.only in (None, "train") and have_train
+    tq, tc, tt, ts, ttr = Timer(), Timer(), Timer(), Timer(), Timer()
+
+    def step(timed):
+        if do_q:
+            if timed:
+                with tq:
+                    ngl.query_sdf(model, S["xq"], lod, out=sdf)
+            else:
+                ngl.query_sdf(model, S["xq"], lod, out=sdf)
+        if do_f:
+            if timed:
+                with tc:
+                    ngl.camera_rays(eye, (0, 0, 0), (0, 1, 0), 45.0, W_, H_, out=(o, d))
+                with tt:
+                    ngl.trace_octree_into(model, o, d, lod + 1, buf)
+                with ts:
+                    ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr)
+            else:
+                ngl.camera_rays(eye, (0, 0, 0), (0, 1, 0), 45.0, W_, H_, out=(o, d))
+                ngl.trace_octree_into(model, o, d, lod + 1, buf)
+                ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr)
+        if do_t:
+            if timed:
+                with ttr:
+                    ngl.train_fwd_bwd(model, S["xt"], S["tg"], grads=grads, ws=tws, loss=loss)
+            else:
+                ngl.train_fwd_bwd(model, S["xt"], S["tg"], grads=grads, ws=tws, loss=loss)
+
+    for k in range(args.warmup):
+        step(False)
+        log("warmup step %d done" % k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    log("timed %d steps: %.3f ms/step" % (args.steps, ms_per_step))
+    if do_f:
+        cnt = buf.counts.cpu()
+        assert int(cnt[1]) <= buf.capacity, "pair list overflowed during timing"
+
+    mean = lambda tm: float(np.mean(tm.values())) if tm.ms else None
+    comp = {}
+    qps = None
+    if do_q:
+        q_ms = mean(tq)
+        qps = cfg.n_query / (q_ms * 1e-3)
+        comp["query"] = {"ms": q_ms, "queries_per_s": qps, "points": cfg.n_query, "lod": lod}
+    if do_f:
+        status = tr["status"].cpu().numpy()
+        steps_arr = tr["steps"].cpu().numpy()
+        frame_ms = mean(tc) + mean(tt) + mean(ts)
+        n_eval = int(steps_arr.sum())
+        comp["frame"] = {"ms": frame_ms, "fps": 1e3 / frame_ms, "rays_per_s": R / (frame_ms * 1e-3),
+                         "camera_ms": mean(tc), "traverse_ms": mean(tt), "trace_ms": mean(ts),
+                         "visible_px": int((status == ngl.HIT).sum()), "rays_with_voxels": int(
+                             (buf.ray_off[1:] > buf.ray_off[:-1]).sum()),
+                         "final_pairs": int(buf.counts[0]), "sdf_evals": n_eval,
+                         "sdf_evals_per_s": n_eval / (mean(ts) * 1e-3)}
+    if do_t:
+        tr_ms = mean(ttr)
+        comp["train"] = {"ms": tr_ms, "points_per_s": S["xt"].shape[1] / (tr_ms * 1e-3), "points": S["xt"].shape[1]}
+
+    # Roofline of the dominant kernel (largest time in the step).
+    roof = None
+    cand = []
+    if do_q:
+        # algorithmic work per query at LOD 5 with m=32, h=128:
+        # gather 5 levels x (8 corner rows x 32 x 4 B + 8 x 4 B corner ids) + 12 B point + 4 B result;
+        # flops: trilinear 5 x 8 x 32 x 2 + decoder 2 x (35 x 128 + 128) + 2 x 128
+        q_flops = 5 * 8 * 32 * 2 + 2 * (35 * 128 + 128) + 2 * 128
+        cand.append(("k_query", comp["query"]["ms"], q_flops * cfg.n_query))
+    if do_f:
+        cand.append(("k_sphere_trace", comp["frame"]["trace_ms"],
+                     (5 * 8 * 32 * 2 + 2 * (35 * 128 + 128) + 2 * 128) * comp["frame"]["sdf_evals"]))
+    if do_t:
+        cand.append(("train", comp["train"]["ms"], None))
+    if cand:
+        name, ms, flops = max(cand, key=lambda c: c[1])
+        if flops is not None:
+            ach = flops / (ms * 1e-3) / 1e12
+            roof = {"kernel": name, "bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None}
+
+    cpu = None
+    if not args.no_cpu and do_q:
+        cpu = cpu_baseline(S, args.cpu_seconds)
+
+    out = {"metric": METRIC, "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "union8s1t-5lod-m32: 2^20 queries at LOD 5 + 1024x1024 frame "
+                                  "(<=100 steps, delta 1e-4)" + (" + 2^19-point train step" if do_t else ""),
+                      "lods": cfg.num_lods, "feat_dim": cfg.feat_dim, "hidden": cfg.hidden,
+                      "queries": cfg.n_query, "image": [W_, H_], "train_points": S["xt"].shape[1]},
+           "roofline": roof, "cpu_baseline": cpu, "components": comp}
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(S, budget_s):
+    """The FP64 oracle on a bounded sample of the same workload, timed on the
+    host cores; scaled to the metric's unit."""
+    import oracle
+    cfg = S["cfg"]
+    t0 = time.perf_counter()
+    otree = oracle.Octree(S["ijk"], cfg.num_lods)
+    feats = S["feats"]
+    dec = S["dec"]
+    om = oracle.Model([np.asarray(f, np.float32).astype(np.float64) for f in feats],
+                      [np.asarray(w, np.float32).astype(np.float64) for w in dec["W1"]],
+                      [np.asarray(b, np.float32).astype(np.float64) for b in dec["b1"]],
+                      [np.asarray(w, np.float32).astype(np.float64) for w in dec["w2"]],
+                      np.asarray(dec["b2"], np.float32).astype(np.float64))
+    build_s = time.perf_counter() - t0
+    cores = oracle.max_threads()
+    # queries: grow the sample until about a third of the budget is spent
+    n = 4096
+    xq = S["xq_host"]
+    while True:
+        t0 = time.perf_counter()
+        oracle.query(otree, om, np.ascontiguousarray(xq[:, :n]), cfg.num_lods)
+        dt = time.perf_counter() - t0
+        if dt > budget_s / 6 or n >= xq.shape[1]:
+            break
+        n = min(xq.shape[1], n * 4)
+    qps = n / dt
+    # frame: every k-th ray of the 1024^2 camera, scaled to the full frame
+    co, cd = oracle.camera_rays(cfg.eye, (0, 0, 0), (0, 1, 0), 45.0, cfg.width, cfg.height)
+    stride = 64
+    idx = np.arange(0, cfg.width * cfg.height, stride)
+    o = np.ascontiguousarray(co[:, idx].astype(np.float32))
+    d = np.ascontiguousarray(cd[:, idx].astype(np.float32))
+    t0 = time.perf_counter()
+    hits = oracle.trace_octree(otree, o, d, cfg.num_lods + 1)
+    oracle.sphere_trace(otree, om, o, d, cfg.num_lods, 0.0, hits, cfg.max_steps, cfg.delta)
+    frame_s = (time.perf_counter() - t0) * stride
+    out = {"value": qps, "unit": "queries/s", "cores": cores, "kind": "oracle",
+           "sample": "%d of the 2^20 queries at LOD 5; frame from every %dth ray of the 1024^2 camera "
+                     "(traversal + trace), scaled x%d" % (n, stride, stride),
+           "fps_1024": 1.0 / frame_s, "octree_build_s": build_s}
+    # training step on a sample
+    nt = 8192
+    t0 = time.perf_counter()
+    oracle.train_fwd_bwd(otree, om, np.ascontiguousarray(S["xt_host"][:, :nt]), S["tg_host"][:nt])
+    out["train_points_per_s"] = nt / (time.perf_counter() - t0)
+    return out
+
+
+if __name__ == "__main__":
+    main()
