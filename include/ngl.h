@@ -96,6 +96,9 @@ typedef struct {
   int32_t* parent[NGL_MAX_DEPTH];       /* [nvox[d]] index of the parent at d-1 (-1 at the root) */
   int32_t* corners[NGL_MAX_LODS];       /* [nvox[l+1]][8] corner index of slot j */
   int32_t* corner_cell[NGL_MAX_LODS];   /* [ncorner[l-1]][3] lattice point of each corner */
+  int32_t* corner_adj_off[NGL_MAX_LODS]; /* [ncorner[l-1]+1] CSR offsets into corner_adj */
+  int32_t* corner_adj[NGL_MAX_LODS];     /* [8*nvox[l+1]] 8*v+j of every (voxel, slot) using the
+                                            corner, ascending per corner (used by training) */
 } ngl_octree_host;
 
 /* Fill the canonical layout (same inputs as ngl_octree_plan). */
@@ -123,6 +126,8 @@ typedef struct {
   const float* b1[NGL_MAX_LODS];             /* device, [h] */
   const float* w2[NGL_MAX_LODS];             /* device, [h] */
   const float* b2;                           /* device, [L] */
+  const int32_t* corner_adj_off[NGL_MAX_LODS]; /* device, training only: CSR of corner -> 8*v+j */
+  const int32_t* corner_adj[NGL_MAX_LODS];
 } ngl_model;
 
 /* ------------------------------------------------------------------ */

@@ -152,6 +152,20 @@ int ngl_octree_fill(const int32_t* ijk, int64_t n, int32_t num_lods, const ngl_o
         out->corners[l - 1][e.second] = idx;
       }
     }
+    if (out->corner_adj_off[l - 1] || out->corner_adj[l - 1]) {
+      // slots are sorted by (corner code, 8v+j): a CSR of corner -> 8v+j
+      int32_t idx = -1;
+      uint64_t prev = ~uint64_t(0);
+      for (size_t k = 0; k < s.size(); ++k) {
+        if (s[k].first != prev) {
+          ++idx;
+          prev = s[k].first;
+          if (out->corner_adj_off[l - 1]) out->corner_adj_off[l - 1][idx] = int32_t(k);
+        }
+        if (out->corner_adj[l - 1]) out->corner_adj[l - 1][k] = int32_t(s[k].second);
+      }
+      if (out->corner_adj_off[l - 1]) out->corner_adj_off[l - 1][idx + 1] = int32_t(s.size());
+    }
     if (out->corner_cell[l - 1]) {
       const auto& cc = t.corner_code[l - 1];
       for (size_t k = 0; k < cc.size(); ++k) {

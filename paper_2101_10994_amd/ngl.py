@@ -44,12 +44,14 @@ class ngl_model(C.Structure):
                 ("nvox", i64 * MAX_DEPTH), ("ncorner", i64 * MAX_LODS),
                 ("cell", P * MAX_DEPTH), ("child_mask", P * MAX_DEPTH), ("first_child", P * MAX_DEPTH),
                 ("parent", P * MAX_DEPTH), ("corners", P * MAX_LODS), ("feat", P * MAX_LODS),
-                ("W1", P * MAX_LODS), ("b1", P * MAX_LODS), ("w2", P * MAX_LODS), ("b2", P)]
+                ("W1", P * MAX_LODS), ("b1", P * MAX_LODS), ("w2", P * MAX_LODS), ("b2", P),
+                ("corner_adj_off", P * MAX_LODS), ("corner_adj", P * MAX_LODS)]
 
 
 class ngl_octree_host(C.Structure):
     _fields_ = [("cell", P * MAX_DEPTH), ("child_mask", P * MAX_DEPTH), ("first_child", P * MAX_DEPTH),
-                ("parent", P * MAX_DEPTH), ("corners", P * MAX_LODS), ("corner_cell", P * MAX_LODS)]
+                ("parent", P * MAX_DEPTH), ("corners", P * MAX_LODS), ("corner_cell", P * MAX_LODS),
+                ("corner_adj_off", P * MAX_LODS), ("corner_adj", P * MAX_LODS)]
 
 
 class ngl_trace_params(C.Structure):
@@ -144,6 +146,8 @@ class Octree:
         self.parent = [np.zeros(int(self.nvox[d]), np.int32) for d in range(D + 1)]
         self.corners = [np.zeros((int(self.nvox[lv + 1]), 8), np.int32) for lv in range(1, D)]
         self.corner_cell = [np.zeros((int(self.ncorner[lv - 1]), 3), np.int32) for lv in range(1, D)]
+        self.corner_adj_off = [np.zeros(int(self.ncorner[lv - 1]) + 1, np.int32) for lv in range(1, D)]
+        self.corner_adj = [np.zeros(8 * int(self.nvox[lv + 1]), np.int32) for lv in range(1, D)]
         h = ngl_octree_host()
         for d in range(D + 1):
             h.cell[d] = _ptr(self.cell[d])
@@ -153,6 +157,8 @@ class Octree:
         for lv in range(self.num_lods):
             h.corners[lv] = _ptr(self.corners[lv])
             h.corner_cell[lv] = _ptr(self.corner_cell[lv])
+            h.corner_adj_off[lv] = _ptr(self.corner_adj_off[lv])
+            h.corner_adj[lv] = _ptr(self.corner_adj[lv])
         _check(L.ngl_octree_fill(_ptr(ijk), ijk.shape[0], self.num_lods, C.addressof(h)))
         self.device = device
         self.d_cell = self.d_child_mask = self.d_first_child = self.d_parent = self.d_corners = None
@@ -166,6 +172,8 @@ class Octree:
         self.d_first_child = [t(a) for a in self.first_child]
         self.d_parent = [t(a) for a in self.parent]
         self.d_corners = [t(a) for a in self.corners]
+        self.d_corner_adj_off = [t(a) for a in self.corner_adj_off]
+        self.d_corner_adj = [t(a) for a in self.corner_adj]
         self.device = device
         return self
 
@@ -236,6 +244,8 @@ class Model:
             s.W1[lv] = _ptr(self.W1[lv])
             s.b1[lv] = _ptr(self.b1[lv])
             s.w2[lv] = _ptr(self.w2[lv])
+            s.corner_adj_off[lv] = _ptr(t.d_corner_adj_off[lv])
+            s.corner_adj[lv] = _ptr(t.d_corner_adj[lv]) if t.nvox[lv + 2] else None
         s.b2 = _ptr(self.b2)
         return s
 
@@ -391,8 +401,9 @@ class Grads:
         self.db1 = [torch.empty_like(b) for b in model.b1]
         self.dw2 = [torch.empty_like(w) for w in model.w2]
         self.db2 = torch.empty_like(model.b2)
-        arr = lambda lst: (P * MAX_LODS)(*[_ptr(t) for t in lst])
-        self._pf, self._pw1, self._pb1, self._pw2 = arr(self.dfeat), arr(self.dW1), arr(self.db1), arr(self.dw2)
+        arr = lambda lst: (P * MAX_LODS)(*[_ptr(t) if t.numel() else None for t in lst])
+        self._arrays = [arr(self.dfeat), arr(self.dW1), arr(self.db1), arr(self.dw2)]
+        self.ptrs = [C.addressof(a) for a in self._arrays]
 
 
 def train_workspace(model: Model, P_: int, device="cuda") -> torch.Tensor:
@@ -409,8 +420,8 @@ def train_fwd_bwd(model: Model, x: torch.Tensor, target: torch.Tensor, grads: Gr
     g = grads if grads is not None else Grads(model)
     w = ws if ws is not None else train_workspace(model, Pn, x.device)
     ls = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=x.device)
-    _check(lib().ngl_train_fwd_bwd(model.ref, _ptr(x), _ptr(target), Pn, _ptr(ls), _ptr(sdf_all), g._pf, g._pw1,
-                                   g._pb1, g._pw2, _ptr(g.db2), _ptr(w), w.numel(), _stream()))
+    _check(lib().ngl_train_fwd_bwd(model.ref, _ptr(x), _ptr(target), Pn, _ptr(ls), _ptr(sdf_all), g.ptrs[0],
+                                   g.ptrs[1], g.ptrs[2], g.ptrs[3], _ptr(g.db2), _ptr(w), w.numel(), _stream()))
     return ls, g
 
 
@@ -421,6 +432,34 @@ def backward_all_lods(model: Model, x: torch.Tensor, grad_sdf: torch.Tensor, gra
     Pn = x.shape[1]
     g = grads if grads is not None else Grads(model)
     w = ws if ws is not None else train_workspace(model, Pn, x.device)
-    _check(lib().ngl_backward_all_lods(model.ref, _ptr(x), Pn, _ptr(grad_sdf), g._pf, g._pw1, g._pb1, g._pw2,
-                                       _ptr(g.db2), _ptr(w), w.numel(), _stream()))
+    _check(lib().ngl_backward_all_lods(model.ref, _ptr(x), Pn, _ptr(grad_sdf), g.ptrs[0], g.ptrs[1], g.ptrs[2],
+                                       g.ptrs[3], _ptr(g.db2), _ptr(w), w.numel(), _stream()))
     return g
+
+
+# ---------------------------------------------------------------------------
+# autograd
+# ---------------------------------------------------------------------------
+class NGLODSdf(torch.autograd.Function):
+    """sdf_all = [f_theta_L([x, z_L(x)]) for L = 1..Lmax] (Eq. 2) with the
+    library's backward (FP32 model).  Usage:
+        sdf_all = NGLODSdf.apply(model, x, *model.parameters())
+    Gradients flow to the corner features and decoder parameters (not to x)."""
+
+    @staticmethod
+    def forward(ctx, model: Model, x: torch.Tensor, *params):
+        ctx.model = model
+        ctx.save_for_backward(x)
+        return query_sdf_all_lods(model, x.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (x,) = ctx.saved_tensors
+        model = ctx.model
+        g = backward_all_lods(model, x.contiguous(), grad_out.contiguous().float())
+        return (None, None, *g.dfeat, *g.dW1, *g.db1, *g.dw2, g.db2)
+
+
+def parameters(model: Model):
+    """The model's tensors in the order NGLODSdf.backward returns gradients."""
+    return [*model.feats, *model.W1, *model.b1, *model.w2, model.b2]

@@ -35,8 +35,8 @@ def test_status_strings():
 
 def test_struct_layout_matches_header():
     import ctypes as C
-    # 6 int32 + 10+8 int64 + 6*10 + 5*8 + 1 pointers
-    assert C.sizeof(ngl.ngl_model) == 6 * 4 + 18 * 8 + (4 * 10 + 5 * 8 + 1) * 8
+    # 6 int32 + 10+8 int64 + 4*10 + 5*8 + 1 + 2*8 pointers
+    assert C.sizeof(ngl.ngl_model) == 6 * 4 + 18 * 8 + (4 * 10 + 5 * 8 + 1 + 2 * 8) * 8
     assert C.sizeof(ngl.ngl_trace_params) == 4 * 5 + 16
 
 

@@ -24,6 +24,12 @@ def compare(ijk, L):
         corners, cijk = o.export_corners(lvl)
         assert np.array_equal(t.corners[lvl - 1], corners)
         assert np.array_equal(t.corner_cell[lvl - 1], cijk)
+        # adjacency: corner c is used exactly by the (v, j) with corners[v][j] == c, ascending
+        flat = corners.ravel()
+        order = np.argsort(flat, kind="stable")
+        assert np.array_equal(t.corner_adj[lvl - 1], order.astype(np.int32))
+        cnt = np.bincount(flat, minlength=int(t.ncorner[lvl - 1]))
+        assert np.array_equal(t.corner_adj_off[lvl - 1], np.concatenate([[0], np.cumsum(cnt)]).astype(np.int32))
 
 
 def test_tiny_sphere():
