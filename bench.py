@@ -7,8 +7,9 @@ resolutions 4..64, 32-dim corner features, 35->128->1 decoders):
   * one 1024x1024 frame: camera rays, breadth-first ray-octree
     intersection down to the finest depth, adaptive-stepping sphere trace
     (<= 100 SDF evaluations per ray, hit threshold 1e-4);
-  * one training forward+backward of Eq. 4 on 2^19 points (when the library
-    provides it).
+  * one training forward+backward of Eq. 4 on 2^19 points;
+  * the same queries and trace in the BF16-MFMA form (FP16 features, BF16
+    first decoder layer with FP32 accumulation) next to the plain FP32 form.
 Prints one JSON line.  `value` is octree SDF queries per second of the
 query batch; frame rate and training points per second are reported next
 to it.
@@ -52,9 +53,12 @@ def setup(device):
     f32 = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=device)
     model = ngl.Model(tree, [f32(f) for f in feats], [f32(w) for w in dec["W1"]], [f32(b) for b in dec["b1"]],
                       [f32(w) for w in dec["w2"]], f32(dec["b2"]))
+    # the BF16-MFMA form of the same model: FP16 features, BF16 first layer
+    half = ngl.Model(tree, [f32(f).half() for f in feats], [f32(w).bfloat16() for w in dec["W1"]],
+                     [f32(b) for b in dec["b1"]], [f32(w) for w in dec["w2"]], f32(dec["b2"]))
     xq = W.soa(W.paper_queries(0, shape, cfg.n_query))
     xt, tg = W.train_points(1, shape, W.TRAIN.n_query)
-    return dict(cfg=cfg, shape=shape, ijk=ijk, tree=tree, model=model, feats=feats, dec=dec,
+    return dict(cfg=cfg, shape=shape, ijk=ijk, tree=tree, model=model, half=half, feats=feats, dec=dec,
                 xq_host=xq, xq=torch.from_numpy(xq).to(device), xt_host=W.soa(xt), tg_host=tg,
                 xt=torch.from_numpy(W.soa(xt)).to(device), tg=torch.from_numpy(tg).to(device))
 
@@ -88,7 +92,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="approximate CPU-baseline budget")
-    ap.add_argument("--only", choices=["query", "frame", "train"], default=None,
+    ap.add_argument("--only", choices=["query", "frame", "train", "half"], default=None,
                     help="run a single component (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -132,7 +136,15 @@ def main():
     do_q = args.only in (None, "query")
     do_f = args.only in (None, "frame")
     do_t = args.only in (None, "train") and have_train
+    do_h = args.only in (None, "half")
     tq, tc, tt, ts, ttr = Timer(), Timer(), Timer(), Timer(), Timer()
+    thq, ths = Timer(), Timer()
+    half = S["half"]
+    sdf_h = torch.empty(cfg.n_query, dtype=torch.float32, device=dev)
+    tr_h = dict(t=torch.empty(R, dtype=torch.float32, device=dev),
+                status=torch.empty(R, dtype=torch.uint8, device=dev),
+                steps=torch.empty(R, dtype=torch.int32, device=dev),
+                hit_vox=torch.empty(R, dtype=torch.int32, device=dev))
 
     def step(timed):
         if do_q:
@@ -153,6 +165,19 @@ def main():
                 ngl.camera_rays(eye, (0, 0, 0), (0, 1, 0), 45.0, W_, H_, out=(o, d))
                 ngl.trace_octree_into(model, o, d, lod + 1, buf)
                 ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr)
+        if do_h:
+            # BF16-MFMA form: same queries; the trace reuses the frame's hit lists
+            if not do_f:
+                ngl.camera_rays(eye, (0, 0, 0), (0, 1, 0), 45.0, W_, H_, out=(o, d))
+                ngl.trace_octree_into(model, o, d, lod + 1, buf)
+            if timed:
+                with thq:
+                    ngl.query_sdf(half, S["xq"], lod, out=sdf_h)
+                with ths:
+                    ngl.sphere_trace(half, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_h)
+            else:
+                ngl.query_sdf(half, S["xq"], lod, out=sdf_h)
+                ngl.sphere_trace(half, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_h)
         if do_t:
             if timed:
                 with ttr:
@@ -193,6 +218,17 @@ def main():
                              (buf.ray_off[1:] > buf.ray_off[:-1]).sum()),
                          "final_pairs": int(buf.counts[0]), "sdf_evals": n_eval,
                          "sdf_evals_per_s": n_eval / (mean(ts) * 1e-3)}
+    if do_h:
+        hq_ms, hs_ms = mean(thq), mean(ths)
+        st_h = tr_h["status"].cpu().numpy()
+        n_eval_h = int(tr_h["steps"].cpu().numpy().sum())
+        comp["bf16_form"] = {"features": "f16", "decoder": "bf16 MFMA, fp32 accumulate",
+                             "query_ms": hq_ms, "queries_per_s": cfg.n_query / (hq_ms * 1e-3),
+                             "trace_ms": hs_ms, "sdf_evals": n_eval_h, "sdf_evals_per_s": n_eval_h / (hs_ms * 1e-3),
+                             "visible_px": int((st_h == ngl.HIT).sum()),
+                             "frame_ms": (mean(tc) + mean(tt) + hs_ms) if do_f else None}
+        if do_q:
+            comp["bf16_form"]["max_abs_diff_vs_fp32"] = float((sdf_h - sdf).abs().max())
     if do_t:
         tr_ms = mean(ttr)
         comp["train"] = {"ms": tr_ms, "points_per_s": S["xt"].shape[1] / (tr_ms * 1e-3), "points": S["xt"].shape[1]}

@@ -222,11 +222,21 @@ typedef struct {
  * and its ancestors (local coordinates clamped to the voxel), and stop
  * with HIT when it is below delta, else t += sdf.  t accumulates in FP32.
  * Outputs (device, [R]): t_hit (t at termination), status (ngl_ray_status),
- * steps (SDF evaluations), hit_vox (pair voxel at HIT, else -1). */
+ * steps (SDF evaluations), hit_vox (pair voxel at HIT, else -1).
+ * The hit lists must come from ngl_trace_octree at depth L'+1 with the same
+ * rays; a voxel index outside that depth ends its ray as INVALID.  Rays are
+ * processed by a persistent grid whose lanes take the next ray from a queue
+ * in `ws` when theirs ends; results do not depend on the schedule. */
 int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t R, int32_t lod,
                      float alpha, const int32_t* pair_vox, const float* t_in, const float* t_out,
                      const int32_t* ray_off, const ngl_trace_params* params, float* t_hit,
-                     uint8_t* status, int32_t* steps, int32_t* hit_vox, void* stream);
+                     uint8_t* status, int32_t* steps, int32_t* hit_vox, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/* Bytes of device workspace ngl_sphere_trace needs (a work-queue counter,
+ * cleared by the call itself).  Calls that share a workspace must not run
+ * concurrently. */
+int ngl_sphere_trace_workspace(size_t* bytes);
 
 /* ------------------------------------------------------------------ */
 /* 4. Training (Sec. 3.3, Eq. 4)                                        */

@@ -84,7 +84,7 @@ def _setup(lib):
     lib.orc_octree_export_depth.argtypes = [P, C.c_int, P, P, P, P]
     lib.orc_octree_export_corners.argtypes = [P, C.c_int, P, P]
     lib.orc_query.restype = C.c_int
-    lib.orc_query.argtypes = [P, P, P, i64, C.c_int, C.c_double, P, P, P, P, P]
+    lib.orc_query.argtypes = [P, P, P, i64, C.c_int, C.c_double, P, P, P, P, P, P]
     lib.orc_ray_box.restype = C.c_int
     lib.orc_ray_box.argtypes = [P, P, C.c_int, P, P, P]
     lib.orc_trace_octree.restype = i64
@@ -202,7 +202,8 @@ class Model:
 def query(tree: Octree, model: Model, x_soa: np.ndarray, lod: int, alpha: float = 0.0,
           alpha_pp: np.ndarray = None, want_vox: bool = False):
     """SDF at LOD `lod` (+alpha).  x_soa: float32 [3][P].
-    Returns dict(sdf, scale, valid, vox)."""
+    Returns dict(sdf, scale, scale1, valid, vox); scale and scale1 are the
+    magnitude scales used in error bounds (see decode in oracle.c)."""
     x = _c(x_soa, np.float32)
     Pn = x.shape[1]
     ap = None if alpha_pp is None else _c(alpha_pp, np.float32)
@@ -210,14 +211,15 @@ def query(tree: Octree, model: Model, x_soa: np.ndarray, lod: int, alpha: float 
     Lp = lod + 1 if blend else lod
     sdf = np.zeros(Pn)
     scale = np.zeros(Pn)
+    scale1 = np.zeros(Pn)
     valid = np.zeros(Pn, np.uint8)
     vox = np.zeros((Lp, Pn), np.int32) if want_vox else None
     ms = model.struct()
     rc = _load().orc_query(tree._h, C.addressof(ms), _ptr(x), Pn, int(lod), float(alpha), _ptr(ap),
-                           _ptr(sdf), _ptr(scale), _ptr(valid), _ptr(vox))
+                           _ptr(sdf), _ptr(scale), _ptr(scale1), _ptr(valid), _ptr(vox))
     if rc != 0:
         raise ValueError("oracle query: invalid arguments")
-    return dict(sdf=sdf, scale=scale, valid=valid, vox=vox)
+    return dict(sdf=sdf, scale=scale, scale1=scale1, valid=valid, vox=vox)
 
 
 def ray_box(o, d, depth, cell):

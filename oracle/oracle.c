@@ -274,25 +274,42 @@ static void interp_level(const orc_octree* t, const orc_model* M, int l, const i
 }
 
 /* One decoder f_{theta_L}([x, z]) (Eq. 2): linear -> ReLU -> linear.
- * Also returns the cancellation scale |b2| + sum_k |w2_k h_k|. */
-static double decode(const orc_model* M, int L, const double x[3], const double* z, double* scale) {
+ * Also returns two magnitude scales for error bounds (not part of the
+ * method): scale = |b2| + sum_k |w2_k h_k| (cancellation in the last dot
+ * product) and scale1 = |b2| + sum_k |w2_k| (|b1_k| + sum_i |W1_ki in_i|)
+ * (magnitude of the first layer's products, which bounds the effect of
+ * rounding the first layer's inputs). */
+static double decode(const orc_model* M, int L, const double x[3], const double* z, double* scale,
+                     double* scale1) {
   int din = din_of(M), H = M->hidden;
   const double* W1 = M->W1[L - 1];
   const double* b1 = M->b1[L - 1];
   const double* w2 = M->w2[L - 1];
   double out = M->b2[L - 1];
   double s = fabs(M->b2[L - 1]);
+  double s1 = fabs(M->b2[L - 1]);
   for (int k = 0; k < H; ++k) {
     double a = b1[k];
+    double mag = fabs(b1[k]);
     int col = 0;
     if (M->with_xyz)
-      for (int q = 0; q < 3; ++q) a += W1[(size_t)k * din + col++] * x[q];
-    for (int q = 0; q < M->m; ++q) a += W1[(size_t)k * din + col++] * z[q];
+      for (int q = 0; q < 3; ++q) {
+        a += W1[(size_t)k * din + col] * x[q];
+        mag += fabs(W1[(size_t)k * din + col] * x[q]);
+        ++col;
+      }
+    for (int q = 0; q < M->m; ++q) {
+      a += W1[(size_t)k * din + col] * z[q];
+      mag += fabs(W1[(size_t)k * din + col] * z[q]);
+      ++col;
+    }
     double h = a > 0.0 ? a : 0.0;
     out += w2[k] * h;
     s += fabs(w2[k] * h);
+    s1 += fabs(w2[k]) * mag;
   }
   if (scale) *scale = s;
+  if (scale1) *scale1 = s1;
   return out;
 }
 
@@ -302,13 +319,13 @@ static double decode(const orc_model* M, int L, const double x[3], const double*
  *   unless alpha_pp (nullable, [P]) is given.  alpha > 0 needs lod < Lmax.
  * For every level l <= L' (L' = lod, or lod+1 when blending), the voxel of
  * depth l+1 containing x is looked up; a missing voxel contributes psi = 0.
- * Outputs sdf[P], scale[P] (cancellation scale of the final dot product,
- * blended like the sdf), valid[P] (voxel at level L' exists) and, if
+ * Outputs sdf[P], scale[P] and scale1[P] (the magnitude scales of decode,
+ * blended like the sdf; nullable), valid[P] (voxel at level L' exists) and, if
  * vox_out is not NULL, vox_out[l-1][P] for l = 1..L' (-1 when absent).
  * Returns 0, or -1 on invalid arguments.
  */
 int orc_query(const orc_octree* t, const orc_model* M, const float* xs, int64_t P, int lod,
-              double alpha, const float* alpha_pp, double* sdf, double* scale, uint8_t* valid,
+              double alpha, const float* alpha_pp, double* sdf, double* scale, double* scale1, uint8_t* valid,
               int32_t* vox_out) {
   if (lod < 1 || lod > M->num_lods || M->num_lods != t->num_lods) return -1;
   int need_next = alpha_pp != NULL || alpha > 0.0;
@@ -339,16 +356,18 @@ int orc_query(const orc_octree* t, const orc_model* M, const float* xs, int64_t 
       else for (int k = 0; k < m; ++k) z_next[k] = z[k] + psi[k];
       if (l == Lp) last_exists = v >= 0;
     }
-    double s0, s1 = 0.0;
-    double d0 = decode(M, lod, x, z, &s0);
-    double d = d0, s = s0;
+    double s0, s1 = 0.0, r0, r1 = 0.0;
+    double d0 = decode(M, lod, x, z, &s0, &r0);
+    double d = d0, s = s0, r = r0;
     if (need_next) {
-      double d1 = decode(M, lod + 1, x, z_next, &s1);
+      double d1 = decode(M, lod + 1, x, z_next, &s1, &r1);
       d = (1.0 - a) * d0 + a * d1;
       s = (1.0 - a) * s0 + a * s1;
+      r = (1.0 - a) * r0 + a * r1;
     }
     sdf[p] = d;
     if (scale) scale[p] = s;
+    if (scale1) scale1[p] = r;
     if (valid) valid[p] = (uint8_t)last_exists;
     free(z); free(psi); free(z_next);
   }
@@ -579,9 +598,9 @@ static double query_in_voxel(const orc_octree* t, const orc_model* M, int lod, d
     else for (int k = 0; k < m; ++k) zn[k] = z[k] + psi[k];
   }
   double s0, s1;
-  double d0 = decode(M, lod, x, z, &s0);
+  double d0 = decode(M, lod, x, z, &s0, NULL);
   if (alpha > 0.0) {
-    double d1 = decode(M, lod + 1, x, zn, &s1);
+    double d1 = decode(M, lod + 1, x, zn, &s1, NULL);
     *scale = (1.0 - alpha) * s0 + alpha * s1;
     return (1.0 - alpha) * d0 + alpha * d1;
   }

@@ -112,11 +112,15 @@ __device__ inline int cell_z(uint32_t c) { return int(c >> 20 & 1023u); }
 
 // Descend from the root to depth `depth` along the cell (cx,cy,cz) given at
 // that depth; vox[l-1] receives the voxel of feature level l (depth l+1)
-// for l = 1..depth-1, or -1 once a voxel is absent.
+// for l = 1..depth-1, or -1 once a voxel is absent.  *last receives the
+// voxel at `depth` (or -1), and *at receives the voxel of level `want`
+// (or -1), without indexing vox at run time.
 template <int MAXL>
-__device__ inline void descend(const ngl_model& md, int cx, int cy, int cz, int depth, int* vox) {
+__device__ inline void descend(const ngl_model& md, int cx, int cy, int cz, int depth, int* vox, int* last = nullptr,
+                               int want = -1, int* at = nullptr) {
   int v = 0;
   bool alive = md.nvox[0] > 0;
+  int vl = -1, va = -1;
 #pragma unroll
   for (int d = 0; d < MAXL + 1; ++d) {
     if (d < depth) {
@@ -130,9 +134,14 @@ __device__ inline void descend(const ngl_model& md, int cx, int cy, int cz, int 
           alive = false;
         }
       }
-      if (d >= 1) vox[d - 1] = alive ? v : -1;
+      const int cur = alive ? v : -1;
+      if (d >= 1) vox[d - 1] = cur;
+      if (d == depth - 1) vl = cur;
+      if (d == want) va = cur;
     }
   }
+  if (last) *last = vl;
+  if (at) *at = va;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,162 @@
+// Wavefront-level decoder on the gfx950 matrix cores.
+//
+// The 64 lanes of a wavefront each hold one point: its position x and its
+// summed feature z (FP32, Eq. 2).  The decoder's first layer for all 64 points
+// is a [h x K] x [K x 64] product evaluated as 16x16 tiles with
+// v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32 accumulation); ReLU, the
+// second layer (a dot product with w2) and the cross-lane reduction follow in
+// FP32.  Operand layouts (verified on gfx950):
+//   A[i][k]: lane l holds i = l%16, k = 8*(l/16) + 0..7
+//   B[k][j]: lane l holds j = l%16, k = 8*(l/16) + 0..7
+//   D[i][j]: lane l holds j = l%16, i = 4*(l/16) + r, r = 0..3
+// Layer-1 inputs: K-step s < KZ covers features 32s..32s+31 (BF16, zero
+// padded); the last K-step carries the position and the bias split into
+// high and low BF16 parts, x = x_hi + x_lo, b1 = b1_hi + b1_lo, so they keep
+// about 16 significant bits: columns [x_hi(3), x_lo(3), 1, 1, 0...] against
+// weights [W1_x(3), W1_x(3), b1_hi, b1_lo, 0...].
+#pragma once
+
+#include "ngl_device.h"
+
+namespace ngl {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// Round-to-nearest-even FP32 -> BF16 bits (finite inputs).
+__device__ inline uint32_t f32_to_bf16_bits(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+template <int M, bool XYZ>
+struct MfmaShape {
+  static constexpr int OFF = XYZ ? 3 : 0;
+  static constexpr int KZ = (M + 31) / 32;   // K-steps over the features
+  static constexpr int KS = KZ + 1;          // + position/bias step
+  static constexpr int ROW = KS * 32 + 8;    // staged BF16 elements per point (16 B pad)
+  static constexpr int STAGE_BYTES = 64 * ROW * 2;
+  static constexpr int frag_bytes(int H) { return (H / 16) * KS * 64 * 16; }
+};
+
+// Block-cooperative: A fragments of decoder L (BF16 weights) into LDS, and
+// its w2 (FP32).  frag: [H/16][KS][64] 16-byte fragments.
+template <int M, bool XYZ>
+__device__ inline void load_frags(const ngl_model& md, int L, uint4* frag, float* w2s) {
+  using S = MfmaShape<M, XYZ>;
+  const int H = md.hidden;
+  const int din = M + S::OFF;
+  const uint16_t* W1 = static_cast<const uint16_t*>(md.W1[L - 1]);
+  const float* b1 = md.b1[L - 1];
+  const int n = (H / 16) * S::KS * 64;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int lane = e & 63;
+    const int s = (e >> 6) % S::KS;
+    const int h = (e >> 6) / S::KS;
+    const int i = 16 * h + (lane & 15);
+    const int g = lane >> 4;
+    uint32_t bits[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int kk = 8 * g + q;
+      uint32_t b = 0;
+      if (s < S::KZ) {
+        const int f = 32 * s + kk;
+        if (f < M) b = W1[i * din + S::OFF + f];
+      } else if (XYZ) {
+        if (kk < 3) b = W1[i * din + kk];
+        else if (kk < 6) b = W1[i * din + kk - 3];
+        else if (kk == 6) b = f32_to_bf16_bits(b1[i]);
+        else if (kk == 7) b = f32_to_bf16_bits(b1[i] - __uint_as_float(f32_to_bf16_bits(b1[i]) << 16));
+      } else {
+        if (kk == 0) b = f32_to_bf16_bits(b1[i]);
+        else if (kk == 1) b = f32_to_bf16_bits(b1[i] - __uint_as_float(f32_to_bf16_bits(b1[i]) << 16));
+      }
+      bits[q] = b;
+    }
+    frag[e] = make_uint4(bits[0] | bits[1] << 16, bits[2] | bits[3] << 16, bits[4] | bits[5] << 16,
+                         bits[6] | bits[7] << 16);
+  }
+  for (int k = threadIdx.x; k < H; k += blockDim.x) w2s[k] = md.w2[L - 1][k];
+}
+
+// Orders this wavefront's LDS writes before its later LDS reads.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Stage this lane's decoder input row (BF16) into the wavefront's buffer.
+template <int M, bool XYZ>
+__device__ inline void stage_row(uint16_t* stage, const float x[3], const float* z) {
+  using S = MfmaShape<M, XYZ>;
+  const int lane = threadIdx.x & 63;
+  uint32_t* row = reinterpret_cast<uint32_t*>(stage + lane * S::ROW);
+#pragma unroll
+  for (int s = 0; s < S::KZ; ++s) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int f0 = 32 * s + 2 * q, f1 = f0 + 1;
+      const uint32_t lo = f0 < M ? f32_to_bf16_bits(z[f0 < M ? f0 : 0]) : 0u;
+      const uint32_t hi = f1 < M ? f32_to_bf16_bits(z[f1 < M ? f1 : 0]) : 0u;
+      row[16 * s + q] = lo | hi << 16;
+    }
+  }
+  uint32_t t[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) t[q] = 0;
+  if (XYZ) {
+    uint32_t hi[3], lo[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      hi[a] = f32_to_bf16_bits(x[a]);
+      lo[a] = f32_to_bf16_bits(x[a] - __uint_as_float(hi[a] << 16));
+    }
+    t[0] = hi[0] | hi[1] << 16;
+    t[1] = hi[2] | lo[0] << 16;
+    t[2] = lo[1] | lo[2] << 16;
+    t[3] = 0x3f80u | 0x3f80u << 16;  // 1.0, 1.0
+  } else {
+    t[0] = 0x3f80u | 0x3f80u << 16;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) row[16 * S::KZ + q] = t[q];
+}
+
+// First layer on the matrix cores, second layer and reduction in FP32: the
+// decoder output for this lane's staged point (all 64 lanes must call it).
+template <int M, bool XYZ>
+__device__ inline float wave_decode(const uint4* frag, const float* w2s, float b2, const uint16_t* stage, int H) {
+  using S = MfmaShape<M, XYZ>;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, j = lane & 15;
+  float mine = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    bf16x8 b[S::KS];
+#pragma unroll
+    for (int s = 0; s < S::KS; ++s)
+      b[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(stage + (16 * t + j) * S::ROW + 32 * s + 8 * g));
+    float part = 0.0f;
+    for (int h = 0; h < H / 16; ++h) {
+      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < S::KS; ++s)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, frag[(h * S::KS + s) * 64 + lane]),
+                                                      b[s], acc, 0, 0, 0);
+      const float4 w = *reinterpret_cast<const float4*>(w2s + 16 * h + 4 * g);
+      part = fmaf(w.x, fmaxf(acc[0], 0.0f), part);
+      part = fmaf(w.y, fmaxf(acc[1], 0.0f), part);
+      part = fmaf(w.z, fmaxf(acc[2], 0.0f), part);
+      part = fmaf(w.w, fmaxf(acc[3], 0.0f), part);
+    }
+    // sum over the four row groups of the tile (lanes j, j+16, j+32, j+48)
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (g == t) mine = part;
+  }
+  return b2 + mine;
+}
+
+}  // namespace ngl

@@ -5,24 +5,29 @@
 // gather summed across levels in registers, then the per-LOD decoder.
 #include "ngl_common.h"
 #include "ngl_device.h"
+#include "ngl_mfma.h"
 
 namespace ngl {
 
-// Locate x at feature levels 1..Lp: vox[l-1] (or -1) and the level's cell.
+// Locate x at feature levels 1..Lp: vox[l-1] (or -1) and the level's cell;
+// *vlast = voxel of level Lp, *vnext = voxel of level `next` (both or -1).
 template <int MAXL>
-__device__ inline void locate(const ngl_model& md, const float x[3], int Lp, int* vox, int* cx, int* cy, int* cz) {
+__device__ inline void locate(const ngl_model& md, const float x[3], int Lp, int* vox, int* cx, int* cy, int* cz,
+                              int* vlast, int next = -1, int* vnext = nullptr) {
   const int Dp = Lp + 1;
   if (!in_box(x[0], x[1], x[2])) {
 #pragma unroll
     for (int l = 0; l < MAXL; ++l) vox[l] = -1;
     *cx = *cy = *cz = 0;
+    *vlast = -1;
+    if (vnext) *vnext = -1;
     return;
   }
   const int r = 1 << Dp;
   *cx = cell_of(x[0], r);
   *cy = cell_of(x[1], r);
   *cz = cell_of(x[2], r);
-  descend<MAXL>(md, *cx, *cy, *cz, Dp, vox);
+  descend<MAXL>(md, *cx, *cy, *cz, Dp, vox, vlast, next, vnext);
 }
 
 template <int M, typename FT, bool XYZ>
@@ -37,8 +42,8 @@ __global__ __launch_bounds__(kBlock) void k_query(ngl_model md, const float* __r
   const int Lp = blend ? lod + 1 : lod;
   const float a = alpha_pp ? alpha_pp[p] : alpha;
   int vox[NGL_MAX_LODS];
-  int cx, cy, cz;
-  locate<NGL_MAX_LODS>(md, x, Lp, vox, &cx, &cy, &cz);
+  int cx, cy, cz, vlast, vn;
+  locate<NGL_MAX_LODS>(md, x, Lp, vox, &cx, &cy, &cz, &vlast, lod + 1, &vn);
   float z[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) z[k] = 0.0f;
@@ -50,12 +55,11 @@ __global__ __launch_bounds__(kBlock) void k_query(ngl_model md, const float* __r
   float out = decode_f32<M, XYZ>(md, lod, x, z);
   if (blend) {
     // z_{L+1} = z_L + psi_{L+1}
-    const int vn = pick<NGL_MAX_LODS>(vox, lod);
     if (vn >= 0) interp_level<M, FT>(md, lod + 1, vn, cx, cy, cz, x, z);
     out = (1.0f - a) * out + a * decode_f32<M, XYZ>(md, lod + 1, x, z);
   }
   sdf[p] = out;
-  if (valid) valid[p] = pick<NGL_MAX_LODS>(vox, Lp - 1) >= 0 ? 1 : 0;
+  if (valid) valid[p] = vlast >= 0 ? 1 : 0;
   if (vox_out) {
 #pragma unroll
     for (int l = 1; l <= NGL_MAX_LODS; ++l)
@@ -72,8 +76,8 @@ __global__ __launch_bounds__(kBlock) void k_query_all(ngl_model md, const float*
   const float x[3] = {xs[p], xs[P + p], xs[2 * P + p]};
   const int Lm = md.num_lods;
   int vox[NGL_MAX_LODS];
-  int cx, cy, cz;
-  locate<NGL_MAX_LODS>(md, x, Lm, vox, &cx, &cy, &cz);
+  int cx, cy, cz, vlast;
+  locate<NGL_MAX_LODS>(md, x, Lm, vox, &cx, &cy, &cz, &vlast);
   float z[M];
 #pragma unroll
   for (int k = 0; k < M; ++k) z[k] = 0.0f;
@@ -85,6 +89,103 @@ __global__ __launch_bounds__(kBlock) void k_query_all(ngl_model md, const float*
       sdf_all[int64_t(l - 1) * P + p] = decode_f32<M, XYZ>(md, l, x, z);
     }
   }
+}
+
+// BF16 decoder weights: the same location and gather per lane, then the
+// first decoder layer for the wavefront's 64 points on the matrix cores.
+// Grid-stride over points so each block stages the decoder fragments in
+// LDS once; inside the loop only wavefront-level LDS ordering is needed.
+template <int M, typename FT, bool XYZ, int NW>
+__global__ __launch_bounds__(64 * NW) void k_query_mfma(ngl_model md, const float* __restrict__ xs, int64_t P,
+                                                        int lod, float alpha, const float* __restrict__ alpha_pp,
+                                                        float* __restrict__ sdf, uint8_t* __restrict__ valid,
+                                                        int32_t* __restrict__ vox_out) {
+  using S = MfmaShape<M, XYZ>;
+  extern __shared__ __align__(16) char smem[];
+  const int H = md.hidden;
+  const bool blend = alpha_pp != nullptr || alpha > 0.0f;
+  const int fe = (H / 16) * S::KS * 64;
+  uint4* frag0 = reinterpret_cast<uint4*>(smem);
+  uint4* frag1 = frag0 + fe;
+  float* w2s0 = reinterpret_cast<float*>(frag1 + (blend ? fe : 0));
+  float* w2s1 = w2s0 + H;
+  uint16_t* stage = reinterpret_cast<uint16_t*>(w2s1 + H) + (threadIdx.x >> 6) * 64 * S::ROW;
+  load_frags<M, XYZ>(md, lod, frag0, w2s0);
+  if (blend) load_frags<M, XYZ>(md, lod + 1, frag1, w2s1);
+  __syncthreads();
+  const float b2a = md.b2[lod - 1];
+  const float b2b = blend ? md.b2[lod] : 0.0f;
+  const int Lp = blend ? lod + 1 : lod;
+  for (int64_t base = int64_t(blockIdx.x) * (64 * NW); base < P; base += int64_t(gridDim.x) * (64 * NW)) {
+    const int64_t p = base + threadIdx.x;
+    const bool act = p < P;
+    float x[3] = {0.0f, 0.0f, 0.0f};
+    if (act) {
+      x[0] = xs[p];
+      x[1] = xs[P + p];
+      x[2] = xs[2 * P + p];
+    }
+    int vox[NGL_MAX_LODS];
+    int cx, cy, cz, vlast, vn;
+    locate<NGL_MAX_LODS>(md, x, Lp, vox, &cx, &cy, &cz, &vlast, lod + 1, &vn);
+    if (!act) {
+#pragma unroll
+      for (int l = 0; l < NGL_MAX_LODS; ++l) vox[l] = -1;
+      vlast = vn = -1;
+    }
+    float z[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) z[k] = 0.0f;
+#pragma unroll
+    for (int l = 1; l <= NGL_MAX_LODS; ++l)
+      if (l <= lod && vox[l - 1] >= 0)
+        interp_level<M, FT>(md, l, vox[l - 1], cx >> (Lp - l), cy >> (Lp - l), cz >> (Lp - l), x, z);
+    stage_row<M, XYZ>(stage, x, z);
+    wave_lds_sync();
+    float out = wave_decode<M, XYZ>(frag0, w2s0, b2a, stage, H);
+    if (blend) {
+      if (vn >= 0) interp_level<M, FT>(md, lod + 1, vn, cx, cy, cz, x, z);
+      wave_lds_sync();
+      stage_row<M, XYZ>(stage, x, z);
+      wave_lds_sync();
+      const float a = act ? (alpha_pp ? alpha_pp[p] : alpha) : 0.0f;
+      out = (1.0f - a) * out + a * wave_decode<M, XYZ>(frag1, w2s1, b2b, stage, H);
+    }
+    wave_lds_sync();
+    if (act) {
+      sdf[p] = out;
+      if (valid) valid[p] = vlast >= 0 ? 1 : 0;
+      if (vox_out) {
+#pragma unroll
+        for (int l = 1; l <= NGL_MAX_LODS; ++l)
+          if (l <= Lp) vox_out[int64_t(l - 1) * P + p] = vox[l - 1];
+      }
+    }
+  }
+}
+
+template <int M, typename FT, bool XYZ, int NW>
+static int launch_query_mfma_nw(const ngl_model& md, const float* x, int64_t P, int lod, float alpha,
+                                const float* app, float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s,
+                                size_t lds) {
+  int64_t grid = (P + 64 * NW - 1) / (64 * NW);
+  if (grid > 4096) grid = 4096;
+  k_query_mfma<M, FT, XYZ, NW><<<unsigned(grid), 64 * NW, lds, s>>>(md, x, P, lod, alpha, app, sdf, valid, vox);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+template <int M, typename FT, bool XYZ>
+static int launch_query_mfma(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app,
+                             float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s) {
+  using S = MfmaShape<M, XYZ>;
+  const bool blend = app != nullptr || alpha > 0.0f;
+  const size_t fixed = size_t(S::frag_bytes(md.hidden)) * (blend ? 2 : 1) + 2 * sizeof(float) * md.hidden;
+  if (fixed + 4 * S::STAGE_BYTES <= 65536)
+    return launch_query_mfma_nw<M, FT, XYZ, 4>(md, x, P, lod, alpha, app, sdf, valid, vox, s, fixed + 4 * S::STAGE_BYTES);
+  if (fixed + 2 * S::STAGE_BYTES <= 65536)
+    return launch_query_mfma_nw<M, FT, XYZ, 2>(md, x, P, lod, alpha, app, sdf, valid, vox, s, fixed + 2 * S::STAGE_BYTES);
+  return launch_query_mfma_nw<M, FT, XYZ, 1>(md, x, P, lod, alpha, app, sdf, valid, vox, s, fixed + S::STAGE_BYTES);
 }
 
 template <int M, typename FT, bool XYZ>
@@ -130,6 +231,7 @@ template <int M, typename FT, bool XYZ>
 struct QueryOp {
   static int run(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app, float* sdf,
                  uint8_t* valid, int32_t* vox, hipStream_t s) {
+    if (md.w_dtype == NGL_BF16) return launch_query_mfma<M, FT, XYZ>(md, x, P, lod, alpha, app, sdf, valid, vox, s);
     return launch_query<M, FT, XYZ>(md, x, P, lod, alpha, app, sdf, valid, vox, s);
   }
 };
@@ -155,7 +257,6 @@ int ngl_query_sdf(const ngl_model* m, const float* x, int64_t P, int32_t lod, fl
   NGL_REQUIRE(!(alpha > 0.0f || alpha_pp) || lod < m->num_lods, "blending needs lod < num_lods");
   if (P == 0) return NGL_OK;
   NGL_REQUIRE(x && sdf, "x or sdf is null");
-  if (m->w_dtype != NGL_F32) NGL_FAIL(NGL_E_UNSUPPORTED, "BF16 decoder weights are not supported by this call yet");
   return ngl::dispatch<ngl::QueryOp>(*m, x, P, int(lod), alpha, alpha_pp, sdf, valid, vox_out,
                                      (hipStream_t)stream);
 }
@@ -166,7 +267,7 @@ int ngl_query_sdf_all_lods(const ngl_model* m, const float* x, int64_t P, float*
   NGL_REQUIRE(P >= 0, "negative point count");
   if (P == 0) return NGL_OK;
   NGL_REQUIRE(x && sdf_all, "x or sdf_all is null");
-  if (m->w_dtype != NGL_F32) NGL_FAIL(NGL_E_UNSUPPORTED, "BF16 decoder weights are not supported by this call yet");
+  if (m->w_dtype != NGL_F32) NGL_FAIL(NGL_E_UNSUPPORTED, "all-LOD queries need FP32 decoder weights");
   return ngl::dispatch<ngl::QueryAllOp>(*m, x, P, sdf_all, (hipStream_t)stream);
 }
 

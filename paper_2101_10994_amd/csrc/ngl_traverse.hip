@@ -2,10 +2,10 @@
 // Alg. 1; subroutines of App. C) on gfx950.
 //
 // Per depth, three launches over the current list of ray-voxel pairs:
-//   k_decide_count  Decide (FP32 slab test + NumChildren) and a per-block sum
+//   k_decide_count  Decide (FP32 slab tests) and a per-block sum
 //   k_scan_blocks   exclusive sum of the block sums (one block), list size
-//   k_decide_emit   Decide again, block-level exclusive scan, then Subdivide
-//                   (children in front-to-back order) or Compactify
+//   k_decide_emit   block-level exclusive scan of the decisions, then
+//                   Subdivide (children front to back) or Compactify
 // so the global ExclusiveSum is reduce-then-scan with the block partition
 // fixed by (list size, grid).  Lists live in caller workspace, sizes stay
 // on the device: no host synchronisation between depths.
@@ -52,15 +52,22 @@ __global__ __launch_bounds__(kBlock) void k_ray_inv(const float* __restrict__ d,
 // ---------------------------------------------------------------------------
 // Traversal
 // ---------------------------------------------------------------------------
+// Lists hold only pairs whose box the ray hits.  The root pass decides the
+// root for every ray; the pass from depth d decides every occupied child of
+// each hit pair (the Decide of depth d+1, evaluated while subdividing), so
+// D = number of hit children, and Subdivide writes exactly those children
+// front to back at the exclusive-sum offset.  The final list equals the one
+// produced by deciding all occupied children at the next depth first.
 struct Level {
-  const float* o;        // [3][R]
-  const float* inv;      // [3][R]
+  const float* o;         // [3][R]
+  const float* inv;       // [3][R]
   int64_t R;
-  const int32_t* ray_in;  // null at depth 0: the list is (i, root) for all rays
+  const int32_t* ray_in;  // hit pairs at `depth` (unused by the root pass)
   const int32_t* vox_in;
-  const int64_t* n_in;    // device list size (null at depth 0: R)
-  int depth;
-  int target;
+  const int64_t* n_in;    // device list size
+  uint8_t* hmask;         // [cap] hit-children mask per input pair (child passes)
+  int depth;              // depth of the input list (root pass: 0)
+  bool final_out;         // the produced list is at the target depth
   int64_t cap;
   uint32_t* bsum;         // [kTravGrid] block sums, then exclusive offsets
   int64_t* n_out;         // device size of the produced list
@@ -71,12 +78,6 @@ struct Level {
   float* tout_out;
 };
 
-__device__ inline int64_t list_size(const Level& L) {
-  if (!L.n_in) return L.R;
-  const int64_t n = *L.n_in;
-  return n < L.cap ? n : L.cap;
-}
-
 // Contiguous chunk of the list owned by block b (multiple of the block size).
 __device__ inline void chunk_of(int64_t n, int64_t& begin, int64_t& end) {
   int64_t chunk = (n + kTravGrid - 1) / kTravGrid;
@@ -85,30 +86,41 @@ __device__ inline void chunk_of(int64_t n, int64_t& begin, int64_t& end) {
   end = begin + chunk < n ? begin + chunk : n;
 }
 
-struct Pair {
-  int32_t ray, vox;
-  uint32_t mask;  // child mask (0 at the target depth)
-  float tin, tout;
-  float o[3];
-};
-
-// Decide (App. C): D = hit ? (depth == target ? 1 : NumChildren) : 0.
-__device__ inline uint32_t decide(const ngl_model& md, const Level& L, int64_t t, Pair& pr) {
-  pr.ray = L.ray_in ? L.ray_in[t] : int32_t(t);
-  pr.vox = L.ray_in ? L.vox_in[t] : 0;
-  float inv[3], lo[3], hi[3];
+__device__ inline void load_ray(const Level& L, int32_t ray, float o[3], float inv[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    pr.o[a] = L.o[a * L.R + pr.ray];
-    inv[a] = L.inv[a * L.R + pr.ray];
+    o[a] = L.o[a * L.R + ray];
+    inv[a] = L.inv[a * L.R + ray];
   }
-  box_of(md.cell[L.depth][pr.vox], L.depth, lo, hi);
-  const bool hit = slab_f32(pr.o, inv, lo, hi, pr.tin, pr.tout);
-  pr.mask = 0;
-  if (!hit) return 0;
-  if (L.depth == L.target) return 1;
-  pr.mask = md.child_mask[L.depth][pr.vox];
-  return uint32_t(__popc(pr.mask));
+}
+
+// Decide for the root: 1 if the ray hits [-1,1]^3.
+__device__ inline uint32_t decide_root(const Level& L, int64_t t, float& tin, float& tout) {
+  float o[3], inv[3], lo[3], hi[3];
+  load_ray(L, int32_t(t), o, inv);
+  box_of(0u, 0, lo, hi);
+  return slab_f32(o, inv, lo, hi, tin, tout) ? 1u : 0u;
+}
+
+// Decide for the occupied children of hit pair (ray, vox) at depth d: bit c
+// of the result is set iff child c exists and the ray hits its box.
+__device__ inline uint32_t decide_children(const ngl_model& md, int d, const float o[3], const float inv[3],
+                                           int32_t vox, uint32_t* cmask, int32_t* fc) {
+  const uint32_t c = md.cell[d][vox];
+  const uint32_t m = md.child_mask[d][vox];
+  *cmask = m;
+  *fc = md.first_child[d][vox];
+  uint32_t hm = 0;
+  const int base[3] = {2 * cell_x(c), 2 * cell_y(c), 2 * cell_z(c)};
+#pragma unroll
+  for (int ch = 0; ch < 8; ++ch) {
+    if (m >> ch & 1u) {
+      float lo[3], hi[3], ti, to;
+      box_of(pack_cell(base[0] + (ch & 1), base[1] + (ch >> 1 & 1), base[2] + (ch >> 2 & 1)), d + 1, lo, hi);
+      if (slab_f32(o, inv, lo, hi, ti, to)) hm |= 1u << ch;
+    }
+  }
+  return hm;
 }
 
 __device__ inline uint32_t wave_incl_scan(uint32_t x) {
@@ -121,13 +133,32 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
+__device__ inline int64_t list_size(const Level& L, bool root) {
+  if (root) return L.R;
+  const int64_t n = *L.n_in;
+  return n < L.cap ? n : L.cap;
+}
+
+template <bool ROOT>
 __global__ __launch_bounds__(kBlock) void k_decide_count(ngl_model md, Level L) {
-  const int64_t n = list_size(L);
+  const int64_t n = list_size(L, ROOT);
   int64_t begin, end;
   chunk_of(n, begin, end);
   uint32_t local = 0;
-  Pair pr;
-  for (int64_t t = begin + threadIdx.x; t < end; t += kBlock) local += decide(md, L, t, pr);
+  for (int64_t t = begin + threadIdx.x; t < end; t += kBlock) {
+    if constexpr (ROOT) {
+      float ti, to;
+      local += decide_root(L, t, ti, to);
+    } else {
+      float o[3], inv[3];
+      load_ray(L, L.ray_in[t], o, inv);
+      uint32_t cm;
+      int32_t fc;
+      const uint32_t hm = decide_children(md, L.depth, o, inv, L.vox_in[t], &cm, &fc);
+      L.hmask[t] = uint8_t(hm);
+      local += uint32_t(__popc(hm));
+    }
+  }
   __shared__ uint32_t part[kBlock / 64];
   const uint32_t w = wave_incl_scan(local);
   if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = w;
@@ -151,7 +182,6 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(Level L) {
     v[k] = L.bsum[threadIdx.x * PER + k];
     local += v[k];
   }
-  // inclusive scan of `local` across the block
   uint64_t x = local;
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -179,12 +209,13 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(Level L) {
   if (threadIdx.x == 0) {
     *L.n_out = int64_t(total);
     if (int64_t(total) > L.counts[1]) L.counts[1] = int64_t(total);
-    if (L.depth == L.target) L.counts[0] = int64_t(total);
+    if (L.final_out) L.counts[0] = int64_t(total);
   }
 }
 
+template <bool ROOT>
 __global__ __launch_bounds__(kBlock) void k_decide_emit(ngl_model md, Level L) {
-  const int64_t n = list_size(L);
+  const int64_t n = list_size(L, ROOT);
   int64_t begin, end;
   chunk_of(n, begin, end);
   int64_t offset = L.bsum[blockIdx.x];
@@ -192,8 +223,16 @@ __global__ __launch_bounds__(kBlock) void k_decide_emit(ngl_model md, Level L) {
   const int64_t cap = L.cap;
   for (int64_t base = begin; base < end; base += kBlock) {
     const int64_t t = base + threadIdx.x;
-    Pair pr;
-    const uint32_t D = t < end ? decide(md, L, t, pr) : 0;
+    uint32_t D = 0, hm = 0;
+    float ti = 0.0f, to = 0.0f;
+    if (t < end) {
+      if constexpr (ROOT) {
+        D = decide_root(L, t, ti, to);
+      } else {
+        hm = L.hmask[t];
+        D = uint32_t(__popc(hm));
+      }
+    }
     const uint32_t incl = wave_incl_scan(D);
     if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = incl;
     __syncthreads();
@@ -207,33 +246,49 @@ __global__ __launch_bounds__(kBlock) void k_decide_emit(ngl_model md, Level L) {
     __syncthreads();
     if (D) {
       int64_t k = offset + pre + incl - D;
-      if (L.depth == L.target) {
-        // Compactify: keep the hit pair at its exclusive-sum slot
+      if constexpr (ROOT) {
+        // Compactify (root pass): keep the rays that hit the root
         if (k < cap) {
-          L.ray_out[k] = pr.ray;
-          L.vox_out[k] = pr.vox;
-          L.tin_out[k] = pr.tin;
-          L.tout_out[k] = pr.tout;
+          L.ray_out[k] = int32_t(t);
+          L.vox_out[k] = 0;
+          if (L.final_out) {
+            L.tin_out[k] = ti;
+            L.tout_out[k] = to;
+          }
         }
       } else {
-        // Subdivide: occupied children front to back, child = k XOR oct
-        const uint32_t c = md.cell[L.depth][pr.vox];
-        const float step = 2.0f / float(1 << L.depth);
+        // Subdivide: hit children front to back, child = q XOR oct
+        const int32_t ray = L.ray_in[t];
+        const int32_t vox = L.vox_in[t];
+        float o[3], inv[3];
+        load_ray(L, ray, o, inv);
+        const int d = L.depth;
+        const uint32_t c = md.cell[d][vox];
+        const uint32_t m = md.child_mask[d][vox];
+        const int32_t fc = md.first_child[d][vox];
+        const float step = 2.0f / float(1 << d);
         const int ijk[3] = {cell_x(c), cell_y(c), cell_z(c)};
         int oct = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const float centre = -1.0f + (float(ijk[a]) + 0.5f) * step;  // exact dyadic
-          oct |= (pr.o[a] > centre ? 1 : 0) << a;
+          oct |= (o[a] > centre ? 1 : 0) << a;
         }
-        const int32_t fc = md.first_child[L.depth][pr.vox];
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const int ch = q ^ oct;
-          if (pr.mask >> ch & 1u) {
+          if (hm >> ch & 1u) {
             if (k < cap) {
-              L.ray_out[k] = pr.ray;
-              L.vox_out[k] = fc + __popc(pr.mask & ((1u << ch) - 1u));
+              L.ray_out[k] = ray;
+              L.vox_out[k] = fc + __popc(m & ((1u << ch) - 1u));
+              if (L.final_out) {
+                float lo[3], hi[3], a0, a1;
+                box_of(pack_cell(2 * ijk[0] + (ch & 1), 2 * ijk[1] + (ch >> 1 & 1), 2 * ijk[2] + (ch >> 2 & 1)), d + 1,
+                       lo, hi);
+                slab_f32(o, inv, lo, hi, a0, a1);
+                L.tin_out[k] = a0;
+                L.tout_out[k] = a1;
+              }
             }
             ++k;
           }
@@ -278,6 +333,7 @@ struct TravWS {
   float* inv;
   int32_t* ray[2];
   int32_t* vox[2];
+  uint8_t* hmask;
   uint32_t* bsum;
   int64_t* nlev;
   size_t bytes;
@@ -297,6 +353,7 @@ static TravWS carve(void* base, int64_t R, int64_t cap) {
     w.ray[k] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * size_t(cap)));
     w.vox[k] = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * size_t(cap)));
   }
+  w.hmask = reinterpret_cast<uint8_t*>(take(size_t(cap)));
   w.bsum = reinterpret_cast<uint32_t*>(take(sizeof(uint32_t) * kTravGrid));
   w.nlev = reinterpret_cast<int64_t*>(take(sizeof(int64_t) * (NGL_MAX_DEPTH + 1)));
   w.bytes = off;
@@ -372,34 +429,44 @@ int ngl_trace_octree(const ngl_model* m, const float* o, const float* d, int64_t
   }
   const unsigned rgrid = unsigned((R + kBlock - 1) / kBlock);
   k_ray_inv<<<rgrid, kBlock, 0, s>>>(d, R, w.inv);
-  for (int depth = 0; depth <= target_depth; ++depth) {
+  // root pass, then one pass per depth d = 0..target-1 producing depth d+1
+  for (int step = -1; step < target_depth; ++step) {
+    const bool root = step < 0;
+    const int out_depth = root ? 0 : step + 1;
     Level L{};
     L.o = o;
     L.inv = w.inv;
     L.R = R;
-    if (depth > 0) {
-      L.ray_in = w.ray[depth & 1];
-      L.vox_in = w.vox[depth & 1];
-      L.n_in = w.nlev + depth;
+    if (!root) {
+      L.ray_in = w.ray[step & 1];
+      L.vox_in = w.vox[step & 1];
+      L.n_in = w.nlev + step;
+      L.depth = step;
     }
-    L.depth = depth;
-    L.target = target_depth;
+    L.hmask = w.hmask;
+    L.final_out = out_depth == target_depth;
     L.cap = pair_capacity;
     L.bsum = w.bsum;
-    L.n_out = w.nlev + depth + 1;
+    L.n_out = w.nlev + out_depth;
     L.counts = counts;
-    if (depth == target_depth) {
+    if (L.final_out) {
       L.ray_out = pair_ray;
       L.vox_out = pair_vox;
       L.tin_out = t_in;
       L.tout_out = t_out;
     } else {
-      L.ray_out = w.ray[(depth + 1) & 1];
-      L.vox_out = w.vox[(depth + 1) & 1];
+      L.ray_out = w.ray[out_depth & 1];
+      L.vox_out = w.vox[out_depth & 1];
     }
-    k_decide_count<<<kTravGrid, kBlock, 0, s>>>(*m, L);
-    k_scan_blocks<<<1, 1024, 0, s>>>(L);
-    k_decide_emit<<<kTravGrid, kBlock, 0, s>>>(*m, L);
+    if (root) {
+      k_decide_count<true><<<kTravGrid, kBlock, 0, s>>>(*m, L);
+      k_scan_blocks<<<1, 1024, 0, s>>>(L);
+      k_decide_emit<true><<<kTravGrid, kBlock, 0, s>>>(*m, L);
+    } else {
+      k_decide_count<false><<<kTravGrid, kBlock, 0, s>>>(*m, L);
+      k_scan_blocks<<<1, 1024, 0, s>>>(L);
+      k_decide_emit<false><<<kTravGrid, kBlock, 0, s>>>(*m, L);
+    }
   }
   k_ray_offsets<<<unsigned((R + 1 + kBlock - 1) / kBlock), kBlock, 0, s>>>(pair_ray, counts, pair_capacity, R,
                                                                             ray_off);

@@ -70,7 +70,8 @@ EXPORTS = {
     "ngl_camera_rays": (C.c_int, [P, P, P, C.c_float, i32, i32, P, P, P]),
     "ngl_trace_octree_workspace": (C.c_int, [i64, i64, P]),
     "ngl_trace_octree": (C.c_int, [P, P, P, i64, i32, i64, P, C.c_size_t, P, P, P, P, P, P, P]),
-    "ngl_sphere_trace": (C.c_int, [P, P, P, i64, i32, C.c_float, P, P, P, P, P, P, P, P, P, P]),
+    "ngl_sphere_trace": (C.c_int, [P, P, P, i64, i32, C.c_float, P, P, P, P, P, P, P, P, P, P, C.c_size_t, P]),
+    "ngl_sphere_trace_workspace": (C.c_int, [P]),
     "ngl_train_workspace": (C.c_int, [P, i64, P]),
     "ngl_backward_all_lods": (C.c_int, [P, P, i64, P, P, P, P, P, P, P, C.c_size_t, P]),
     "ngl_train_fwd_bwd": (C.c_int, [P, P, P, i64, P, P, P, P, P, P, P, P, C.c_size_t, P]),
@@ -381,10 +382,14 @@ def sphere_trace(model: Model, o, d, lod: int, alpha: float, hits: dict, max_ste
                    steps=torch.empty(R, dtype=torch.int32, device=dev),
                    hit_vox=torch.empty(R, dtype=torch.int32, device=dev))
     prm = trace_params(max_steps, delta, t_far, osc_check, analytic_sphere)
+    if "ws" not in out:
+        nb = C.c_size_t()
+        _check(lib().ngl_sphere_trace_workspace(C.addressof(nb)))
+        out["ws"] = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
     _check(lib().ngl_sphere_trace(model.ref, _ptr(o), _ptr(d), R, int(lod), float(alpha), _ptr(hits["vox"]),
                                   _ptr(hits["t_in"]), _ptr(hits["t_out"]), _ptr(hits["ray_off"]), C.addressof(prm),
                                   _ptr(out["t"]), _ptr(out["status"]), _ptr(out["steps"]), _ptr(out["hit_vox"]),
-                                  _stream()))
+                                  _ptr(out["ws"]), out["ws"].numel(), _stream()))
     return out
 
 

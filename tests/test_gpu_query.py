@@ -7,7 +7,7 @@ import pytest
 import oracle
 from paper_2101_10994_amd import workloads as W
 
-from cases import edge_points, paper_case, tiny_case
+from cases import edge_points, make_case, paper_case, tiny_case
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -24,14 +24,14 @@ def run_both(case, x, lod, alpha=0.0, alpha_pp=None):
     return {k: v.cpu().numpy() for k, v in g.items()}, o
 
 
-def check(g, o, tol=TOL):
+def check(g, o, tol=TOL, scale="scale"):
     assert np.array_equal(g["vox"], o["vox"])
     assert np.array_equal(g["valid"], o["valid"])
     err = np.abs(g["sdf"].astype(np.float64) - o["sdf"])
-    bound = tol * o["scale"]
+    bound = tol * o[scale]
     bad = np.nonzero(err > bound)[0]
     assert bad.size == 0, (bad[:10], err[bad[:10]], bound[bad[:10]])
-    return float((err / np.maximum(o["scale"], 1e-30)).max())
+    return float((err / np.maximum(o[scale], 1e-30)).max())
 
 
 @pytest.mark.parametrize("lod", [1, 2, 3])
@@ -121,3 +121,69 @@ def test_empty_and_edge_sizes():
         ngl.query_sdf(gm, torch.zeros((3, 4), dtype=torch.float32, device="cuda"), 4)
     with pytest.raises(ngl.NGLError):
         ngl.query_sdf(gm, torch.zeros((3, 4), dtype=torch.float32, device="cuda"), 3, alpha=0.5)
+
+
+# ---------------------------------------------------------------------------
+# BF16 decoder on the matrix cores (FP32 accumulation), FP16/BF16/FP32 features.
+# Bar: |d - oracle| <= 2e-3 s1, the oracle evaluated in FP64 on the same stored
+# (rounded) parameters.  The residual error is the BF16 rounding of the first
+# layer's inputs z (relative 2^-9), which moves each pre-activation by at most
+# 2^-9 sum_i |W1_ki z_i|; s1 = |b2| + sum_k |w2_k| (|b1_k| + sum_i |W1_ki in_i|)
+# is that magnitude, so 2e-3 s1 bounds it.
+# ---------------------------------------------------------------------------
+TOL16 = 2e-3
+
+
+@pytest.mark.parametrize("fdt", ["f32", "f16", "bf16"])
+def test_bf16_decoder_tiny(fdt):
+    case = tiny_case(sigma=0.2, feat_dtype=fdt, w_dtype="bf16")
+    rng = np.random.default_rng(21)
+    x = edge_points(case.ijk, 16, 3, rng)
+    worst = 0.0
+    for lod in (1, 2, 3):
+        g, o = run_both(case, x, lod)
+        worst = max(worst, check(g, o, TOL16, "scale1"))
+    app = rng.uniform(0, 1, size=x.shape[1]).astype(np.float32)
+    g, o = run_both(case, x, 2, alpha_pp=app)
+    worst = max(worst, check(g, o, TOL16, "scale1"))
+    g, o = run_both(case, x, 1, alpha=0.3)
+    worst = max(worst, check(g, o, TOL16, "scale1"))
+    print("bf16 decoder (%s features): worst |err|/s = %.2e" % (fdt, worst))
+
+
+@pytest.mark.parametrize("m,H,xyz", [(8, 16, False), (16, 64, True), (64, 32, True)])
+def test_bf16_decoder_shapes(m, H, xyz):
+    case = make_case(W.tiny_shape(), 16, 3, m, H, sigma=0.2, with_xyz=xyz, feat_dtype="f16", w_dtype="bf16")
+    x = edge_points(case.ijk, 16, 3, np.random.default_rng(m + H))
+    g, o = run_both(case, x, 3)
+    check(g, o, TOL16, "scale1")
+
+
+def test_precision_config_sampled():
+    """7 LODs (resolutions 4..256) over 32 spheres + 4 tori, FP16 features and
+    BF16 decoders; 2^22 queries at continuous LOD 5 + alpha, alpha ~ U[0,1] per
+    query, on the GPU; the oracle checks a 32,768-point sample and the error
+    is reported per discrete LOD."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    case = make_case(W.prec_shape(0), 256, 7, 32, 128, feat_dtype="f16", w_dtype="bf16")
+    rng = np.random.default_rng(5)
+    x = W.soa(W.paper_queries(0, case.shape, 1 << 22))
+    app = rng.uniform(0, 1, size=x.shape[1]).astype(np.float32)
+    gm = case.gpu_model()
+    g = ngl.query_sdf(gm, torch.from_numpy(x).cuda(), 5, alpha_pp=torch.from_numpy(app).cuda(), want_valid=True,
+                      want_vox=True)
+    g = {k: v.cpu().numpy() for k, v in g.items()}
+    idx = np.random.default_rng(2).choice(x.shape[1], 32768, replace=False)
+    xs = np.ascontiguousarray(x[:, idx])
+    o = oracle.query(case.otree, case.oracle_model(), xs, 5, alpha_pp=app[idx], want_vox=True)
+    check({"vox": g["vox"][:, idx], "valid": g["valid"][idx], "sdf": g["sdf"][idx]}, o, TOL16, "scale1")
+    om = case.oracle_model()
+    for lod in range(1, 8):
+        gl = ngl.query_sdf(gm, torch.from_numpy(xs).cuda(), lod)["sdf"].cpu().numpy()
+        ol = oracle.query(case.otree, om, xs, lod)
+        rel = np.abs(gl - ol["sdf"]) / ol["scale1"]
+        assert rel.max() <= TOL16, (lod, rel.max())
+        print("precision config LOD %d: max |err|/s1 %.2e, median %.2e, max |err| %.2e, max |err|/s %.2e"
+              % (lod, rel.max(), np.median(rel), np.abs(gl - ol["sdf"]).max(),
+                 (np.abs(gl - ol["sdf"]) / ol["scale"]).max()))

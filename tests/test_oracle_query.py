@@ -196,3 +196,18 @@ def test_blend_alpha():
     np.testing.assert_allclose(dp, (1 - app.astype(np.float64)) * d1 + app * d2, rtol=0, atol=1e-14)
     with pytest.raises(ValueError):
         oracle.query(t, mdl, x, lod=3, alpha=0.5)
+
+
+def test_error_scales_bound_the_result():
+    """The tolerance scales satisfy |sdf| <= scale <= scale1 (triangle
+    inequality and |ReLU(a)| <= sum of |terms of a|)."""
+    ijk, t = tiny_tree()
+    rng = np.random.default_rng(8)
+    feats = [rng.normal(0, 0.3, size=(int(n), 8)) for n in t.ncorner]
+    d = W.decoders(rng, 3, 11, 32)
+    mdl = oracle.Model(feats, list(d["W1"]), list(d["b1"]), list(d["w2"]), d["b2"])
+    x = W.soa(np.concatenate([W.points_in_cells(rng, ijk, 16, 500), rng.uniform(-1, 1, (100, 3))]))
+    for lod, a in ((1, 0.0), (3, 0.0), (2, 0.4)):
+        o = oracle.query(t, mdl, x, lod, alpha=a)
+        assert np.all(np.abs(o["sdf"]) <= o["scale"] * (1 + 1e-12))
+        assert np.all(o["scale"] <= o["scale1"] * (1 + 1e-12))
