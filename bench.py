@@ -137,6 +137,14 @@ def main():
     do_f = args.only in (None, "frame")
     do_t = args.only in (None, "train") and have_train
     do_h = args.only in (None, "half")
+    do_v = args.only is None
+    f32_mode = ngl.get_option(ngl.OPT_F32_DECODER)
+    tvq, tvs = Timer(), Timer()
+    sdf_v = torch.empty(cfg.n_query, dtype=torch.float32, device=dev)
+    tr_v = dict(t=torch.empty(R, dtype=torch.float32, device=dev),
+                status=torch.empty(R, dtype=torch.uint8, device=dev),
+                steps=torch.empty(R, dtype=torch.int32, device=dev),
+                hit_vox=torch.empty(R, dtype=torch.int32, device=dev))
     tq, tc, tt, ts, ttr = Timer(), Timer(), Timer(), Timer(), Timer()
     thq, ths = Timer(), Timer()
     half = S["half"]
@@ -165,6 +173,18 @@ def main():
                 ngl.camera_rays(eye, (0, 0, 0), (0, 1, 0), 45.0, W_, H_, out=(o, d))
                 ngl.trace_octree_into(model, o, d, lod + 1, buf)
                 ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr)
+        if do_v:
+            # FP32 decoder on the vector ALUs (the per-lane form), for comparison
+            ngl.set_option(ngl.OPT_F32_DECODER, 0)
+            if timed:
+                with tvq:
+                    ngl.query_sdf(model, S["xq"], lod, out=sdf_v)
+                with tvs:
+                    ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_v)
+            else:
+                ngl.query_sdf(model, S["xq"], lod, out=sdf_v)
+                ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_v)
+            ngl.set_option(ngl.OPT_F32_DECODER, f32_mode)
         if do_h:
             # BF16-MFMA form: same queries; the trace reuses the frame's hit lists
             if not do_f:
@@ -229,6 +249,10 @@ def main():
                              "frame_ms": (mean(tc) + mean(tt) + hs_ms) if do_f else None}
         if do_q:
             comp["bf16_form"]["max_abs_diff_vs_fp32"] = float((sdf_h - sdf).abs().max())
+    if do_v:
+        comp["fp32_valu_form"] = {"decoder": "fp32 per lane on the vector ALUs", "query_ms": mean(tvq),
+                                  "queries_per_s": cfg.n_query / (mean(tvq) * 1e-3), "trace_ms": mean(tvs),
+                                  "max_abs_diff_vs_mfma": float((sdf_v - sdf).abs().max())}
     if do_t:
         tr_ms = mean(ttr)
         comp["train"] = {"ms": tr_ms, "points_per_s": S["xt"].shape[1] / (tr_ms * 1e-3), "points": S["xt"].shape[1]}
@@ -261,6 +285,7 @@ def main():
     out = {"metric": METRIC, "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "f32_decoder": ["vector ALU", "matrix cores (v_mfma_f32_16x16x4f32)"][f32_mode],
            "config": {"workload": "union8s1t-5lod-m32: 2^20 queries at LOD 5 + 1024x1024 frame "
                                   "(<=100 steps, delta 1e-4)" + (" + 2^19-point train step" if do_t else ""),
                       "lods": cfg.num_lods, "feat_dim": cfg.feat_dim, "hidden": cfg.hidden,

@@ -71,6 +71,26 @@ const char* ngl_status_str(int status);
 const char* ngl_last_error(void);
 int ngl_version(void);
 
+/* Process-wide implementation choices (they never change results beyond
+ * the stated tolerances; the autotuner sets them).
+ *  NGL_OPT_F32_DECODER: how the decoder's first layer runs for FP32
+ *    weights: 0 = per lane on the vector ALUs with weights read through the
+ *    scalar cache, 1 = on the matrix cores (v_mfma_f32_16x16x4f32, FP32
+ *    operands and accumulation; default).
+ *  NGL_OPT_TRACE_WAVES: wavefronts per block of the matrix-core tracers
+ *    (1, 2 or 4; 0 = the most that fit in 64 KB of LDS, default).
+ *  NGL_OPT_TRACE_BLOCKS_PER_CU: cap on resident tracer blocks per compute
+ *    unit (0 = occupancy limit, default).
+ * NGL_E_INVALID for an unknown option or value. */
+typedef enum {
+  NGL_OPT_F32_DECODER = 0,
+  NGL_OPT_TRACE_WAVES = 1,
+  NGL_OPT_TRACE_BLOCKS_PER_CU = 2,
+  NGL_OPT_COUNT = 3
+} ngl_option;
+int ngl_set_option(int option, int value);
+int ngl_get_option(int option, int* value);
+
 /* ------------------------------------------------------------------ */
 /* 1. Octree from occupancy (Sec. 3.2: a voxel exists only where there   */
 /*    is surface; Sec. 3.4: parents always exist, and the voxel-to-corner */
@@ -237,6 +257,51 @@ int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t
  * cleared by the call itself).  Calls that share a workspace must not run
  * concurrently. */
 int ngl_sphere_trace_workspace(size_t* bytes);
+
+/* ------------------------------------------------------------------ */
+/* 3b. Batched rendering of several models (each its own octree, camera   */
+/*     and LOD) with one persistent sphere-tracing launch.                */
+/* ------------------------------------------------------------------ */
+#define NGL_MAX_BATCH 32
+
+typedef struct {
+  float eye[3], target[3], up[3];  /* camera as in ngl_camera_rays */
+  float fov_y_deg;
+  int32_t width, height;
+  int32_t lod;                     /* LOD traced (1..num_lods of the view's model) */
+  float alpha;                     /* continuous LOD lod + alpha, in [0,1) */
+} ngl_view;
+
+/* Device copy of up to NGL_MAX_BATCH model views for the batched tracer.
+ * ngl_model_table_upload copies the host array into `table` (device, at
+ * least ngl_model_table_bytes bytes) and synchronises `stream`, so the host
+ * array may be released on return.  Re-upload when a model changes. */
+int ngl_model_table_bytes(int32_t n, size_t* bytes);
+int ngl_model_table_upload(const ngl_model* models, int32_t n, void* table, void* stream);
+
+/* Workspace bytes of ngl_render_batch for these views and a per-view pair
+ * capacity (see ngl_trace_octree). */
+int ngl_render_batch_workspace(const ngl_view* views, int32_t n, int64_t pair_capacity, size_t* bytes);
+
+/* Renders view i of model i (i < n <= NGL_MAX_BATCH): camera rays, the
+ * ray-octree intersection at the depth of LOD lod (lod+1 if alpha > 0),
+ * then ONE persistent sphere-trace launch for all views: each block takes
+ * a view, stages that model's decoder in LDS and serves the view's ray
+ * queue with lane refill (every step runs on compacted active rays), then
+ * moves on to views with work left.  All models must share feat_dim,
+ * hidden, with_xyz, feat_dtype and w_dtype.  models: host array (checked);
+ * table: its device copy from ngl_model_table_upload.  Outputs (device)
+ * concatenate the views in order, view i owning width*height entries:
+ * t_hit, status, steps, hit_vox as in ngl_sphere_trace.  counts (device
+ * int64 [n][2]) as in ngl_trace_octree per view; if any counts[i][1] >
+ * pair_capacity the render is incomplete (retry with a larger capacity).
+ * frame_clock (device uint64 [n+1], nullable): [0] a device wall-clock
+ * timestamp (100 MHz) taken when the batch starts, [i+1] when view i's last
+ * ray ends.  No host synchronisation; safe to capture in a graph. */
+int ngl_render_batch(const ngl_model* models, const void* table, const ngl_view* views, int32_t n,
+                     const ngl_trace_params* params, int64_t pair_capacity, void* ws, size_t ws_bytes,
+                     float* t_hit, uint8_t* status, int32_t* steps, int32_t* hit_vox, int64_t* counts,
+                     uint64_t* frame_clock, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* 4. Training (Sec. 3.3, Eq. 4)                                        */

@@ -1,9 +1,16 @@
 // Status strings, thread-local error text and model validation for the C ABI.
 #include "ngl_common.h"
 
+#include <atomic>
+
 namespace ngl {
 
 static thread_local std::string g_last_error;
+
+// Library options; defaults are the fastest measured choices.
+static std::atomic<int> g_options[NGL_OPT_COUNT] = {{1}, {0}, {0}};
+
+int option(int key) { return (key >= 0 && key < NGL_OPT_COUNT) ? g_options[key].load() : 0; }
 
 void set_error(const char* fmt, ...) {
   char buf[1024];
@@ -65,5 +72,21 @@ const char* ngl_status_str(int s) {
 const char* ngl_last_error(void) { return ngl::g_last_error.c_str(); }
 
 int ngl_version(void) { return 1; }
+
+int ngl_set_option(int key, int value) {
+  NGL_REQUIRE(key >= 0 && key < NGL_OPT_COUNT, "unknown option %d", key);
+  if (key == NGL_OPT_F32_DECODER) NGL_REQUIRE(value == 0 || value == 1, "NGL_OPT_F32_DECODER takes 0 or 1");
+  if (key == NGL_OPT_TRACE_WAVES)
+    NGL_REQUIRE(value == 0 || value == 1 || value == 2 || value == 4, "NGL_OPT_TRACE_WAVES takes 0, 1, 2 or 4");
+  if (key == NGL_OPT_TRACE_BLOCKS_PER_CU) NGL_REQUIRE(value >= 0 && value <= 64, "NGL_OPT_TRACE_BLOCKS_PER_CU takes 0..64");
+  ngl::g_options[key].store(value);
+  return NGL_OK;
+}
+
+int ngl_get_option(int key, int* value) {
+  NGL_REQUIRE(key >= 0 && key < NGL_OPT_COUNT && value != nullptr, "unknown option %d or null value", key);
+  *value = ngl::g_options[key].load();
+  return NGL_OK;
+}
 
 }  // extern "C"

@@ -40,6 +40,9 @@ void set_error(const char* fmt, ...);
       NGL_FAIL(NGL_E_HIP, "kernel launch failed: %s", hipGetErrorString(e_));  \
   } while (0)
 
+// Current value of a library option (ngl_set_option).
+int option(int key);
+
 // Checks the structural fields of a model view used by every device call.
 int check_model(const ngl_model* m, bool need_features);
 

@@ -2,10 +2,12 @@
 //
 // The 64 lanes of a wavefront each hold one point: its position x and its
 // summed feature z (FP32, Eq. 2).  The decoder's first layer for all 64 points
-// is a [h x K] x [K x 64] product evaluated as 16x16 tiles with
-// v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32 accumulation); ReLU, the
-// second layer (a dot product with w2) and the cross-lane reduction follow in
-// FP32.  Operand layouts (verified on gfx950):
+// is a [h x K] x [K x 64] product evaluated as 16x16 tiles on the matrix
+// cores; ReLU, the second layer (a dot product with w2) and the cross-lane
+// reduction follow in FP32.  Two forms share the structure:
+//   DecBF16: v_mfma_f32_16x16x32_bf16 (BF16 operands, FP32 accumulation);
+//   DecF32:  v_mfma_f32_16x16x4f32 (FP32 operands and accumulation).
+// BF16 operand layouts (verified on gfx950):
 //   A[i][k]: lane l holds i = l%16, k = 8*(l/16) + 0..7
 //   B[k][j]: lane l holds j = l%16, k = 8*(l/16) + 0..7
 //   D[i][j]: lane l holds j = l%16, i = 4*(l/16) + r, r = 0..3
@@ -158,5 +160,136 @@ __device__ inline float wave_decode(const uint4* frag, const float* w2s, float b
   }
   return b2 + mine;
 }
+
+// ---------------------------------------------------------------------------
+// FP32 form.  v_mfma_f32_16x16x4f32 layouts (verified on gfx950):
+//   A[i][k]: lane l holds i = l%16, k = l/16;  B[k][j]: j = l%16, k = l/16;
+//   D as above.  Inputs per point: [x(3), z(m), 1] (zero padded to a multiple
+//   of 4), weights [W1 | b1]: position and bias stay exact FP32.
+// ---------------------------------------------------------------------------
+template <int M, bool XYZ>
+struct MfmaShape32 {
+  static constexpr int OFF = XYZ ? 3 : 0;
+  static constexpr int KP = ((M + OFF + 1) + 3) / 4 * 4;
+  static constexpr int KS = KP / 4;
+  static constexpr int ROW = KP + 1;  // odd row stride spreads LDS banks
+  static constexpr int STAGE_BYTES = 64 * ROW * 4;
+  static constexpr int frag_bytes(int H) { return (H / 16) * KS * 64 * 4; }
+};
+
+template <int M, bool XYZ>
+__device__ inline void load_frags32(const ngl_model& md, int L, float* frag, float* w2s) {
+  using S = MfmaShape32<M, XYZ>;
+  const int H = md.hidden;
+  const int din = M + S::OFF;
+  const float* W1 = static_cast<const float*>(md.W1[L - 1]);
+  const float* b1 = md.b1[L - 1];
+  const int n = (H / 16) * S::KS * 64;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int lane = e & 63;
+    const int s = (e >> 6) % S::KS;
+    const int h = (e >> 6) / S::KS;
+    const int i = 16 * h + (lane & 15);
+    const int k = 4 * s + (lane >> 4);
+    frag[e] = k < din ? W1[i * din + k] : (k == din ? b1[i] : 0.0f);
+  }
+  for (int k = threadIdx.x; k < H; k += blockDim.x) w2s[k] = md.w2[L - 1][k];
+}
+
+template <int M, bool XYZ>
+__device__ inline void stage_row32(float* stage, const float x[3], const float* z) {
+  using S = MfmaShape32<M, XYZ>;
+  float* row = stage + (threadIdx.x & 63) * S::ROW;
+#pragma unroll
+  for (int k = 0; k < S::KP; ++k) {
+    float v = 0.0f;
+    if (k < S::OFF) v = x[k < 3 ? k : 0];
+    else if (k < S::OFF + M) v = z[k - S::OFF < M && k >= S::OFF ? k - S::OFF : 0];
+    else if (k == S::OFF + M) v = 1.0f;
+    row[k] = v;
+  }
+}
+
+template <int M, bool XYZ>
+__device__ inline float wave_decode32(const float* frag, const float* w2s, float b2, const float* stage, int H) {
+  using S = MfmaShape32<M, XYZ>;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, j = lane & 15;
+  float mine = 0.0f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    float b[S::KS];
+#pragma unroll
+    for (int s = 0; s < S::KS; ++s) b[s] = stage[(16 * t + j) * S::ROW + 4 * s + g];
+    float part = 0.0f;
+    for (int h = 0; h < H / 16; ++h) {
+      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < S::KS; ++s)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(h * S::KS + s) * 64 + lane], b[s], acc, 0, 0, 0);
+      const float4 w = *reinterpret_cast<const float4*>(w2s + 16 * h + 4 * g);
+      part = fmaf(w.x, fmaxf(acc[0], 0.0f), part);
+      part = fmaf(w.y, fmaxf(acc[1], 0.0f), part);
+      part = fmaf(w.z, fmaxf(acc[2], 0.0f), part);
+      part = fmaf(w.w, fmaxf(acc[3], 0.0f), part);
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (g == t) mine = part;
+  }
+  return b2 + mine;
+}
+
+// Decoder policies used by the kernels.
+template <int M, bool XYZ>
+struct DecBF16 {
+  using Frag = uint4;
+  using Stage = uint16_t;
+  static constexpr int STAGE_BYTES = MfmaShape<M, XYZ>::STAGE_BYTES;
+  static constexpr int STAGE_ELEMS = 64 * MfmaShape<M, XYZ>::ROW;
+  static constexpr int frag_elems(int H) { return (H / 16) * MfmaShape<M, XYZ>::KS * 64; }
+  static constexpr int frag_bytes(int H) { return MfmaShape<M, XYZ>::frag_bytes(H); }
+  __device__ static void load(const ngl_model& md, int L, Frag* f, float* w2s) { load_frags<M, XYZ>(md, L, f, w2s); }
+  __device__ static void stage(Stage* st, const float x[3], const float* z) { stage_row<M, XYZ>(st, x, z); }
+  __device__ static float decode(const Frag* f, const float* w2s, float b2, const Stage* st, int H) {
+    return wave_decode<M, XYZ>(f, w2s, b2, st, H);
+  }
+};
+
+template <int M, bool XYZ>
+struct DecF32 {
+  using Frag = float;
+  using Stage = float;
+  static constexpr int STAGE_BYTES = MfmaShape32<M, XYZ>::STAGE_BYTES;
+  static constexpr int STAGE_ELEMS = 64 * MfmaShape32<M, XYZ>::ROW;
+  static constexpr int frag_elems(int H) { return (H / 16) * MfmaShape32<M, XYZ>::KS * 64; }
+  static constexpr int frag_bytes(int H) { return MfmaShape32<M, XYZ>::frag_bytes(H); }
+  __device__ static void load(const ngl_model& md, int L, Frag* f, float* w2s) { load_frags32<M, XYZ>(md, L, f, w2s); }
+  __device__ static void stage(Stage* st, const float x[3], const float* z) { stage_row32<M, XYZ>(st, x, z); }
+  __device__ static float decode(const Frag* f, const float* w2s, float b2, const Stage* st, int H) {
+    return wave_decode32<M, XYZ>(f, w2s, b2, st, H);
+  }
+};
+
+// LDS carve-up shared by the kernels that decode with a policy:
+// [frag0][frag1 (blend only)][w2s0][w2s1][stage per wavefront].
+template <class DEC>
+struct DecLds {
+  typename DEC::Frag* frag0;
+  typename DEC::Frag* frag1;
+  float* w2s0;
+  float* w2s1;
+  typename DEC::Stage* stage;  // this wavefront's staging rows
+  __device__ DecLds(char* smem, int H, bool blend) {
+    frag0 = reinterpret_cast<typename DEC::Frag*>(smem);
+    frag1 = frag0 + DEC::frag_elems(H);
+    w2s0 = reinterpret_cast<float*>(frag1 + (blend ? DEC::frag_elems(H) : 0));
+    w2s1 = w2s0 + H;
+    stage = reinterpret_cast<typename DEC::Stage*>(w2s1 + H) + (threadIdx.x >> 6) * DEC::STAGE_ELEMS;
+  }
+  static size_t fixed_bytes(int H, bool blend) {
+    return size_t(DEC::frag_bytes(H)) * (blend ? 2 : 1) + 2 * sizeof(float) * size_t(H);
+  }
+};
 
 }  // namespace ngl

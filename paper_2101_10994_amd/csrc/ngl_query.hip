@@ -91,27 +91,22 @@ __global__ __launch_bounds__(kBlock) void k_query_all(ngl_model md, const float*
   }
 }
 
-// BF16 decoder weights: the same location and gather per lane, then the
-// first decoder layer for the wavefront's 64 points on the matrix cores.
-// Grid-stride over points so each block stages the decoder fragments in
-// LDS once; inside the loop only wavefront-level LDS ordering is needed.
-template <int M, typename FT, bool XYZ, int NW>
+// Matrix-core decoder (BF16 or FP32 form): the same location and gather per
+// lane, then the first decoder layer for the wavefront's 64 points on the
+// matrix cores.  Grid-stride over points so each block stages the decoder
+// fragments in LDS once; inside the loop only wavefront-level LDS ordering
+// is needed.
+template <int M, typename FT, bool XYZ, int NW, class DEC>
 __global__ __launch_bounds__(64 * NW) void k_query_mfma(ngl_model md, const float* __restrict__ xs, int64_t P,
                                                         int lod, float alpha, const float* __restrict__ alpha_pp,
                                                         float* __restrict__ sdf, uint8_t* __restrict__ valid,
                                                         int32_t* __restrict__ vox_out) {
-  using S = MfmaShape<M, XYZ>;
   extern __shared__ __align__(16) char smem[];
   const int H = md.hidden;
   const bool blend = alpha_pp != nullptr || alpha > 0.0f;
-  const int fe = (H / 16) * S::KS * 64;
-  uint4* frag0 = reinterpret_cast<uint4*>(smem);
-  uint4* frag1 = frag0 + fe;
-  float* w2s0 = reinterpret_cast<float*>(frag1 + (blend ? fe : 0));
-  float* w2s1 = w2s0 + H;
-  uint16_t* stage = reinterpret_cast<uint16_t*>(w2s1 + H) + (threadIdx.x >> 6) * 64 * S::ROW;
-  load_frags<M, XYZ>(md, lod, frag0, w2s0);
-  if (blend) load_frags<M, XYZ>(md, lod + 1, frag1, w2s1);
+  DecLds<DEC> S(smem, H, blend);
+  DEC::load(md, lod, S.frag0, S.w2s0);
+  if (blend) DEC::load(md, lod + 1, S.frag1, S.w2s1);
   __syncthreads();
   const float b2a = md.b2[lod - 1];
   const float b2b = blend ? md.b2[lod] : 0.0f;
@@ -140,16 +135,16 @@ __global__ __launch_bounds__(64 * NW) void k_query_mfma(ngl_model md, const floa
     for (int l = 1; l <= NGL_MAX_LODS; ++l)
       if (l <= lod && vox[l - 1] >= 0)
         interp_level<M, FT>(md, l, vox[l - 1], cx >> (Lp - l), cy >> (Lp - l), cz >> (Lp - l), x, z);
-    stage_row<M, XYZ>(stage, x, z);
+    DEC::stage(S.stage, x, z);
     wave_lds_sync();
-    float out = wave_decode<M, XYZ>(frag0, w2s0, b2a, stage, H);
+    float out = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H);
     if (blend) {
       if (vn >= 0) interp_level<M, FT>(md, lod + 1, vn, cx, cy, cz, x, z);
       wave_lds_sync();
-      stage_row<M, XYZ>(stage, x, z);
+      DEC::stage(S.stage, x, z);
       wave_lds_sync();
       const float a = act ? (alpha_pp ? alpha_pp[p] : alpha) : 0.0f;
-      out = (1.0f - a) * out + a * wave_decode<M, XYZ>(frag1, w2s1, b2b, stage, H);
+      out = (1.0f - a) * out + a * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H);
     }
     wave_lds_sync();
     if (act) {
@@ -164,28 +159,30 @@ __global__ __launch_bounds__(64 * NW) void k_query_mfma(ngl_model md, const floa
   }
 }
 
-template <int M, typename FT, bool XYZ, int NW>
+template <int M, typename FT, bool XYZ, int NW, class DEC>
 static int launch_query_mfma_nw(const ngl_model& md, const float* x, int64_t P, int lod, float alpha,
                                 const float* app, float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s,
                                 size_t lds) {
   int64_t grid = (P + 64 * NW - 1) / (64 * NW);
   if (grid > 4096) grid = 4096;
-  k_query_mfma<M, FT, XYZ, NW><<<unsigned(grid), 64 * NW, lds, s>>>(md, x, P, lod, alpha, app, sdf, valid, vox);
+  k_query_mfma<M, FT, XYZ, NW, DEC><<<unsigned(grid), 64 * NW, lds, s>>>(md, x, P, lod, alpha, app, sdf, valid, vox);
   NGL_LAUNCHED();
   return NGL_OK;
 }
 
-template <int M, typename FT, bool XYZ>
+template <int M, typename FT, bool XYZ, class DEC>
 static int launch_query_mfma(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app,
                              float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s) {
-  using S = MfmaShape<M, XYZ>;
   const bool blend = app != nullptr || alpha > 0.0f;
-  const size_t fixed = size_t(S::frag_bytes(md.hidden)) * (blend ? 2 : 1) + 2 * sizeof(float) * md.hidden;
-  if (fixed + 4 * S::STAGE_BYTES <= 65536)
-    return launch_query_mfma_nw<M, FT, XYZ, 4>(md, x, P, lod, alpha, app, sdf, valid, vox, s, fixed + 4 * S::STAGE_BYTES);
-  if (fixed + 2 * S::STAGE_BYTES <= 65536)
-    return launch_query_mfma_nw<M, FT, XYZ, 2>(md, x, P, lod, alpha, app, sdf, valid, vox, s, fixed + 2 * S::STAGE_BYTES);
-  return launch_query_mfma_nw<M, FT, XYZ, 1>(md, x, P, lod, alpha, app, sdf, valid, vox, s, fixed + S::STAGE_BYTES);
+  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, blend);
+  if (fixed + 4 * DEC::STAGE_BYTES <= 65536)
+    return launch_query_mfma_nw<M, FT, XYZ, 4, DEC>(md, x, P, lod, alpha, app, sdf, valid, vox, s,
+                                                    fixed + 4 * DEC::STAGE_BYTES);
+  if (fixed + 2 * DEC::STAGE_BYTES <= 65536)
+    return launch_query_mfma_nw<M, FT, XYZ, 2, DEC>(md, x, P, lod, alpha, app, sdf, valid, vox, s,
+                                                    fixed + 2 * DEC::STAGE_BYTES);
+  return launch_query_mfma_nw<M, FT, XYZ, 1, DEC>(md, x, P, lod, alpha, app, sdf, valid, vox, s,
+                                                  fixed + DEC::STAGE_BYTES);
 }
 
 template <int M, typename FT, bool XYZ>
@@ -231,7 +228,10 @@ template <int M, typename FT, bool XYZ>
 struct QueryOp {
   static int run(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app, float* sdf,
                  uint8_t* valid, int32_t* vox, hipStream_t s) {
-    if (md.w_dtype == NGL_BF16) return launch_query_mfma<M, FT, XYZ>(md, x, P, lod, alpha, app, sdf, valid, vox, s);
+    if (md.w_dtype == NGL_BF16)
+      return launch_query_mfma<M, FT, XYZ, DecBF16<M, XYZ>>(md, x, P, lod, alpha, app, sdf, valid, vox, s);
+    if (option(NGL_OPT_F32_DECODER) == 1)
+      return launch_query_mfma<M, FT, XYZ, DecF32<M, XYZ>>(md, x, P, lod, alpha, app, sdf, valid, vox, s);
     return launch_query<M, FT, XYZ>(md, x, P, lod, alpha, app, sdf, valid, vox, s);
   }
 };

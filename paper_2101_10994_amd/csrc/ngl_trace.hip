@@ -10,38 +10,42 @@
 namespace ngl {
 
 struct TraceArgs {
-  const float* o;
+  const float* o;         // this view's rays, SoA [3][stride]
   const float* d;
-  int64_t R;
+  int64_t stride;         // SoA stride of o and d
+  int64_t base;           // index of this view's first ray in the outputs
+  int64_t R;              // rays of this view
   int lod;
   float alpha;
-  const int32_t* pair_vox;
+  const int32_t* pair_vox;  // this view's hit lists
   const float* t_in;
   const float* t_out;
-  const int32_t* ray_off;
+  const int32_t* ray_off;   // [R+1]
   ngl_trace_params prm;
-  float* t_hit;
+  float* t_hit;           // outputs indexed base + ray
   uint8_t* status;
   int32_t* steps;
   int32_t* hit_vox;
-  unsigned int* counter;  // work queue head (zeroed before the launch)
+  unsigned int* counter;  // this view's work queue head (zeroed before the launch)
+  unsigned int* live;     // nullable: rays of this view not yet finished
+  uint64_t* done_clock;   // nullable: timestamp when the view's last ray ends
 };
 
-// Persistent sphere tracer.  Each wavefront keeps one ray per lane; a lane
-// whose ray terminates takes the next ray from a global queue, so every step
-// is evaluated on a compacted set of active rays.  Every ray ends after at
-// most max_steps evaluations and one pass over its pairs, and the queue is
-// finite, so every wavefront reaches the exit.
-template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW>
-__global__ __launch_bounds__(64 * NW) void k_sphere_trace(ngl_model md, TraceArgs A) {
-  using S = MfmaShape<M, XYZ>;
-  extern __shared__ __align__(16) char smem[];
+// One wavefront serves a view's ray queue.  Each lane keeps one ray; a lane
+// whose ray terminates takes the next ray from the queue, so every step is
+// evaluated on a compacted set of active rays.  Every ray ends after at most
+// max_steps evaluations and one pass over its pairs, and the queue is finite,
+// so the loop ends.  All lanes of the wavefront reach the matrix-core decode
+// together (idle lanes stage zeros).
+template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, class DEC>
+__device__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLds<DEC>& S, float b2a, float b2b) {
   const int lane = threadIdx.x & 63;
   const int64_t R = A.R;
   const bool blend = A.alpha > 0.0f;
   const int lod = A.lod;
   const int Lp = blend ? lod + 1 : lod;
   const int64_t nv_t = ANALYTIC ? 0 : md.nvox[Lp + 1];
+  const int H = md.hidden;
   int ray = -1, p = 0, e = 0, k = 0, cp = -1;
   bool ready = false;
   float t = 0.0f, prev = __builtin_inff();
@@ -53,29 +57,17 @@ __global__ __launch_bounds__(64 * NW) void k_sphere_trace(ngl_model md, TraceArg
     vox[l] = 0;
     cell[l] = 0;
   }
-  // decoder fragments (MFMA form): LOD lod, and lod+1 when blending
-  const int H = md.hidden;
-  uint4* frag0 = reinterpret_cast<uint4*>(smem);
-  uint4* frag1 = frag0 + (MFMA ? (H / 16) * S::KS * 64 : 0);
-  float* w2s0 = reinterpret_cast<float*>(frag1 + (MFMA && blend ? (H / 16) * S::KS * 64 : 0));
-  float* w2s1 = w2s0 + H;
-  uint16_t* stage = reinterpret_cast<uint16_t*>(w2s1 + H) + (threadIdx.x >> 6) * 64 * S::ROW;
-  float b2a = 0.0f, b2b = 0.0f;
-  if constexpr (MFMA) {
-    load_frags<M, XYZ>(md, lod, frag0, w2s0);
-    if (blend) load_frags<M, XYZ>(md, lod + 1, frag1, w2s1);
-    __syncthreads();
-    b2a = md.b2[lod - 1];
-    b2b = blend ? md.b2[lod] : 0.0f;
-  }
   bool exhausted = false;  // wave-uniform
+  unsigned nfin = 0;       // rays this lane finished since the last report
   auto finish = [&](uint8_t st, int32_t hv) {
-    A.t_hit[ray] = t;
-    A.status[ray] = st;
-    A.steps[ray] = k;
-    A.hit_vox[ray] = hv;
+    const int64_t g = A.base + ray;
+    A.t_hit[g] = t;
+    A.status[g] = st;
+    A.steps[g] = k;
+    A.hit_vox[g] = hv;
     ray = -1;
     ready = false;
+    ++nfin;
   };
   for (;;) {
     // 1. refill idle lanes and move every ray to an evaluable state
@@ -99,8 +91,8 @@ __global__ __launch_bounds__(64 * NW) void k_sphere_trace(ngl_model md, TraceArg
             prev = __builtin_inff();
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-              oo[a] = A.o[a * R + ray];
-              dd[a] = A.d[a * R + ray];
+              oo[a] = A.o[a * A.stride + ray];
+              dd[a] = A.d[a * A.stride + ray];
             }
             t = p < e ? A.t_in[p] : 0.0f;
             bool bad = false;
@@ -126,89 +118,204 @@ __global__ __launch_bounds__(64 * NW) void k_sphere_trace(ngl_model md, TraceArg
       if (__ballot(waiting) == 0) break;
     }
     const bool act = ray >= 0 && ready;
-    if (__ballot(act) == 0) {
-      if (exhausted && __ballot(ray >= 0) == 0) break;
+    const bool any_act = __ballot(act) != 0;
+    const bool done = !any_act && exhausted && __ballot(ray >= 0) == 0;
+    if (any_act) {
+      // 2. one SDF evaluation per active lane
+      float dist = 0.0f;
+      int32_t v = -1;
+      float x[3] = {0.0f, 0.0f, 0.0f};
+      float z[M];
+#pragma unroll
+      for (int q = 0; q < M; ++q) z[q] = 0.0f;
+      bool ok = false;  // this lane evaluates the model
+      if (act) {
+        x[0] = fmaf(t, dd[0], oo[0]);
+        x[1] = fmaf(t, dd[1], oo[1]);
+        x[2] = fmaf(t, dd[2], oo[2]);
+        v = A.pair_vox[p];
+        if constexpr (ANALYTIC) {
+          const float q0 = x[0] - A.prm.sphere[0], q1 = x[1] - A.prm.sphere[1], q2 = x[2] - A.prm.sphere[2];
+          dist = sqrtf(q0 * q0 + q1 * q1 + q2 * q2) - A.prm.sphere[3];
+        } else {
+          if (v < 0 || int64_t(v) >= nv_t) {
+            finish(NGL_RAY_INVALID, -1);  // hit list does not belong to this depth
+          } else {
+            if (p != cp) {
+              // ancestor chain of the pair's voxel (parents always exist)
+              int w = v;
+#pragma unroll
+              for (int l = NGL_MAX_LODS; l >= 1; --l) {
+                if (l <= Lp) {
+                  vox[l - 1] = w;
+                  cell[l - 1] = md.cell[l + 1][w];
+                  w = md.parent[l + 1][w];
+                }
+              }
+              cp = p;
+            }
+#pragma unroll
+            for (int l = 1; l <= NGL_MAX_LODS; ++l)
+              if (l <= lod)
+                interp_level<M, FT>(md, l, vox[l - 1], cell_x(cell[l - 1]), cell_y(cell[l - 1]), cell_z(cell[l - 1]),
+                                    x, z);
+            ok = true;
+          }
+        }
+      }
+      if constexpr (!ANALYTIC) {
+        if constexpr (MFMA) {
+          DEC::stage(S.stage, x, z);
+          wave_lds_sync();
+          dist = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H);
+          if (blend) {
+            // with alpha > 0 the pair voxel is the level lod+1 voxel
+            if (ok) {
+              const uint32_t c = md.cell[Lp + 1][v];
+              interp_level<M, FT>(md, lod + 1, v, cell_x(c), cell_y(c), cell_z(c), x, z);
+            }
+            wave_lds_sync();
+            DEC::stage(S.stage, x, z);
+            wave_lds_sync();
+            dist = (1.0f - A.alpha) * dist + A.alpha * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H);
+          }
+          wave_lds_sync();
+        } else if (ok) {
+          dist = decode_f32<M, XYZ>(md, lod, x, z);
+          if (blend) {
+            const uint32_t c = md.cell[Lp + 1][v];
+            interp_level<M, FT>(md, lod + 1, v, cell_x(c), cell_y(c), cell_z(c), x, z);
+            dist = (1.0f - A.alpha) * dist + A.alpha * decode_f32<M, XYZ>(md, lod + 1, x, z);
+          }
+        }
+      }
+      // 3. step
+      if (act && ray >= 0) {
+        ++k;
+        if (dist < A.prm.delta) {
+          finish(NGL_RAY_HIT, v);
+        } else if (A.prm.osc_check && fabsf(dist - prev) < 6.0f * A.prm.delta) {
+          finish(NGL_RAY_STALLED, -1);
+        } else {
+          prev = dist;
+          t += dist;
+          ready = false;
+        }
+      }
+    }
+    if (A.live) {
+      // report finished rays once per iteration; the wavefront that takes
+      // the count to zero stamps the view's end time
+      unsigned tot = nfin;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off, 64);
+      nfin = 0;
+      if (lane == 0 && tot > 0) {
+        const unsigned old = atomicSub(A.live, tot);
+        if (old == tot && A.done_clock) *A.done_clock = wall_clock64();
+      }
+    }
+    if (done) break;
+  }
+}
+
+template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW, class DEC>
+__global__ __launch_bounds__(64 * NW) void k_sphere_trace(ngl_model md, TraceArgs A) {
+  extern __shared__ __align__(16) char smem[];
+  const bool blend = A.alpha > 0.0f;
+  const int H = md.hidden;
+  DecLds<DEC> S(smem, H, blend && MFMA);
+  float b2a = 0.0f, b2b = 0.0f;
+  if constexpr (MFMA) {
+    DEC::load(md, A.lod, S.frag0, S.w2s0);
+    if (blend) DEC::load(md, A.lod + 1, S.frag1, S.w2s1);
+    __syncthreads();
+    b2a = md.b2[A.lod - 1];
+    b2b = blend ? md.b2[A.lod] : 0.0f;
+  }
+  serve_queue<M, FT, XYZ, ANALYTIC, MFMA, DEC>(md, A, S, b2a, b2b);
+}
+
+// Batched form: views in one launch.  Each block walks the views once, in
+// rotation from its own start; at each view that still has queued rays it
+// copies the model into LDS, stages its decoder and serves the view's queue
+// with all its wavefronts, then moves on.  Every block visits each view at
+// most once, so the grid drains.
+struct BatchView {
+  int64_t base;      // first ray of the view in the concatenated arrays
+  int64_t R;
+  int32_t lod;
+  float alpha;
+};
+
+struct BatchArgs {
+  const ngl_model* table;  // device [n]
+  int n;
+  BatchView view[NGL_MAX_BATCH];
+  const float* o;          // view i's rays: SoA block [3][R_i] at 3 * base_i
+  const float* d;
+  int64_t cap;             // pair capacity per view
+  const int32_t* pair_vox;  // [n][cap]
+  const float* t_in;
+  const float* t_out;
+  const int32_t* ray_off;   // view i at base_i + i, [R_i + 1]
+  ngl_trace_params prm;
+  float* t_hit;
+  uint8_t* status;
+  int32_t* steps;
+  int32_t* hit_vox;
+  unsigned int* counters;   // [n] queue heads
+  unsigned int* live;       // [n] unfinished rays
+  uint64_t* clock;          // nullable [n+1]
+};
+
+template <int M, typename FT, bool XYZ, int NW, class DEC>
+__global__ __launch_bounds__(64 * NW) void k_trace_batch(BatchArgs B) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ ngl_model smd;
+  __shared__ int s_has;
+  const int H = B.table[0].hidden;
+  for (int step = 0; step < B.n; ++step) {
+    const int v = (int(blockIdx.x) + step) % B.n;
+    if (threadIdx.x == 0) s_has = int64_t(__atomic_load_n(&B.counters[v], __ATOMIC_RELAXED)) < B.view[v].R;
+    __syncthreads();
+    if (!s_has) {
+      __syncthreads();
       continue;
     }
-    // 2. one SDF evaluation per active lane
-    float dist = 0.0f;
-    int32_t v = -1;
-    float x[3] = {0.0f, 0.0f, 0.0f};
-    float z[M];
-#pragma unroll
-    for (int q = 0; q < M; ++q) z[q] = 0.0f;
-    bool ok = false;  // this lane evaluates the model
-    if (act) {
-      x[0] = fmaf(t, dd[0], oo[0]);
-      x[1] = fmaf(t, dd[1], oo[1]);
-      x[2] = fmaf(t, dd[2], oo[2]);
-      v = A.pair_vox[p];
-      if constexpr (ANALYTIC) {
-        const float q0 = x[0] - A.prm.sphere[0], q1 = x[1] - A.prm.sphere[1], q2 = x[2] - A.prm.sphere[2];
-        dist = sqrtf(q0 * q0 + q1 * q1 + q2 * q2) - A.prm.sphere[3];
-      } else {
-        if (v < 0 || int64_t(v) >= nv_t) {
-          finish(NGL_RAY_INVALID, -1);  // hit list does not belong to this depth
-        } else {
-          if (p != cp) {
-            // ancestor chain of the pair's voxel (parents always exist)
-            int w = v;
-#pragma unroll
-            for (int l = NGL_MAX_LODS; l >= 1; --l) {
-              if (l <= Lp) {
-                vox[l - 1] = w;
-                cell[l - 1] = md.cell[l + 1][w];
-                w = md.parent[l + 1][w];
-              }
-            }
-            cp = p;
-          }
-#pragma unroll
-          for (int l = 1; l <= NGL_MAX_LODS; ++l)
-            if (l <= lod)
-              interp_level<M, FT>(md, l, vox[l - 1], cell_x(cell[l - 1]), cell_y(cell[l - 1]), cell_z(cell[l - 1]), x, z);
-          ok = true;
-        }
-      }
+    {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(B.table + v);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(&smd);
+      for (int w = threadIdx.x; w < int(sizeof(ngl_model) / 4); w += blockDim.x) dst[w] = src[w];
     }
-    if constexpr (!ANALYTIC) {
-      if constexpr (MFMA) {
-        // every lane joins the wavefront's decode; idle lanes stage zeros
-        stage_row<M, XYZ>(stage, x, z);
-        wave_lds_sync();
-        dist = wave_decode<M, XYZ>(frag0, w2s0, b2a, stage, H);
-        if (blend) {
-          // with alpha > 0 the pair voxel is the level lod+1 voxel
-          if (ok) interp_level<M, FT>(md, lod + 1, v, cell_x(md.cell[Lp + 1][v]), cell_y(md.cell[Lp + 1][v]),
-                                      cell_z(md.cell[Lp + 1][v]), x, z);
-          wave_lds_sync();
-          stage_row<M, XYZ>(stage, x, z);
-          wave_lds_sync();
-          dist = (1.0f - A.alpha) * dist + A.alpha * wave_decode<M, XYZ>(frag1, w2s1, b2b, stage, H);
-        }
-        wave_lds_sync();
-      } else if (ok) {
-        dist = decode_f32<M, XYZ>(md, lod, x, z);
-        if (blend) {
-          interp_level<M, FT>(md, lod + 1, v, cell_x(md.cell[Lp + 1][v]), cell_y(md.cell[Lp + 1][v]),
-                              cell_z(md.cell[Lp + 1][v]), x, z);
-          dist = (1.0f - A.alpha) * dist + A.alpha * decode_f32<M, XYZ>(md, lod + 1, x, z);
-        }
-      }
-    }
-    // 3. step
-    if (act && ray >= 0) {
-      ++k;
-      if (dist < A.prm.delta) {
-        finish(NGL_RAY_HIT, v);
-      } else if (A.prm.osc_check && fabsf(dist - prev) < 6.0f * A.prm.delta) {
-        finish(NGL_RAY_STALLED, -1);
-      } else {
-        prev = dist;
-        t += dist;
-        ready = false;
-      }
-    }
+    __syncthreads();
+    TraceArgs A{};
+    A.o = B.o + 3 * B.view[v].base;  // each view's rays are one SoA block
+    A.d = B.d + 3 * B.view[v].base;
+    A.stride = B.view[v].R;
+    A.base = B.view[v].base;
+    A.R = B.view[v].R;
+    A.lod = B.view[v].lod;
+    A.alpha = B.view[v].alpha;
+    A.pair_vox = B.pair_vox + int64_t(v) * B.cap;
+    A.t_in = B.t_in + int64_t(v) * B.cap;
+    A.t_out = B.t_out + int64_t(v) * B.cap;
+    A.ray_off = B.ray_off + B.view[v].base + v;
+    A.prm = B.prm;
+    A.t_hit = B.t_hit;
+    A.status = B.status;
+    A.steps = B.steps;
+    A.hit_vox = B.hit_vox;
+    A.counter = B.counters + v;
+    A.live = B.live + v;
+    A.done_clock = B.clock ? B.clock + 1 + v : nullptr;
+    const bool blend = A.alpha > 0.0f;
+    DecLds<DEC> S(smem, H, blend);
+    DEC::load(smd, A.lod, S.frag0, S.w2s0);
+    if (blend) DEC::load(smd, A.lod + 1, S.frag1, S.w2s1);
+    __syncthreads();
+    serve_queue<M, FT, XYZ, false, true, DEC>(smd, A, S, smd.b2[A.lod - 1], blend ? smd.b2[A.lod] : 0.0f);
+    __syncthreads();  // every wavefront is done with this view's LDS
   }
 }
 
@@ -218,40 +325,105 @@ __global__ void k_zero_counter(unsigned int* c) {
 
 // Enough blocks to fill every CU at the kernel's occupancy (one value per
 // instantiation, computed on first use).
-template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW>
+template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW, class DEC>
 static int persistent_grid(size_t lds) {
   static int cached = 0;
   if (cached) return cached;
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 1024;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
-  const void* kern = reinterpret_cast<const void*>(&k_sphere_trace<M, FT, XYZ, ANALYTIC, MFMA, NW>);
+  const void* kern = reinterpret_cast<const void*>(&k_sphere_trace<M, FT, XYZ, ANALYTIC, MFMA, NW, DEC>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
   cached = cus * per;
   return cached;
 }
 
-template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW>
+template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW, class DEC>
 static int launch_trace_nw(const ngl_model& md, const TraceArgs& A, hipStream_t s, size_t lds) {
   k_zero_counter<<<1, 64, 0, s>>>(A.counter);
-  int grid = persistent_grid<M, FT, XYZ, ANALYTIC, MFMA, NW>(lds);
+  int grid = persistent_grid<M, FT, XYZ, ANALYTIC, MFMA, NW, DEC>(lds);
+  const int bpc = option(NGL_OPT_TRACE_BLOCKS_PER_CU);
+  if (bpc > 0) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus * bpc < grid) grid = cus * bpc;
+  }
   const int64_t need = (A.R + 64 * NW - 1) / (64 * NW);
   if (need < grid) grid = int(need);
-  k_sphere_trace<M, FT, XYZ, ANALYTIC, MFMA, NW><<<grid, 64 * NW, lds, s>>>(md, A);
+  k_sphere_trace<M, FT, XYZ, ANALYTIC, MFMA, NW, DEC><<<grid, 64 * NW, lds, s>>>(md, A);
   NGL_LAUNCHED();
   return NGL_OK;
 }
 
+template <int M, typename FT, bool XYZ, class DEC>
+static int launch_trace_mfma(const ngl_model& md, const TraceArgs& A, hipStream_t s) {
+  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, A.alpha > 0.0f);
+  const int want = option(NGL_OPT_TRACE_WAVES);
+  if ((want == 0 || want >= 4) && fixed + 4 * DEC::STAGE_BYTES <= 65536)
+    return launch_trace_nw<M, FT, XYZ, false, true, 4, DEC>(md, A, s, fixed + 4 * DEC::STAGE_BYTES);
+  if ((want == 0 || want >= 2) && fixed + 2 * DEC::STAGE_BYTES <= 65536)
+    return launch_trace_nw<M, FT, XYZ, false, true, 2, DEC>(md, A, s, fixed + 2 * DEC::STAGE_BYTES);
+  return launch_trace_nw<M, FT, XYZ, false, true, 1, DEC>(md, A, s, fixed + DEC::STAGE_BYTES);
+}
+
 template <int M, typename FT, bool XYZ, bool ANALYTIC>
 static int launch_trace(const ngl_model& md, const TraceArgs& A, hipStream_t s) {
-  using S = MfmaShape<M, XYZ>;
-  if (ANALYTIC || md.w_dtype != NGL_BF16) return launch_trace_nw<M, FT, XYZ, ANALYTIC, false, 4>(md, A, s, 0);
-  const size_t fixed = size_t(S::frag_bytes(md.hidden)) * (A.alpha > 0.0f ? 2 : 1) + 2 * sizeof(float) * md.hidden;
-  if (fixed + 4 * S::STAGE_BYTES <= 65536)
-    return launch_trace_nw<M, FT, XYZ, false, true, 4>(md, A, s, fixed + 4 * S::STAGE_BYTES);
-  if (fixed + 2 * S::STAGE_BYTES <= 65536)
-    return launch_trace_nw<M, FT, XYZ, false, true, 2>(md, A, s, fixed + 2 * S::STAGE_BYTES);
-  return launch_trace_nw<M, FT, XYZ, false, true, 1>(md, A, s, fixed + S::STAGE_BYTES);
+  if (ANALYTIC) return launch_trace_nw<M, FT, XYZ, true, false, 4, DecF32<M, XYZ>>(md, A, s, 0);
+  if (md.w_dtype == NGL_BF16) return launch_trace_mfma<M, FT, XYZ, DecBF16<M, XYZ>>(md, A, s);
+  if (option(NGL_OPT_F32_DECODER) == 1) return launch_trace_mfma<M, FT, XYZ, DecF32<M, XYZ>>(md, A, s);
+  return launch_trace_nw<M, FT, XYZ, false, false, 4, DecF32<M, XYZ>>(md, A, s, 0);
+}
+
+template <int M, typename FT, bool XYZ, int NW, class DEC>
+static int launch_batch_nw(const BatchArgs& B, hipStream_t s, size_t lds) {
+  static int per = 0;
+  static int cus = 0;
+  if (!per) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    const void* kern = reinterpret_cast<const void*>(&k_trace_batch<M, FT, XYZ, NW, DEC>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
+  }
+  int grid = cus * per;
+  const int cap = option(NGL_OPT_TRACE_BLOCKS_PER_CU);
+  if (cap > 0 && cap < per) grid = cus * cap;
+  k_trace_batch<M, FT, XYZ, NW, DEC><<<grid, 64 * NW, lds, s>>>(B);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+template <int M, typename FT, bool XYZ, class DEC>
+static int launch_batch(const BatchArgs& B, bool any_blend, int H, hipStream_t s) {
+  const size_t fixed = DecLds<DEC>::fixed_bytes(H, any_blend);
+  const int want = option(NGL_OPT_TRACE_WAVES);
+  if ((want == 0 || want >= 4) && fixed + 4 * DEC::STAGE_BYTES <= 65536)
+    return launch_batch_nw<M, FT, XYZ, 4, DEC>(B, s, fixed + 4 * DEC::STAGE_BYTES);
+  if ((want == 0 || want >= 2) && fixed + 2 * DEC::STAGE_BYTES <= 65536)
+    return launch_batch_nw<M, FT, XYZ, 2, DEC>(B, s, fixed + 2 * DEC::STAGE_BYTES);
+  return launch_batch_nw<M, FT, XYZ, 1, DEC>(B, s, fixed + DEC::STAGE_BYTES);
+}
+
+template <int M, typename FT, bool XYZ>
+struct BatchOp {
+  static int run(const ngl_model& md, const BatchArgs& B, bool any_blend, hipStream_t s) {
+    if (md.w_dtype == NGL_BF16) return launch_batch<M, FT, XYZ, DecBF16<M, XYZ>>(B, any_blend, md.hidden, s);
+    return launch_batch<M, FT, XYZ, DecF32<M, XYZ>>(B, any_blend, md.hidden, s);
+  }
+};
+
+struct BatchInit {
+  int n;
+  int64_t R[NGL_MAX_BATCH];
+};
+
+__global__ void k_batch_init(unsigned int* counters, unsigned int* live, BatchInit I, uint64_t* clock) {
+  const int i = threadIdx.x;
+  if (i < I.n) {
+    counters[i] = 0u;
+    live[i] = unsigned(I.R[i]);
+  }
+  if (i == 0 && clock) clock[0] = wall_clock64();
 }
 
 template <int M, typename FT, bool XYZ>
@@ -289,8 +461,8 @@ int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t
   NGL_REQUIRE(o && d && ray_off && t_hit && status && steps && hit_vox, "null buffer");
   NGL_REQUIRE(ws != nullptr && ws_bytes >= 256, "workspace too small: %zu < 256 bytes", ws_bytes);
   hipStream_t s = (hipStream_t)stream;
-  TraceArgs A{o, d, R, int(lod), alpha, pair_vox, t_in, t_out, ray_off, *params, t_hit, status, steps, hit_vox,
-              static_cast<unsigned int*>(ws)};
+  TraceArgs A{o, d, R, 0, R, int(lod), alpha, pair_vox, t_in, t_out, ray_off, *params, t_hit, status, steps,
+              hit_vox, static_cast<unsigned int*>(ws), nullptr, nullptr};
   if (analytic) return launch_trace<8, F32, true, true>(*m, A, s);
   const ngl_model& md = *m;
 #define NGL_TRACE_XYZ(M_, FT_) \
@@ -310,6 +482,169 @@ int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t
   }
 #undef NGL_TRACE_FT
 #undef NGL_TRACE_XYZ
+}
+
+int ngl_model_table_bytes(int32_t n, size_t* bytes) {
+  NGL_REQUIRE(bytes && n >= 1 && n <= NGL_MAX_BATCH, "n must be in 1..%d", NGL_MAX_BATCH);
+  *bytes = sizeof(ngl_model) * size_t(n);
+  return NGL_OK;
+}
+
+int ngl_model_table_upload(const ngl_model* models, int32_t n, void* table, void* stream) {
+  NGL_REQUIRE(models && table && n >= 1 && n <= NGL_MAX_BATCH, "invalid model table upload");
+  hipStream_t s = (hipStream_t)stream;
+  NGL_HIP(hipMemcpyAsync(table, models, sizeof(ngl_model) * size_t(n), hipMemcpyHostToDevice, s));
+  NGL_HIP(hipStreamSynchronize(s));
+  return NGL_OK;
+}
+
+namespace {
+struct BatchLayout {
+  int64_t base[NGL_MAX_BATCH];
+  int64_t R_total = 0, R_max = 0;
+  float* o = nullptr;
+  float* d = nullptr;
+  int32_t* pair_ray = nullptr;
+  int32_t* pair_vox = nullptr;
+  float* t_in = nullptr;
+  float* t_out = nullptr;
+  int32_t* ray_off = nullptr;
+  unsigned int* counters = nullptr;
+  unsigned int* live = nullptr;
+  char* trav_ws = nullptr;
+  size_t trav_bytes = 0;
+  size_t bytes = 0;
+};
+
+size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+BatchLayout batch_layout(const ngl_view* views, int n, int64_t cap, void* ws) {
+  BatchLayout L;
+  for (int i = 0; i < n; ++i) {
+    const int64_t R = int64_t(views[i].width) * views[i].height;
+    L.base[i] = L.R_total;
+    L.R_total += R;
+    if (R > L.R_max) L.R_max = R;
+  }
+  char* b = static_cast<char*>(ws);
+  size_t off = 0;
+  auto take = [&](size_t nb) {
+    char* q = b ? b + off : nullptr;
+    off += al256(nb);
+    return q;
+  };
+  L.o = reinterpret_cast<float*>(take(sizeof(float) * 3 * size_t(L.R_total)));
+  L.d = reinterpret_cast<float*>(take(sizeof(float) * 3 * size_t(L.R_total)));
+  L.pair_ray = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * size_t(n) * size_t(cap)));
+  L.pair_vox = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * size_t(n) * size_t(cap)));
+  L.t_in = reinterpret_cast<float*>(take(sizeof(float) * size_t(n) * size_t(cap)));
+  L.t_out = reinterpret_cast<float*>(take(sizeof(float) * size_t(n) * size_t(cap)));
+  L.ray_off = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * size_t(L.R_total + n)));
+  L.counters = reinterpret_cast<unsigned int*>(take(sizeof(unsigned int) * NGL_MAX_BATCH));
+  L.live = reinterpret_cast<unsigned int*>(take(sizeof(unsigned int) * NGL_MAX_BATCH));
+  size_t tb = 0;
+  ngl_trace_octree_workspace(L.R_max, cap, &tb);
+  L.trav_bytes = tb;
+  L.trav_ws = take(tb);
+  L.bytes = off;
+  return L;
+}
+}  // namespace
+
+int ngl_render_batch_workspace(const ngl_view* views, int32_t n, int64_t pair_capacity, size_t* bytes) {
+  NGL_REQUIRE(views && bytes && n >= 1 && n <= NGL_MAX_BATCH, "n must be in 1..%d", NGL_MAX_BATCH);
+  NGL_REQUIRE(pair_capacity >= 0 && pair_capacity < (int64_t(1) << 31), "pair_capacity out of range");
+  *bytes = batch_layout(views, n, pair_capacity, nullptr).bytes;
+  return NGL_OK;
+}
+
+int ngl_render_batch(const ngl_model* models, const void* table, const ngl_view* views, int32_t n,
+                     const ngl_trace_params* params, int64_t pair_capacity, void* ws, size_t ws_bytes, float* t_hit,
+                     uint8_t* status, int32_t* steps, int32_t* hit_vox, int64_t* counts, uint64_t* frame_clock,
+                     void* stream) {
+  using namespace ngl;
+  NGL_REQUIRE(models && table && views && params, "null argument");
+  NGL_REQUIRE(n >= 1 && n <= NGL_MAX_BATCH, "n must be in 1..%d", NGL_MAX_BATCH);
+  NGL_REQUIRE(params->analytic == 0, "batched rendering traces the models (analytic mode is per call)");
+  NGL_REQUIRE(params->max_steps >= 0, "max_steps must be >= 0");
+  NGL_REQUIRE(t_hit && status && steps && hit_vox && counts, "null output buffer");
+  const ngl_model& m0 = models[0];
+  bool any_blend = false;
+  for (int i = 0; i < n; ++i) {
+    const ngl_model* m = models + i;
+    int rc = check_model(m, true);
+    if (rc) return rc;
+    NGL_REQUIRE(m->feat_dim == m0.feat_dim && m->hidden == m0.hidden && m->with_xyz == m0.with_xyz &&
+                    m->feat_dtype == m0.feat_dtype && m->w_dtype == m0.w_dtype,
+                "model %d differs in feat_dim, hidden, with_xyz or dtypes from model 0", i);
+    const ngl_view& v = views[i];
+    NGL_REQUIRE(v.width > 0 && v.height > 0, "view %d has an empty image", i);
+    NGL_REQUIRE(v.lod >= 1 && v.lod <= m->num_lods, "view %d: lod %d outside 1..%d", i, v.lod, m->num_lods);
+    NGL_REQUIRE(v.alpha >= 0.0f && v.alpha < 1.0f, "view %d: alpha must be in [0,1)", i);
+    NGL_REQUIRE(!(v.alpha > 0.0f) || v.lod < m->num_lods, "view %d: blending needs lod < num_lods", i);
+    NGL_REQUIRE(m->nvox[0] > 0, "model %d is empty", i);
+    any_blend = any_blend || v.alpha > 0.0f;
+  }
+  BatchLayout L = batch_layout(views, n, pair_capacity, ws);
+  NGL_REQUIRE(L.R_total < (int64_t(1) << 31), "too many rays in the batch");
+  NGL_REQUIRE(ws != nullptr && ws_bytes >= L.bytes, "workspace too small: %zu < %zu bytes", ws_bytes, L.bytes);
+  hipStream_t s = (hipStream_t)stream;
+  BatchInit I{};
+  I.n = n;
+  for (int i = 0; i < n; ++i) I.R[i] = int64_t(views[i].width) * views[i].height;
+  k_batch_init<<<1, 64, 0, s>>>(L.counters, L.live, I, frame_clock);
+  NGL_LAUNCHED();
+  // rays and hit lists, view by view (the traversal workspace is reused)
+  for (int i = 0; i < n; ++i) {
+    const ngl_view& v = views[i];
+    const int64_t R = I.R[i];
+    float* o = L.o + 3 * L.base[i];
+    float* d = L.d + 3 * L.base[i];
+    int rc = ngl_camera_rays(v.eye, v.target, v.up, v.fov_y_deg, v.width, v.height, o, d, stream);
+    if (rc) return rc;
+    const int depth = (v.alpha > 0.0f ? v.lod + 1 : v.lod) + 1;
+    const int64_t pb = int64_t(i) * pair_capacity;
+    rc = ngl_trace_octree(models + i, o, d, R, depth, pair_capacity, L.trav_ws, L.trav_bytes, L.pair_ray + pb,
+                          L.pair_vox + pb, L.t_in + pb, L.t_out + pb, L.ray_off + L.base[i] + i, counts + 2 * i,
+                          stream);
+    if (rc) return rc;
+  }
+  BatchArgs B{};
+  B.table = static_cast<const ngl_model*>(table);
+  B.n = n;
+  for (int i = 0; i < n; ++i) B.view[i] = BatchView{L.base[i], I.R[i], views[i].lod, views[i].alpha};
+  B.o = L.o;
+  B.d = L.d;
+  B.cap = pair_capacity;
+  B.pair_vox = L.pair_vox;
+  B.t_in = L.t_in;
+  B.t_out = L.t_out;
+  B.ray_off = L.ray_off;
+  B.prm = *params;
+  B.t_hit = t_hit;
+  B.status = status;
+  B.steps = steps;
+  B.hit_vox = hit_vox;
+  B.counters = L.counters;
+  B.live = L.live;
+  B.clock = frame_clock;
+#define NGL_BATCH_XYZ(M_, FT_) \
+  return m0.with_xyz ? BatchOp<M_, FT_, true>::run(m0, B, any_blend, s) : BatchOp<M_, FT_, false>::run(m0, B, any_blend, s)
+#define NGL_BATCH_FT(M_)                   \
+  switch (m0.feat_dtype) {                 \
+    case NGL_F32: NGL_BATCH_XYZ(M_, F32);  \
+    case NGL_F16: NGL_BATCH_XYZ(M_, F16);  \
+    default: NGL_BATCH_XYZ(M_, BF16);      \
+  }
+  switch (m0.feat_dim) {
+    case 8: NGL_BATCH_FT(8);
+    case 16: NGL_BATCH_FT(16);
+    case 32: NGL_BATCH_FT(32);
+    case 64: NGL_BATCH_FT(64);
+    default: NGL_FAIL(NGL_E_UNSUPPORTED, "feat_dim %d not compiled (8, 16, 32, 64)", m0.feat_dim);
+  }
+#undef NGL_BATCH_FT
+#undef NGL_BATCH_XYZ
 }
 
 }  // extern "C"

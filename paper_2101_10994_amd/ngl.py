@@ -54,6 +54,11 @@ class ngl_octree_host(C.Structure):
                 ("corner_adj_off", P * MAX_LODS), ("corner_adj", P * MAX_LODS)]
 
 
+class ngl_view(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("target", C.c_float * 3), ("up", C.c_float * 3), ("fov_y_deg", C.c_float),
+                ("width", i32), ("height", i32), ("lod", i32), ("alpha", C.c_float)]
+
+
 class ngl_trace_params(C.Structure):
     _fields_ = [("max_steps", i32), ("delta", C.c_float), ("t_far", C.c_float), ("osc_check", i32),
                 ("analytic", i32), ("sphere", C.c_float * 4)]
@@ -63,6 +68,8 @@ EXPORTS = {
     "ngl_status_str": (C.c_char_p, [C.c_int]),
     "ngl_last_error": (C.c_char_p, []),
     "ngl_version": (C.c_int, []),
+    "ngl_set_option": (C.c_int, [C.c_int, C.c_int]),
+    "ngl_get_option": (C.c_int, [C.c_int, P]),
     "ngl_octree_plan": (C.c_int, [P, i64, i32, P, P]),
     "ngl_octree_fill": (C.c_int, [P, i64, i32, P]),
     "ngl_query_sdf": (C.c_int, [P, P, i64, i32, C.c_float, P, P, P, P, P]),
@@ -72,6 +79,10 @@ EXPORTS = {
     "ngl_trace_octree": (C.c_int, [P, P, P, i64, i32, i64, P, C.c_size_t, P, P, P, P, P, P, P]),
     "ngl_sphere_trace": (C.c_int, [P, P, P, i64, i32, C.c_float, P, P, P, P, P, P, P, P, P, P, C.c_size_t, P]),
     "ngl_sphere_trace_workspace": (C.c_int, [P]),
+    "ngl_model_table_bytes": (C.c_int, [i32, P]),
+    "ngl_model_table_upload": (C.c_int, [P, i32, P, P]),
+    "ngl_render_batch_workspace": (C.c_int, [P, i32, i64, P]),
+    "ngl_render_batch": (C.c_int, [P, P, P, i32, P, i64, P, C.c_size_t, P, P, P, P, P, P, P]),
     "ngl_train_workspace": (C.c_int, [P, i64, P]),
     "ngl_backward_all_lods": (C.c_int, [P, P, i64, P, P, P, P, P, P, P, C.c_size_t, P]),
     "ngl_train_fwd_bwd": (C.c_int, [P, P, P, i64, P, P, P, P, P, P, P, P, C.c_size_t, P]),
@@ -93,6 +104,21 @@ def lib():
                 f.argtypes = args
             _lib = h
     return _lib
+
+
+OPT_F32_DECODER, OPT_TRACE_WAVES, OPT_TRACE_BLOCKS_PER_CU = 0, 1, 2
+MAX_BATCH = 32
+
+
+def set_option(key: int, value: int):
+    """Library option (see ngl_set_option): OPT_F32_DECODER 0 = VALU, 1 = matrix cores."""
+    _check(lib().ngl_set_option(int(key), int(value)))
+
+
+def get_option(key: int) -> int:
+    v = C.c_int()
+    _check(lib().ngl_get_option(int(key), C.addressof(v)))
+    return int(v.value)
 
 
 def _check(rc: int):
@@ -391,6 +417,71 @@ def sphere_trace(model: Model, o, d, lod: int, alpha: float, hits: dict, max_ste
                                   _ptr(out["t"]), _ptr(out["status"]), _ptr(out["steps"]), _ptr(out["hit_vox"]),
                                   _ptr(out["ws"]), out["ws"].numel(), _stream()))
     return out
+
+
+# ---------------------------------------------------------------------------
+# 3b. Batched rendering
+# ---------------------------------------------------------------------------
+def make_view(eye, width, height, lod, alpha=0.0, target=(0.0, 0.0, 0.0), up=(0.0, 1.0, 0.0), fov_y_deg=45.0):
+    v = ngl_view()
+    for a in range(3):
+        v.eye[a], v.target[a], v.up[a] = float(eye[a]), float(target[a]), float(up[a])
+    v.fov_y_deg = float(fov_y_deg)
+    v.width, v.height, v.lod, v.alpha = int(width), int(height), int(lod), float(alpha)
+    return v
+
+
+class BatchRenderer:
+    """Device model table, workspace and outputs for ngl_render_batch over a
+    fixed list of models (all of one format) and view sizes."""
+
+    def __init__(self, models: Sequence[Model], views: Sequence[ngl_view], pair_capacity: int, device="cuda"):
+        L = lib()
+        self.models = list(models)
+        self.n = len(self.models)
+        if not 1 <= self.n <= MAX_BATCH:
+            raise NGLError("between 1 and %d models" % MAX_BATCH)
+        self.h_models = (ngl_model * self.n)(*[m._struct for m in self.models])
+        nb = C.c_size_t()
+        _check(L.ngl_model_table_bytes(self.n, C.addressof(nb)))
+        self.table = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        _check(L.ngl_model_table_upload(C.addressof(self.h_models), self.n, _ptr(self.table), _stream()))
+        self.set_views(views, pair_capacity, device)
+
+    def set_views(self, views, pair_capacity, device="cuda"):
+        self.views = (ngl_view * self.n)(*views)
+        self.sizes = [v.width * v.height for v in views]
+        self.base = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self.capacity = int(pair_capacity)
+        nb = C.c_size_t()
+        _check(lib().ngl_render_batch_workspace(C.addressof(self.views), self.n, self.capacity, C.addressof(nb)))
+        self.ws = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        R = int(self.base[-1])
+        self.t = torch.empty(R, dtype=torch.float32, device=device)
+        self.status = torch.empty(R, dtype=torch.uint8, device=device)
+        self.steps = torch.empty(R, dtype=torch.int32, device=device)
+        self.hit_vox = torch.empty(R, dtype=torch.int32, device=device)
+        self.counts = torch.zeros((self.n, 2), dtype=torch.int64, device=device)
+        self.clock = torch.zeros(self.n + 1, dtype=torch.int64, device=device)
+
+    def render(self, max_steps: int, delta: float, t_far: float = 5.0, osc_check: bool = False):
+        """Enqueue one batched render (no synchronisation)."""
+        self._prm = trace_params(max_steps, delta, t_far, osc_check)
+        _check(lib().ngl_render_batch(C.addressof(self.h_models), _ptr(self.table), C.addressof(self.views), self.n,
+                                      C.addressof(self._prm), self.capacity, _ptr(self.ws), self.ws.numel(),
+                                      _ptr(self.t), _ptr(self.status), _ptr(self.steps), _ptr(self.hit_vox),
+                                      _ptr(self.counts), _ptr(self.clock), _stream()))
+
+    def overflowed(self) -> bool:
+        return bool((self.counts[:, 1] > self.capacity).any().item())
+
+    def view_slice(self, i: int) -> slice:
+        return slice(int(self.base[i]), int(self.base[i + 1]))
+
+    def frame_ms(self):
+        """Per-view end time after the batch start (device wall clock, 100 MHz)."""
+        c = self.clock.cpu().numpy().astype(np.float64)
+        return (c[1:] - c[0]) * 1e-5
 
 
 # ---------------------------------------------------------------------------

@@ -25,3 +25,13 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture(params=[0, 1], ids=["f32-valu", "f32-mfma"])
+def f32_decoder(request):
+    """Runs a test with each FP32 decoder form (vector ALUs, matrix cores)."""
+    from paper_2101_10994_amd import ngl
+    old = ngl.get_option(ngl.OPT_F32_DECODER)
+    ngl.set_option(ngl.OPT_F32_DECODER, request.param)
+    yield request.param
+    ngl.set_option(ngl.OPT_F32_DECODER, old)

@@ -64,3 +64,16 @@ def test_device_calls_validate_before_launch():
     assert lib.ngl_trace_octree(C.addressof(m), None, None, 0, 7, 0, None, 0, None, None, None, None, None, None,
                                 None) == 1
     assert b"target_depth" in lib.ngl_last_error()
+
+
+def test_options():
+    from paper_2101_10994_amd import ngl
+    assert ngl.get_option(ngl.OPT_F32_DECODER) in (0, 1)
+    old = ngl.get_option(ngl.OPT_F32_DECODER)
+    ngl.set_option(ngl.OPT_F32_DECODER, 0)
+    assert ngl.get_option(ngl.OPT_F32_DECODER) == 0
+    ngl.set_option(ngl.OPT_F32_DECODER, old)
+    with pytest.raises(ngl.NGLError):
+        ngl.set_option(ngl.OPT_F32_DECODER, 7)
+    with pytest.raises(ngl.NGLError):
+        ngl.set_option(99, 0)

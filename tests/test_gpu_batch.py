@@ -1,0 +1,67 @@
+"""Batched persistent rendering: several models (different octree depths,
+cameras and LODs) traced by one launch.  Each view must equal the
+single-view path (camera rays, ray-octree intersection, sphere trace) bit
+for bit -- that path is the one checked against the oracle -- every ray must
+end, and the per-view clocks must be ordered."""
+import numpy as np
+import pytest
+
+from paper_2101_10994_amd import workloads as W
+
+from cases import make_case
+
+pytestmark = pytest.mark.gpu
+
+
+def batch_cases():
+    rs = W.rngs(11)
+    shapes = [W.tiny_shape(), W.paper_shape(0), W.random_union(rs[0], 4, 1), W.random_union(rs[1], 6, 2)]
+    lods = [3, 4, 2, 5]
+    cases = []
+    for s, L in zip(shapes, lods):
+        cases.append(make_case(s, 2 ** (L + 1), L, 32, 128, embedded=True, feat_dtype="f16", w_dtype="bf16"))
+    return cases
+
+
+@pytest.mark.parametrize("alphas", [(0.0, 0.0, 0.0, 0.0), (0.0, 0.5, 0.0, 0.25)])
+def test_batch_equals_single_view(alphas):
+    import torch
+    from paper_2101_10994_amd import ngl
+    cases = batch_cases()
+    models = [c.gpu_model() for c in cases]
+    rng = np.random.default_rng(3)
+    views = []
+    for i, c in enumerate(cases):
+        cam = W.camera_on_sphere(rng, 2.6, 96 + 16 * i, 80 + 8 * i)
+        lod = c.L if alphas[i] == 0.0 else c.L - 1
+        views.append(ngl.make_view(cam.eye, cam.width, cam.height, lod, alphas[i]))
+    br = ngl.BatchRenderer(models, views, pair_capacity=1 << 20)
+    br.status.fill_(255)
+    br.render(100, 1e-4)
+    torch.cuda.synchronize()
+    assert not br.overflowed()
+    assert int((br.status == 255).sum()) == 0
+    fm = br.frame_ms()
+    assert np.all(fm > 0)
+    for i, (m, v) in enumerate(zip(models, views)):
+        o, d = ngl.camera_rays(tuple(v.eye), (0, 0, 0), (0, 1, 0), 45.0, v.width, v.height)
+        depth = (v.lod + 1 if v.alpha > 0 else v.lod) + 1
+        hits = ngl.trace_octree(m, o, d, depth)
+        single = ngl.sphere_trace(m, o, d, v.lod, v.alpha, hits, 100, 1e-4)
+        sl = br.view_slice(i)
+        for key, out in (("t", br.t), ("status", br.status), ("steps", br.steps), ("hit_vox", br.hit_vox)):
+            a = single[key].cpu().numpy()
+            b = out[sl].cpu().numpy()
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (i, key)
+        assert int((single["status"] == ngl.HIT).sum()) > 100
+
+
+def test_batch_rejects_mixed_formats():
+    from paper_2101_10994_amd import ngl
+    cases = batch_cases()[:2]
+    m0 = cases[0].gpu_model()
+    c1 = make_case(W.tiny_shape(), 16, 3, 16, 64, feat_dtype="f16", w_dtype="bf16")
+    views = [ngl.make_view((0, 0, 2.5), 32, 32, 3), ngl.make_view((0, 0, 2.5), 32, 32, 3)]
+    br = ngl.BatchRenderer([m0, c1.gpu_model()], views, pair_capacity=1 << 16)
+    with pytest.raises(ngl.NGLError):
+        br.render(10, 1e-4)

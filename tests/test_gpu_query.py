@@ -35,14 +35,14 @@ def check(g, o, tol=TOL, scale="scale"):
 
 
 @pytest.mark.parametrize("lod", [1, 2, 3])
-def test_tiny_discrete_lods(lod):
+def test_tiny_discrete_lods(lod, f32_decoder):
     case = tiny_case()
     x = edge_points(case.ijk, 16, 3, np.random.default_rng(lod))
     g, o = run_both(case, x, lod)
     check(g, o)
 
 
-def test_tiny_blend_scalar_and_per_point():
+def test_tiny_blend_scalar_and_per_point(f32_decoder):
     case = tiny_case(sigma=0.2)
     rng = np.random.default_rng(7)
     x = edge_points(case.ijk, 16, 3, rng)
@@ -55,7 +55,7 @@ def test_tiny_blend_scalar_and_per_point():
 
 
 @pytest.mark.parametrize("fdt", ["f16", "bf16"])
-def test_tiny_half_features(fdt):
+def test_tiny_half_features(fdt, f32_decoder):
     """FP16/BF16 storage, FP32 arithmetic: same bound against the oracle
     evaluated on the same stored values."""
     case = tiny_case(sigma=0.2, feat_dtype=fdt)
@@ -64,14 +64,14 @@ def test_tiny_half_features(fdt):
     check(g, o)
 
 
-def test_tiny_without_xyz():
+def test_tiny_without_xyz(f32_decoder):
     case = tiny_case(sigma=0.2, with_xyz=False)
     x = edge_points(case.ijk, 16, 3, np.random.default_rng(12))
     g, o = run_both(case, x, 3)
     check(g, o)
 
 
-def test_paper_scale_sampled():
+def test_paper_scale_sampled(f32_decoder):
     """2^20 paper-scale queries (half uniform, half near-surface) on the GPU;
     the oracle checks a 65,536-point sample element by element."""
     import torch
@@ -89,7 +89,7 @@ def test_paper_scale_sampled():
     assert np.all(np.isfinite(g["sdf"]))
 
 
-def test_paper_scale_all_lods_and_blend():
+def test_paper_scale_all_lods_and_blend(f32_decoder):
     import torch
     from paper_2101_10994_amd import ngl
     case = paper_case(sigma=0.05)
@@ -106,7 +106,7 @@ def test_paper_scale_all_lods_and_blend():
     check(g, o)
 
 
-def test_empty_and_edge_sizes():
+def test_empty_and_edge_sizes(f32_decoder):
     import torch
     from paper_2101_10994_amd import ngl
     case = tiny_case()
