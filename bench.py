@@ -92,6 +92,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="approximate CPU-baseline budget")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 16-shape batched render")
     ap.add_argument("--only", choices=["query", "frame", "train", "half"], default=None,
                     help="run a single component (profiling)")
     args = ap.parse_args()
@@ -278,6 +279,9 @@ def main():
             roof = {"kernel": name, "bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None}
 
+    if args.only is None and not args.no_batch:
+        comp["batch"] = run_batch(dev, args.steps, args.warmup)
+
     cpu = None
     if not args.no_cpu and do_q:
         cpu = cpu_baseline(S, args.cpu_seconds)
@@ -292,6 +296,77 @@ def main():
                       "queries": cfg.n_query, "image": [W_, H_], "train_points": S["xt"].shape[1]},
            "roofline": roof, "cpu_baseline": cpu, "components": comp}
     print(json.dumps(out), flush=True)
+
+
+def run_batch(dev, steps, warmup):
+    """16 seeded shapes (3..7 LODs, FP16 features, BF16 decoders), one
+    512x512 view each at its own camera and LOD, traced by one persistent
+    launch per frame; launch shape picked by the autotuner; the frame is
+    captured in a graph and timed by replaying it."""
+    import torch
+    from paper_2101_10994_amd import autotune, ngl
+    from paper_2101_10994_amd import workloads as W
+    cfg = W.BATCH
+    t0 = time.perf_counter()
+    scene = W.batch_scene(0, 16, cfg.width, cfg.height)
+    models, views = [], []
+    for i, it in enumerate(scene):
+        L = it["num_lods"]
+        ijk = W.occupancy_ijk(it["shape"], 2 ** (L + 1))
+        tree = ngl.Octree(ijk, L, device=dev)
+        rs = W.rngs(100 + i)
+        feats = W.embedded_features(rs[W.STREAM_FEAT], it["shape"], tree.corner_positions(), cfg.feat_dim)
+        dec = W.embedded_decoders(rs[W.STREAM_DEC], L, cfg.feat_dim, cfg.hidden)
+        f32 = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+        models.append(ngl.Model(tree, [f32(f).half() for f in feats], [f32(w).bfloat16() for w in dec["W1"]],
+                                [f32(b) for b in dec["b1"]], [f32(w) for w in dec["w2"]], f32(dec["b2"])))
+        views.append(ngl.make_view(it["camera"].eye, cfg.width, cfg.height, it["lod"]))
+    setup_s = time.perf_counter() - t0
+    cap = 1 << 22
+    br = ngl.BatchRenderer(models, views, cap, dev)
+    br.render(cfg.max_steps, cfg.delta)
+    torch.cuda.synchronize()
+    while br.overflowed():
+        cap = max(2 * cap, int(br.counts[:, 1].max().item()))
+        br = ngl.BatchRenderer(models, views, cap, dev)
+        br.render(cfg.max_steps, cfg.delta)
+        torch.cuda.synchronize()
+    log("batch setup %.1fs, pair capacity %d" % (setup_s, cap))
+    tuned = autotune.tune("batch16x512-f16-bf16", lambda: br.render(cfg.max_steps, cfg.delta), fp32_model=False,
+                          repeats=3, use_cache=False)
+    log("autotuned batch launch: %s (%.3f ms)" % (tuned["config"], tuned["ms"]))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        br.render(cfg.max_steps, cfg.delta)
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(max(1, warmup)):
+        g.replay()
+    torch.cuda.synchronize()
+    ev = []
+    for _ in range(steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        g.replay()
+        b.record()
+        ev.append((a, b))
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    assert not br.overflowed(), "pair list overflowed during timing"
+    R = sum(cfg.width * cfg.height for _ in views)
+    status = br.status.cpu().numpy()
+    steps_arr = br.steps.cpu().numpy()
+    fm = br.frame_ms()
+    out = {"shapes": len(views), "image": [cfg.width, cfg.height], "lods": [it["num_lods"] for it in scene],
+           "view_lods": [it["lod"] for it in scene], "ms": ms, "rays": R, "rays_per_s": R / (ms * 1e-3),
+           "frame_ms_per_shape": [round(float(x), 4) for x in fm],
+           "visible_px": int((status == ngl.HIT).sum()), "sdf_evals": int(steps_arr.sum()),
+           "graph": True, "tuned": tuned["config"], "tuned_ms": tuned["ms"],
+           "untuned_ms": tuned.get("default_ms"), "setup_s": setup_s}
+    autotune.apply({"waves": 0, "blocks_per_cu": 0, "f32_decoder": 1})
+    return out
 
 
 def cpu_baseline(S, budget_s):

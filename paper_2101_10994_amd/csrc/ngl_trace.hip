@@ -38,7 +38,7 @@ struct TraceArgs {
 // so the loop ends.  All lanes of the wavefront reach the matrix-core decode
 // together (idle lanes stage zeros).
 template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, class DEC>
-__device__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLds<DEC>& S, float b2a, float b2b) {
+__device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLds<DEC>& S, float b2a, float b2b) {
   const int lane = threadIdx.x & 63;
   const int64_t R = A.R;
   const bool blend = A.alpha > 0.0f;
@@ -59,16 +59,17 @@ __device__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLd
   }
   bool exhausted = false;  // wave-uniform
   unsigned nfin = 0;       // rays this lane finished since the last report
-  auto finish = [&](uint8_t st, int32_t hv) {
-    const int64_t g = A.base + ray;
-    A.t_hit[g] = t;
-    A.status[g] = st;
-    A.steps[g] = k;
-    A.hit_vox[g] = hv;
-    ray = -1;
-    ready = false;
-    ++nfin;
-  };
+#define NGL_FINISH(st_, hv_)            \
+  do {                                  \
+    const int64_t g_ = A.base + ray;    \
+    A.t_hit[g_] = t;                    \
+    A.status[g_] = (st_);               \
+    A.steps[g_] = k;                    \
+    A.hit_vox[g_] = (hv_);              \
+    ray = -1;                           \
+    ready = false;                      \
+    ++nfin;                             \
+  } while (0)
   for (;;) {
     // 1. refill idle lanes and move every ray to an evaluable state
     for (int round = 0; round < 8; ++round) {
@@ -98,19 +99,19 @@ __device__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLd
             bool bad = false;
 #pragma unroll
             for (int a = 0; a < 3; ++a) bad = bad || !__builtin_isfinite(oo[a]) || !__builtin_isfinite(dd[a]);
-            if (bad) finish(NGL_RAY_INVALID, -1);
+            if (bad) NGL_FINISH(NGL_RAY_INVALID, -1);
           }
         }
       }
       if (ray >= 0 && !ready) {
         while (p < e && t > A.t_out[p]) ++p;  // empty space: next voxel
         if (p == e) {
-          finish(NGL_RAY_MISS, -1);
+          NGL_FINISH(NGL_RAY_MISS, -1);
         } else {
           const float ti = A.t_in[p];
           if (t < ti) t = ti;  // outside the voxel: jump to its entry
-          if (t > A.prm.t_far) finish(NGL_RAY_FAR, -1);
-          else if (k == A.prm.max_steps) finish(NGL_RAY_MAX_STEPS, -1);
+          if (t > A.prm.t_far) NGL_FINISH(NGL_RAY_FAR, -1);
+          else if (k == A.prm.max_steps) NGL_FINISH(NGL_RAY_MAX_STEPS, -1);
           else ready = true;
         }
       }
@@ -139,7 +140,7 @@ __device__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLd
           dist = sqrtf(q0 * q0 + q1 * q1 + q2 * q2) - A.prm.sphere[3];
         } else {
           if (v < 0 || int64_t(v) >= nv_t) {
-            finish(NGL_RAY_INVALID, -1);  // hit list does not belong to this depth
+            NGL_FINISH(NGL_RAY_INVALID, -1);  // hit list does not belong to this depth
           } else {
             if (p != cp) {
               // ancestor chain of the pair's voxel (parents always exist)
@@ -193,9 +194,9 @@ __device__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLd
       if (act && ray >= 0) {
         ++k;
         if (dist < A.prm.delta) {
-          finish(NGL_RAY_HIT, v);
+          NGL_FINISH(NGL_RAY_HIT, v);
         } else if (A.prm.osc_check && fabsf(dist - prev) < 6.0f * A.prm.delta) {
-          finish(NGL_RAY_STALLED, -1);
+          NGL_FINISH(NGL_RAY_STALLED, -1);
         } else {
           prev = dist;
           t += dist;
@@ -218,6 +219,8 @@ __device__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLd
     if (done) break;
   }
 }
+
+#undef NGL_FINISH
 
 template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW, class DEC>
 __global__ __launch_bounds__(64 * NW) void k_sphere_trace(ngl_model md, TraceArgs A) {

@@ -163,12 +163,13 @@ def surface_points(rng, shape: Shape, n: int) -> np.ndarray:
                 ring = big + small * np.cos(vv)
                 local = np.stack([ring * np.cos(uu), ring * np.sin(uu), small * np.sin(vv)], 1)
                 a = int(axis)
-                perm = {2: [0, 1, 2], 0: [2, 0, 1], 1: [0, 2, 1]}[a]
+                ax = [(1, 2), (0, 2), (0, 1)][a]
                 world = np.zeros_like(local)
-                # local z is the torus axis; map it onto world axis a
-                world[:, perm[0]] = local[:, 0]
-                world[:, perm[1]] = local[:, 1]
-                world[:, perm[2]] = local[:, 2]
+                # local z is the torus axis (world axis a); the ring lies in
+                # the plane of the other two axes, as in Shape.sdf
+                world[:, ax[0]] = local[:, 0]
+                world[:, ax[1]] = local[:, 1]
+                world[:, a] = local[:, 2]
                 pts[sel] = np.array([cx, cy, cz]) + world
         keep = np.abs(shape.sdf(pts)) <= 1e-9
         keep &= np.all(np.abs(pts) <= 1.0, axis=1)
@@ -360,3 +361,23 @@ def train_points(seed: int, shape: Shape, n: int):
 def soa(p: np.ndarray, dtype=np.float32) -> np.ndarray:
     """[n,3] -> contiguous [3][n]."""
     return np.ascontiguousarray(np.asarray(p).T.astype(dtype))
+
+
+# --------------------------------------------------------------------------
+# Batched rendering: 16 seeded shapes with 3..7 LODs
+# --------------------------------------------------------------------------
+BATCH = Config("batch16-3to7lod-m32-half", 0, 32, 128, 0, 512, 512, 100, 1e-4, feat_dtype="f16", w_dtype="bf16")
+
+
+def batch_scene(seed: int = 0, n: int = 16, width: int = 512, height: int = 512):
+    """n seeded sphere/torus unions; shape s has 3 + s % 5 LODs, a camera on a
+    radius-3 sphere looking at the origin, and renders at LOD num_lods - s % 2.
+    Returns a list of dicts (shape, num_lods, camera, lod)."""
+    r = rngs(seed)
+    out = []
+    for s in range(n):
+        L = 3 + s % 5
+        shape = random_union(r[STREAM_SHAPE], 2 + s % 5, 1 + s % 2)
+        cam = camera_on_sphere(r[STREAM_CAMERA], 3.0, width, height)
+        out.append(dict(shape=shape, num_lods=L, camera=cam, lod=max(1, L - s % 2)))
+    return out

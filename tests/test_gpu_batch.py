@@ -65,3 +65,59 @@ def test_batch_rejects_mixed_formats():
     br = ngl.BatchRenderer([m0, c1.gpu_model()], views, pair_capacity=1 << 16)
     with pytest.raises(ngl.NGLError):
         br.render(10, 1e-4)
+
+
+def test_graph_replay_matches_eager():
+    """The batched render captured in a graph replays to the eager result,
+    with eager work between replays."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    cases = batch_cases()
+    models = [c.gpu_model() for c in cases]
+    rng = np.random.default_rng(9)
+    views = []
+    for c in cases:
+        cam = W.camera_on_sphere(rng, 2.8, 64, 48)
+        views.append(ngl.make_view(cam.eye, cam.width, cam.height, c.L))
+    br = ngl.BatchRenderer(models, views, pair_capacity=1 << 18)
+    br.render(60, 1e-4)
+    torch.cuda.synchronize()
+    ref = {k: getattr(br, k).clone() for k in ("t", "status", "steps", "hit_vox")}
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        br.render(60, 1e-4)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        br.t.fill_(-1.0)
+        br.status.fill_(255)
+        br.steps.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, v in ref.items():
+            assert torch.equal(getattr(br, k), v), (rep, k)
+        assert np.all(br.frame_ms() >= 0)
+
+
+def test_autotuner_applies_a_valid_config(tmp_path):
+    import torch
+    from paper_2101_10994_amd import autotune, ngl
+    cases = batch_cases()[:2]
+    models = [c.gpu_model() for c in cases]
+    views = [ngl.make_view((0.3, 0.2, 2.6), 64, 64, c.L) for c in cases]
+    br = ngl.BatchRenderer(models, views, pair_capacity=1 << 18)
+    saved = autotune.current()
+    try:
+        res = autotune.tune("test-batch", lambda: br.render(40, 1e-4), fp32_model=False, repeats=1,
+                            path=str(tmp_path / "tune.json"))
+        assert res["config"] == autotune.current()
+        assert len(res["trials"]) >= 9 and res["ms"] > 0
+        again = autotune.tune("test-batch", lambda: br.render(40, 1e-4), fp32_model=False,
+                              path=str(tmp_path / "tune.json"))
+        assert again["cached"] and again["config"] == res["config"]
+        br.render(40, 1e-4)
+        torch.cuda.synchronize()
+    finally:
+        autotune.apply(saved)
