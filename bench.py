@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="approximate CPU-baseline budget")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-shape batched render")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, run one plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--only", choices=["query", "frame", "train", "half"], default=None,
                     help="run a single component (profiling)")
     args = ap.parse_args()
@@ -279,6 +281,15 @@ def main():
             roof = {"kernel": name, "bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None}
 
+    if args.calibrate_copy:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
+        # calibrate the HBM-traffic counters of the kernels above
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.only is None and not args.no_batch:
         comp["batch"] = run_batch(dev, args.steps, args.warmup)
 
