@@ -14,6 +14,8 @@ Entry points and the passage each one follows:
 * ``camera_rays``     -- pinhole primary rays (the ray set of Alg. 1)
 * ``sphere_trace``    -- adaptive-stepping sphere tracing (Sec. 3.4, Fig. 3;
                          stopping rules of App. A.4)
+* ``normals``         -- surface normals by central finite differences of
+                         ``query`` (App. A.4), at points or ray hit points
 * ``train_fwd_bwd``   -- Eq. 4 loss and its gradient (Sec. 3.3)
 
 Every entry point is pinned by CPU tests against closed forms, brute force
@@ -220,6 +222,67 @@ def query(tree: Octree, model: Model, x_soa: np.ndarray, lod: int, alpha: float 
     if rc != 0:
         raise ValueError("oracle query: invalid arguments")
     return dict(sdf=sdf, scale=scale, scale1=scale1, valid=valid, vox=vox)
+
+
+def fma_f32(a, b, c):
+    """a*b + c for float32 arrays, rounded once to float32 (IEEE fused
+    multiply-add, round to nearest even)."""
+    a64 = np.asarray(a, np.float32).astype(np.float64)
+    b64 = np.asarray(b, np.float32).astype(np.float64)
+    c64 = np.asarray(c, np.float32).astype(np.float64)
+    p = a64 * b64                      # exact: 24 + 24 bits fit in 53
+    s = p + c64
+    bv = s - p                         # two-sum: s + e == p + c exactly
+    e = (p - (s - bv)) + (c64 - bv)
+    r = s.astype(np.float32)
+    # s rounds like the exact sum unless s is a float32 midpoint and e != 0.
+    toward = np.where(s > r.astype(np.float64), np.float32(np.inf), np.float32(-np.inf)).astype(np.float32)
+    r2 = np.nextafter(r, toward)
+    mid = (r.astype(np.float64) + r2.astype(np.float64)) * 0.5
+    tie = (s == mid) & (e != 0.0) & (s != r.astype(np.float64))
+    pick2 = tie & ((e > 0.0) == (r2 > r))
+    return np.where(pick2, r2, r).astype(np.float32)
+
+
+def normals(tree: Octree, model: Model, lod: int, alpha: float, h: float, x_soa=None, rays=None):
+    """Unit surface normals by central differences (App. A.4 names finite
+    differences; the central form and the step h are this library's
+    reading).  For each point x and axis a, f(x + h e_a) and f(x - h e_a)
+    are SDF values at LOD lod (+alpha) of the float32 points x_a +- h, and
+    g_a = (f+ - f-) / (2h); the normal is g / |g| (zero when |g| = 0).
+    With rays = (o, d, t_hit, status) the points are fma(t_hit, d, o) for
+    rays with status HIT, zero normals elsewhere.  Also returns g and
+    per-axis (scale, scale1) sums of the six queries for error bounds."""
+    h32 = np.float32(h)
+    if rays is not None:
+        o, d, t, st = rays
+        o = _c(o, np.float32)
+        d = _c(d, np.float32)
+        t = np.asarray(t, np.float32)
+        x = np.stack([fma_f32(t, d[a], o[a]) for a in range(3)])
+        act = np.asarray(st) == HIT
+    else:
+        x = _c(x_soa, np.float32)
+        act = np.ones(x.shape[1], bool)
+    Pn = x.shape[1]
+    g = np.zeros((3, Pn))
+    fsum = np.zeros((3, Pn))
+    ssum = np.zeros((3, Pn))
+    s1sum = np.zeros((3, Pn))
+    for a in range(3):
+        for sgn in (1.0, -1.0):
+            xs = x.copy()
+            xs[a] = (x[a] + np.float32(sgn) * h32).astype(np.float32)
+            q = query(tree, model, xs, lod, alpha)
+            g[a] += sgn * q["sdf"]
+            fsum[a] += np.abs(q["sdf"])
+            ssum[a] += q["scale"]
+            s1sum[a] += q["scale1"]
+    g /= 2.0 * float(h32)
+    g[:, ~act] = 0.0
+    ln = np.sqrt((g * g).sum(0))
+    n = np.where(ln > 0.0, g / np.where(ln > 0.0, ln, 1.0), 0.0)
+    return dict(n=n, g=g, points=x, active=act, fsum=fsum, scale=ssum, scale1=s1sum)
 
 
 def ray_box(o, d, depth, cell):
