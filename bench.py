@@ -149,7 +149,10 @@ def main():
                 steps=torch.empty(R, dtype=torch.int32, device=dev),
                 hit_vox=torch.empty(R, dtype=torch.int32, device=dev))
     tq, tc, tt, ts, ttr = Timer(), Timer(), Timer(), Timer(), Timer()
-    thq, ths = Timer(), Timer()
+    thq, ths, tn, thn = Timer(), Timer(), Timer(), Timer()
+    h_fd = ngl.default_normal_step(model)
+    nrm = torch.empty((3, R), dtype=torch.float32, device=dev)
+    nrm_h = torch.empty((3, R), dtype=torch.float32, device=dev)
     half = S["half"]
     sdf_h = torch.empty(cfg.n_query, dtype=torch.float32, device=dev)
     tr_h = dict(t=torch.empty(R, dtype=torch.float32, device=dev),
@@ -172,10 +175,13 @@ def main():
                     ngl.trace_octree_into(model, o, d, lod + 1, buf)
                 with ts:
                     ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr)
+                with tn:
+                    ngl.sdf_normals(model, lod, 0.0, h_fd, rays=(o, d, tr["t"], tr["status"]), out=nrm)
             else:
                 ngl.camera_rays(eye, (0, 0, 0), (0, 1, 0), 45.0, W_, H_, out=(o, d))
                 ngl.trace_octree_into(model, o, d, lod + 1, buf)
                 ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr)
+                ngl.sdf_normals(model, lod, 0.0, h_fd, rays=(o, d, tr["t"], tr["status"]), out=nrm)
         if do_v:
             # FP32 decoder on the vector ALUs (the per-lane form), for comparison
             ngl.set_option(ngl.OPT_F32_DECODER, 0)
@@ -198,9 +204,12 @@ def main():
                     ngl.query_sdf(half, S["xq"], lod, out=sdf_h)
                 with ths:
                     ngl.sphere_trace(half, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_h)
+                with thn:
+                    ngl.sdf_normals(half, lod, 0.0, h_fd, rays=(o, d, tr_h["t"], tr_h["status"]), out=nrm_h)
             else:
                 ngl.query_sdf(half, S["xq"], lod, out=sdf_h)
                 ngl.sphere_trace(half, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_h)
+                ngl.sdf_normals(half, lod, 0.0, h_fd, rays=(o, d, tr_h["t"], tr_h["status"]), out=nrm_h)
         if do_t:
             if timed:
                 with ttr:
@@ -233,10 +242,11 @@ def main():
     if do_f:
         status = tr["status"].cpu().numpy()
         steps_arr = tr["steps"].cpu().numpy()
-        frame_ms = mean(tc) + mean(tt) + mean(ts)
+        frame_ms = mean(tc) + mean(tt) + mean(ts) + mean(tn)
         n_eval = int(steps_arr.sum())
         comp["frame"] = {"ms": frame_ms, "fps": 1e3 / frame_ms, "rays_per_s": R / (frame_ms * 1e-3),
                          "camera_ms": mean(tc), "traverse_ms": mean(tt), "trace_ms": mean(ts),
+                         "normals_ms": mean(tn), "normal_step": h_fd,
                          "visible_px": int((status == ngl.HIT).sum()), "rays_with_voxels": int(
                              (buf.ray_off[1:] > buf.ray_off[:-1]).sum()),
                          "final_pairs": int(buf.counts[0]), "sdf_evals": n_eval,
@@ -249,7 +259,8 @@ def main():
                              "query_ms": hq_ms, "queries_per_s": cfg.n_query / (hq_ms * 1e-3),
                              "trace_ms": hs_ms, "sdf_evals": n_eval_h, "sdf_evals_per_s": n_eval_h / (hs_ms * 1e-3),
                              "visible_px": int((st_h == ngl.HIT).sum()),
-                             "frame_ms": (mean(tc) + mean(tt) + hs_ms) if do_f else None}
+                             "normals_ms": mean(thn),
+                             "frame_ms": (mean(tc) + mean(tt) + hs_ms + mean(thn)) if do_f else None}
         if do_q:
             comp["bf16_form"]["max_abs_diff_vs_fp32"] = float((sdf_h - sdf).abs().max())
     if do_v:
@@ -302,7 +313,7 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "f32_decoder": ["vector ALU", "matrix cores (v_mfma_f32_16x16x4f32)"][f32_mode],
            "config": {"workload": "union8s1t-5lod-m32: 2^20 queries at LOD 5 + 1024x1024 frame "
-                                  "(<=100 steps, delta 1e-4)" + (" + 2^19-point train step" if do_t else ""),
+                                  "(<=100 steps, delta 1e-4, FD normals at hits)" + (" + 2^19-point train step" if do_t else ""),
                       "lods": cfg.num_lods, "feat_dim": cfg.feat_dim, "hidden": cfg.hidden,
                       "queries": cfg.n_query, "image": [W_, H_], "train_points": S["xt"].shape[1]},
            "roofline": roof, "cpu_baseline": cpu, "components": comp}
@@ -415,11 +426,13 @@ def cpu_baseline(S, budget_s):
     d = np.ascontiguousarray(cd[:, idx].astype(np.float32))
     t0 = time.perf_counter()
     hits = oracle.trace_octree(otree, o, d, cfg.num_lods + 1)
-    oracle.sphere_trace(otree, om, o, d, cfg.num_lods, 0.0, hits, cfg.max_steps, cfg.delta)
+    r = oracle.sphere_trace(otree, om, o, d, cfg.num_lods, 0.0, hits, cfg.max_steps, cfg.delta)
+    h_fd = 2.0 / (4 << (cfg.num_lods - 1)) / 16.0
+    oracle.normals(otree, om, cfg.num_lods, 0.0, h_fd, rays=(o, d, r["t"].astype(np.float32), r["status"]))
     frame_s = (time.perf_counter() - t0) * stride
     out = {"value": qps, "unit": "queries/s", "cores": cores, "kind": "oracle",
            "sample": "%d of the 2^20 queries at LOD 5; frame from every %dth ray of the 1024^2 camera "
-                     "(traversal + trace), scaled x%d" % (n, stride, stride),
+                     "(traversal + trace + normals), scaled x%d" % (n, stride, stride),
            "fps_1024": 1.0 / frame_s, "octree_build_s": build_s}
     # training step on a sample
     nt = 8192

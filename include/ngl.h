@@ -172,6 +172,18 @@ typedef struct {
 int ngl_query_sdf(const ngl_model* m, const float* x, int64_t P, int32_t lod, float alpha,
                   const float* alpha_pp, float* sdf, uint8_t* valid, int32_t* vox_out, void* stream);
 
+/* Surface normals by central differences (App. A.4: normals are obtained by
+ * finite differences).  For each point x_p (device x[3][P]) the gradient
+ * g_a = (f(x + h e_a) - f(x - h e_a)) / (2h) of f = the SDF of
+ * ngl_query_sdf at LOD lod (+alpha) is evaluated with six queries and
+ * normals[3][P] (device) receives g / |g| (0 if |g| = 0).  With status
+ * non-null the points are the hit points of rays instead: x = o + t_hit d
+ * for rays whose status is NGL_RAY_HIT (o, d: [3][P], t_hit, status: [P]);
+ * other rays get the zero vector.  h > 0. */
+int ngl_sdf_normals(const ngl_model* m, const float* x, const float* o, const float* d, const float* t_hit,
+                    const uint8_t* status, int64_t P, int32_t lod, float alpha, float h, float* normals,
+                    void* stream);
+
 /* All discrete LODs at once: sdf_all[L][P] (device) with sdf_all[L-1][p] =
  * f_{theta_L}([x_p, z_L(x_p)]) for L = 1..num_lods (the forward of Eq. 4). */
 int ngl_query_sdf_all_lods(const ngl_model* m, const float* x, int64_t P, float* sdf_all, void* stream);

@@ -185,6 +185,134 @@ static int launch_query_mfma(const ngl_model& md, const float* x, int64_t P, int
                                                   fixed + DEC::STAGE_BYTES);
 }
 
+// Central-difference normals: six queries per point.  MFMA selects the
+// matrix-core decoder (every lane joins each of the six decodes).
+struct NormalArgs {
+  const float* x;       // points [3][P], or null with rays below
+  const float* o;
+  const float* d;
+  const float* t_hit;
+  const uint8_t* status;
+  int64_t P;
+  int lod;
+  float alpha;
+  float h;
+  float* normals;       // [3][P]
+};
+
+template <int M, typename FT, bool XYZ>
+__device__ inline void query_z(const ngl_model& md, const float x[3], int lod, bool blend, float* z, float* zn) {
+  const int Lp = blend ? lod + 1 : lod;
+  int vox[NGL_MAX_LODS];
+  int cx, cy, cz, vlast, vn;
+  locate<NGL_MAX_LODS>(md, x, Lp, vox, &cx, &cy, &cz, &vlast, lod + 1, &vn);
+#pragma unroll
+  for (int k = 0; k < M; ++k) z[k] = 0.0f;
+#pragma unroll
+  for (int l = 1; l <= NGL_MAX_LODS; ++l)
+    if (l <= lod && vox[l - 1] >= 0)
+      interp_level<M, FT>(md, l, vox[l - 1], cx >> (Lp - l), cy >> (Lp - l), cz >> (Lp - l), x, z);
+  if (blend) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) zn[k] = z[k];
+    if (vn >= 0) interp_level<M, FT>(md, lod + 1, vn, cx, cy, cz, x, zn);
+  }
+}
+
+template <int M, typename FT, bool XYZ, int NW, class DEC, bool MFMA>
+__global__ __launch_bounds__(64 * NW) void k_normals(ngl_model md, NormalArgs A) {
+  extern __shared__ __align__(16) char smem[];
+  const int H = md.hidden;
+  const bool blend = A.alpha > 0.0f;
+  DecLds<DEC> S(smem, H, blend && MFMA);
+  if constexpr (MFMA) {
+    DEC::load(md, A.lod, S.frag0, S.w2s0);
+    if (blend) DEC::load(md, A.lod + 1, S.frag1, S.w2s1);
+    __syncthreads();
+  }
+  const float b2a = md.b2[A.lod - 1];
+  const float b2b = blend ? md.b2[A.lod] : 0.0f;
+  const int64_t P = A.P;
+  for (int64_t base = int64_t(blockIdx.x) * (64 * NW); base < P; base += int64_t(gridDim.x) * (64 * NW)) {
+    const int64_t p = base + threadIdx.x;
+    bool act = p < P;
+    float x0[3] = {0.0f, 0.0f, 0.0f};
+    if (act) {
+      if (A.status) {
+        act = A.status[p] == NGL_RAY_HIT;
+        const float t = A.t_hit[p];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x0[a] = fmaf(t, A.d[a * P + p], A.o[a * P + p]);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x0[a] = A.x[a * P + p];
+      }
+    }
+    float g[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int a = e >> 1;
+      const float sgn = (e & 1) ? -1.0f : 1.0f;
+      float x[3] = {x0[0], x0[1], x0[2]};
+      x[a] = x0[a] + sgn * A.h;
+      float z[M], zn[M];
+      query_z<M, FT, XYZ>(md, x, A.lod, blend, z, zn);
+      float f;
+      if constexpr (MFMA) {
+        DEC::stage(S.stage, x, z);
+        wave_lds_sync();
+        f = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H);
+        if (blend) {
+          wave_lds_sync();
+          DEC::stage(S.stage, x, zn);
+          wave_lds_sync();
+          f = (1.0f - A.alpha) * f + A.alpha * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H);
+        }
+        wave_lds_sync();
+      } else {
+        f = decode_f32<M, XYZ>(md, A.lod, x, z);
+        if (blend) f = (1.0f - A.alpha) * f + A.alpha * decode_f32<M, XYZ>(md, A.lod + 1, x, zn);
+      }
+      g[a] += sgn * f;
+    }
+    if (p < P) {
+      float n[3] = {0.0f, 0.0f, 0.0f};
+      if (act) {
+        const float inv2h = 0.5f / A.h;
+        const float gx = g[0] * inv2h, gy = g[1] * inv2h, gz = g[2] * inv2h;
+        const float len = sqrtf(gx * gx + gy * gy + gz * gz);
+        if (len > 0.0f) {
+          n[0] = gx / len;
+          n[1] = gy / len;
+          n[2] = gz / len;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) A.normals[a * P + p] = n[a];
+    }
+  }
+}
+
+template <int M, typename FT, bool XYZ, class DEC, bool MFMA>
+static int launch_normals(const ngl_model& md, const NormalArgs& A, hipStream_t s) {
+  const bool blend = A.alpha > 0.0f;
+  const size_t lds = MFMA ? DecLds<DEC>::fixed_bytes(md.hidden, blend) + 2 * DEC::STAGE_BYTES : 0;
+  int64_t grid = (A.P + 127) / 128;
+  if (grid > 4096) grid = 4096;
+  k_normals<M, FT, XYZ, 2, DEC, MFMA><<<unsigned(grid), 128, lds, s>>>(md, A);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+template <int M, typename FT, bool XYZ>
+struct NormalOp {
+  static int run(const ngl_model& md, const NormalArgs& A, hipStream_t s) {
+    if (md.w_dtype == NGL_BF16) return launch_normals<M, FT, XYZ, DecBF16<M, XYZ>, true>(md, A, s);
+    if (option(NGL_OPT_F32_DECODER) == 1) return launch_normals<M, FT, XYZ, DecF32<M, XYZ>, true>(md, A, s);
+    return launch_normals<M, FT, XYZ, DecF32<M, XYZ>, false>(md, A, s);
+  }
+};
+
 template <int M, typename FT, bool XYZ>
 static int launch_query(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app,
                         float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s) {
@@ -269,6 +397,23 @@ int ngl_query_sdf_all_lods(const ngl_model* m, const float* x, int64_t P, float*
   NGL_REQUIRE(x && sdf_all, "x or sdf_all is null");
   if (m->w_dtype != NGL_F32) NGL_FAIL(NGL_E_UNSUPPORTED, "all-LOD queries need FP32 decoder weights");
   return ngl::dispatch<ngl::QueryAllOp>(*m, x, P, sdf_all, (hipStream_t)stream);
+}
+
+int ngl_sdf_normals(const ngl_model* m, const float* x, const float* o, const float* d, const float* t_hit,
+                    const uint8_t* status, int64_t P, int32_t lod, float alpha, float h, float* normals,
+                    void* stream) {
+  int rc = ngl::check_model(m, true);
+  if (rc) return rc;
+  NGL_REQUIRE(P >= 0, "negative point count");
+  NGL_REQUIRE(lod >= 1 && lod <= m->num_lods, "lod %d outside 1..%d", lod, m->num_lods);
+  NGL_REQUIRE(alpha >= 0.0f && alpha < 1.0f, "alpha must be in [0,1)");
+  NGL_REQUIRE(!(alpha > 0.0f) || lod < m->num_lods, "blending needs lod < num_lods");
+  NGL_REQUIRE(h > 0.0f, "h must be positive");
+  if (P == 0) return NGL_OK;
+  NGL_REQUIRE(normals != nullptr, "normals is null");
+  NGL_REQUIRE(status ? (o && d && t_hit) : (x != nullptr), "points, or rays with t_hit and status, are required");
+  ngl::NormalArgs A{status ? nullptr : x, o, d, t_hit, status, P, int(lod), alpha, h, normals};
+  return ngl::dispatch<ngl::NormalOp>(*m, A, (hipStream_t)stream);
 }
 
 }  // extern "C"

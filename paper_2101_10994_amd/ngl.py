@@ -74,6 +74,7 @@ EXPORTS = {
     "ngl_octree_fill": (C.c_int, [P, i64, i32, P]),
     "ngl_query_sdf": (C.c_int, [P, P, i64, i32, C.c_float, P, P, P, P, P]),
     "ngl_query_sdf_all_lods": (C.c_int, [P, P, i64, P, P]),
+    "ngl_sdf_normals": (C.c_int, [P, P, P, P, P, P, i64, i32, C.c_float, C.c_float, P, P]),
     "ngl_camera_rays": (C.c_int, [P, P, P, C.c_float, i32, i32, P, P, P]),
     "ngl_trace_octree_workspace": (C.c_int, [i64, i64, P]),
     "ngl_trace_octree": (C.c_int, [P, P, P, i64, i32, i64, P, C.c_size_t, P, P, P, P, P, P, P]),
@@ -317,6 +318,36 @@ def query_sdf_all_lods(model: Model, x: torch.Tensor, out: torch.Tensor = None) 
     o = out if out is not None else torch.empty((model.num_lods, Pn), dtype=torch.float32, device=x.device)
     _check(lib().ngl_query_sdf_all_lods(model.ref, _ptr(x), Pn, _ptr(o), _stream()))
     return o
+
+
+def default_normal_step(model: "Model") -> float:
+    """Finite-difference step: 1/16 of the finest voxel's edge."""
+    return 2.0 / (4 << (model.num_lods - 1)) / 16.0
+
+
+def sdf_normals(model: Model, lod: int, alpha: float = 0.0, h: float = None, x: torch.Tensor = None,
+                rays=None, out: torch.Tensor = None) -> torch.Tensor:
+    """Unit normals [3][P] by central differences of the SDF at LOD lod
+    (+alpha), either at points x [3][P] or at the hit points of rays =
+    (o, d, t_hit, status) (zero for rays that did not hit)."""
+    h = default_normal_step(model) if h is None else h
+    if rays is not None:
+        o, d, t_hit, status = rays
+        for a in (o, d):
+            _dev(a, torch.float32)
+        _dev(t_hit, torch.float32)
+        _dev(status, torch.uint8)
+        Pn = t_hit.shape[0]
+        dev = t_hit.device
+        args = (None, _ptr(o), _ptr(d), _ptr(t_hit), _ptr(status))
+    else:
+        _dev(x, torch.float32)
+        Pn = x.shape[1]
+        dev = x.device
+        args = (_ptr(x), None, None, None, None)
+    n = out if out is not None else torch.empty((3, Pn), dtype=torch.float32, device=dev)
+    _check(lib().ngl_sdf_normals(model.ref, *args, Pn, int(lod), float(alpha), float(h), _ptr(n), _stream()))
+    return n
 
 
 # ---------------------------------------------------------------------------

@@ -60,6 +60,7 @@ def test_device_calls_validate_before_launch():
     m = ngl.ngl_model()
     m.num_lods = 0
     assert lib.ngl_query_sdf(C.addressof(m), None, 0, 1, 0.0, None, None, None, None, None) == 1
+    assert lib.ngl_sdf_normals(C.addressof(m), None, None, None, None, None, 0, 1, 0.0, 0.01, None, None) == 1
     m.num_lods = 2
     assert lib.ngl_trace_octree(C.addressof(m), None, None, 0, 7, 0, None, 0, None, None, None, None, None, None,
                                 None) == 1
