@@ -30,7 +30,50 @@ if ROOT not in sys.path:
 
 METRIC = "octree SDF queries/s, 1024^2 sphere-trace fps, fwd+bwd points/s at fixed err"
 HBM_PEAK_GBS = 8000.0
-FP32_VALU_PEAK_TFLOPS = 78.6   # non-packed FP32 FMA: 256 CU x 64 lanes/clk x 2 flop x 2.4 GHz
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 (packed vector / matrix) peak
+
+# Algorithmic work per SDF evaluation at LOD 5 with m = 32, h = 128:
+# gather 5 levels x (8 corner rows x 32 x 4 B + 8 corner ids x 4 B) = 5,280 B;
+# a query adds its 12 B point and 4 B result, a trace step about 28 B of
+# ray/pair state.  Flops: trilinear 5 x 8 x 32 x 2 + decoder 2 x (35 x 128 +
+# 128) + 2 x 128.
+GATHER_BYTES = 5 * (8 * 32 * 4 + 8 * 4)
+QUERY_BYTES = GATHER_BYTES + 16
+TRACE_STEP_BYTES = GATHER_BYTES + 28
+EVAL_FLOPS = 5 * 8 * 32 * 2 + 2 * (35 * 128 + 128) + 2 * 128
+
+# HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
+# of this bench (KiB per dispatch), each scaled by the reading of the same
+# counter for a plain 256 MiB device copy (FETCH_SIZE reads 131,088 KiB,
+# WRITE_SIZE 262,144 KiB).  Valid only while the kernel's sources hash to
+# the recorded value; otherwise traffic is reported as null.
+COUNTERS = {
+    "k_sphere_trace": {"sources": ["ngl_trace.hip", "ngl_device.h", "ngl_mfma.h"],
+                       "sha256": "6f0aed9ffa81e08fb77a9f7c4567bd2b4535dff30590bc36ed21e1a87555a8ea",
+                       "fetch_kib": 643103.9, "write_kib": 40544.5},
+    "k_query": {"sources": ["ngl_query.hip", "ngl_device.h", "ngl_mfma.h"],
+                "sha256": "df9f1c2b5be0f28378f97e732e9dcc0176f1f6b1666d84b627e719d4e083baa8",
+                "fetch_kib": 114441.0, "write_kib": 4096.0},
+}
+FETCH_SCALE = (256 << 10) / 131088.125
+WRITE_SCALE = (256 << 10) / 262144.0
+
+
+def sources_sha256(names):
+    import hashlib
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2101_10994_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """Calibrated HBM bytes per launch, or None if the sources changed."""
+    c = COUNTERS.get(kernel)
+    if c is None or sources_sha256(c["sources"]) != c["sha256"]:
+        return None
+    return (c["fetch_kib"] * FETCH_SCALE + c["write_kib"] * WRITE_SCALE) * 1024.0
 
 
 def log(*a):
@@ -271,26 +314,29 @@ def main():
         tr_ms = mean(ttr)
         comp["train"] = {"ms": tr_ms, "points_per_s": S["xt"].shape[1] / (tr_ms * 1e-3), "points": S["xt"].shape[1]}
 
-    # Roofline of the dominant kernel (largest time in the step).
+    # Roofline of the dominant kernel (largest time in the step): the
+    # feature gather is priced against HBM with its algorithmic bytes; the
+    # measured HBM traffic of the same launch and the FP32 flop rate are
+    # reported beside it.
     roof = None
     cand = []
     if do_q:
-        # algorithmic work per query at LOD 5 with m=32, h=128:
-        # gather 5 levels x (8 corner rows x 32 x 4 B + 8 x 4 B corner ids) + 12 B point + 4 B result;
-        # flops: trilinear 5 x 8 x 32 x 2 + decoder 2 x (35 x 128 + 128) + 2 x 128
-        q_flops = 5 * 8 * 32 * 2 + 2 * (35 * 128 + 128) + 2 * 128
-        cand.append(("k_query", comp["query"]["ms"], q_flops * cfg.n_query))
+        cand.append(("k_query", comp["query"]["ms"], QUERY_BYTES * cfg.n_query, EVAL_FLOPS * cfg.n_query))
+        comp["query"]["algorithmic_GBps"] = QUERY_BYTES * cfg.n_query / (comp["query"]["ms"] * 1e6)
+        comp["query"]["hbm_traffic_bytes"] = measured_traffic("k_query")
     if do_f:
-        cand.append(("k_sphere_trace", comp["frame"]["trace_ms"],
-                     (5 * 8 * 32 * 2 + 2 * (35 * 128 + 128) + 2 * 128) * comp["frame"]["sdf_evals"]))
+        ev = comp["frame"]["sdf_evals"]
+        cand.append(("k_sphere_trace", comp["frame"]["trace_ms"], TRACE_STEP_BYTES * ev, EVAL_FLOPS * ev))
     if do_t:
-        cand.append(("train", comp["train"]["ms"], None))
+        cand.append(("train", comp["train"]["ms"], None, None))
     if cand:
-        name, ms, flops = max(cand, key=lambda c: c[1])
-        if flops is not None:
-            ach = flops / (ms * 1e-3) / 1e12
-            roof = {"kernel": name, "bound": "alu", "achieved": ach, "peak": FP32_VALU_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": ach / FP32_VALU_PEAK_TFLOPS, "traffic": None}
+        name, ms, nbytes, flops = max(cand, key=lambda c: c[1])
+        if nbytes is not None:
+            ach = nbytes / (ms * 1e-3) / 1e9
+            tfl = flops / (ms * 1e-3) / 1e12
+            roof = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(name),
+                    "algorithmic_bytes": nbytes, "fp32_tflops": tfl, "fp32_frac": tfl / FP32_PEAK_TFLOPS}
 
     if args.calibrate_copy:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
