@@ -10,6 +10,7 @@ Entry points and the passage each one follows:
 
 * ``Octree``          -- sparse voxel octree from occupancy (Sec. 3.2; App. A.1)
 * ``query``           -- SDF at LOD L (Eq. 2) or continuous L+alpha (Eq. 3)
+* ``decode``          -- the per-LOD decoder of Eq. 2 alone, on given [x, z]
 * ``trace_octree``    -- ray-octree hit lists (Sec. 3.4, Alg. 1, App. C)
 * ``camera_rays``     -- pinhole primary rays (the ray set of Alg. 1)
 * ``sphere_trace``    -- adaptive-stepping sphere tracing (Sec. 3.4, Fig. 3;
@@ -85,6 +86,8 @@ def _setup(lib):
     lib.orc_octree_counts.argtypes = [P, P, P]
     lib.orc_octree_export_depth.argtypes = [P, C.c_int, P, P, P, P]
     lib.orc_octree_export_corners.argtypes = [P, C.c_int, P, P]
+    lib.orc_decode.restype = C.c_int
+    lib.orc_decode.argtypes = [P, C.c_int, P, P, i64, P, P, P]
     lib.orc_query.restype = C.c_int
     lib.orc_query.argtypes = [P, P, P, i64, C.c_int, C.c_double, P, P, P, P, P, P]
     lib.orc_ray_box.restype = C.c_int
@@ -222,6 +225,20 @@ def query(tree: Octree, model: Model, x_soa: np.ndarray, lod: int, alpha: float 
     if rc != 0:
         raise ValueError("oracle query: invalid arguments")
     return dict(sdf=sdf, scale=scale, scale1=scale1, valid=valid, vox=vox)
+
+
+def decode(model: Model, lod: int, z, x_soa=None):
+    """Decoder `lod` (Eq. 2's MLP) on inputs z [P][m] (float64 values) and
+    x [3][P] float32.  Returns dict(sdf, scale, scale1)."""
+    zz = _c(z, np.float64)
+    Pn = zz.shape[0]
+    x = _c(x_soa if x_soa is not None else np.zeros((3, Pn)), np.float32)
+    sdf, scale, scale1 = np.zeros(Pn), np.zeros(Pn), np.zeros(Pn)
+    ms = model.struct()
+    rc = _load().orc_decode(C.addressof(ms), int(lod), _ptr(x), _ptr(zz), Pn, _ptr(sdf), _ptr(scale), _ptr(scale1))
+    if rc != 0:
+        raise ValueError("oracle decode: invalid arguments")
+    return dict(sdf=sdf, scale=scale, scale1=scale1)
 
 
 def fma_f32(a, b, c):

@@ -314,6 +314,28 @@ static double decode(const orc_model* M, int L, const double x[3], const double*
 }
 
 /*
+ * Decoder only (Eq. 2's MLP of LOD `lod`) on given inputs: x SoA [3][P]
+ * float (ignored without the position input), z [P][m] double rows.
+ * Outputs sdf[P] and the two magnitude scales of decode (nullable).
+ * Returns 0, or -1 on invalid arguments.
+ */
+int orc_decode(const orc_model* M, int lod, const float* xs, const double* zs, int64_t P, double* sdf,
+               double* scale, double* scale1) {
+  if (lod < 1 || lod > M->num_lods) return -1;
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < P; ++p) {
+    double x[3] = {0.0, 0.0, 0.0};
+    if (M->with_xyz)
+      for (int a = 0; a < 3; ++a) x[a] = xs[(size_t)a * (size_t)P + (size_t)p];
+    double s0, s1;
+    sdf[p] = decode(M, lod, x, zs + (size_t)p * (size_t)M->m, &s0, &s1);
+    if (scale) scale[p] = s0;
+    if (scale1) scale1[p] = s1;
+  }
+  return 0;
+}
+
+/*
  * SDF query (Sec. 3.2 Eq. 2, blended per Eq. 3).
  *   x: SoA [3][P] float; lod in 1..Lmax; alpha in [0,1) applies to all points
  *   unless alpha_pp (nullable, [P]) is given.  alpha > 0 needs lod < Lmax.

@@ -211,3 +211,43 @@ def test_error_scales_bound_the_result():
         o = oracle.query(t, mdl, x, lod, alpha=a)
         assert np.all(np.abs(o["sdf"]) <= o["scale"] * (1 + 1e-12))
         assert np.all(o["scale"] <= o["scale1"] * (1 + 1e-12))
+
+
+def test_decode_alone_matches_query_at_lattice_points():
+    """At a level's lattice points inside occupied voxels z is the stored
+    corner feature itself, so the decoder applied to that feature reproduces
+    the query (one level only: the other levels' features are zero)."""
+    ijk, t = tiny_tree()
+    rng = np.random.default_rng(21)
+    feats = [np.zeros((int(n), 8)) for n in t.ncorner]
+    feats[2] = rng.normal(size=(int(t.ncorner[2]), 8))
+    d = W.decoders(rng, 3, 11, 32)
+    mdl = oracle.Model(feats, list(d["W1"]), list(d["b1"]), list(d["w2"]), d["b2"])
+    corners, cijk = t.export_corners(3)
+    pts = -1.0 + cijk * (2.0 / 16)
+    q = oracle.query(t, mdl, W.soa(pts), lod=3, want_vox=True)
+    have = q["vox"][2] >= 0
+    dec = oracle.decode(mdl, 3, feats[2], W.soa(pts))
+    np.testing.assert_array_equal(dec["sdf"][have], q["sdf"][have])
+    assert have.sum() > 500
+
+
+def test_decode_closed_forms():
+    """One hidden unit on a position column and one on a feature column:
+    out = b2 + w2_0 ReLU(W x_a + b) + w2_1 ReLU(V z_c + c), with inputs on
+    both sides of the kinks."""
+    rng = np.random.default_rng(22)
+    m, H = 8, 4
+    W1 = np.zeros((1, H, m + 3))
+    W1[0, 0, 1] = 2.0
+    W1[0, 1, 3 + 5] = -3.0
+    b1 = np.array([[0.5, 1.0, 0.0, 0.0]])
+    w2 = np.array([[1.5, -0.25, 7.0, 7.0]])
+    b2 = np.array([0.125])
+    mdl = oracle.Model([np.zeros((1, m))], list(W1), list(b1), list(w2), b2)
+    z = rng.normal(size=(200, m))
+    x = rng.uniform(-1, 1, size=(3, 200)).astype(np.float32)
+    out = oracle.decode(mdl, 1, z, x)["sdf"]
+    xv = x[1].astype(np.float64)
+    expect = 0.125 + 1.5 * np.maximum(2.0 * xv + 0.5, 0) - 0.25 * np.maximum(-3.0 * z[:, 5] + 1.0, 0)
+    np.testing.assert_allclose(out, expect, rtol=0, atol=1e-14)
