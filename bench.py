@@ -41,6 +41,9 @@ GATHER_BYTES = 5 * (8 * 32 * 4 + 8 * 4)
 QUERY_BYTES = GATHER_BYTES + 16
 TRACE_STEP_BYTES = GATHER_BYTES + 28
 EVAL_FLOPS = 5 * 8 * 32 * 2 + 2 * (35 * 128 + 128) + 2 * 128
+# Traversal: 16 B per slab-tested candidate (8 B pair read, 8 B per emitted
+# child written; ray and voxel records amortised over their pairs).
+TRAVERSAL_BYTES = 16
 
 # HBM traffic per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs
 # of this bench (KiB per dispatch), each scaled by the reading of the same
@@ -57,6 +60,17 @@ COUNTERS = {
 }
 FETCH_SCALE = (256 << 10) / 131088.125
 WRITE_SCALE = (256 << 10) / 262144.0
+
+
+def traversal_candidates(ngl, model, o, d, target):
+    """Slab tests of one traversal to `target`: the root test of every ray
+    plus every occupied child of every hit pair at depths 0..target-1."""
+    pop = np.array([bin(i).count("1") for i in range(256)], np.int64)
+    cand = o.shape[1]
+    for dd in range(target):
+        vox = ngl.trace_octree(model, o, d, dd)["vox"].cpu().numpy()
+        cand += int(pop[model.tree.child_mask[dd][vox]].sum())
+    return cand
 
 
 def sources_sha256(names):
@@ -286,10 +300,14 @@ def main():
         status = tr["status"].cpu().numpy()
         steps_arr = tr["steps"].cpu().numpy()
         frame_ms = mean(tc) + mean(tt) + mean(ts) + mean(tn)
+        n_cand = traversal_candidates(ngl, model, o, d, lod + 1)
+        trav_gbs = TRAVERSAL_BYTES * n_cand / (mean(tt) * 1e6)
         n_eval = int(steps_arr.sum())
         comp["frame"] = {"ms": frame_ms, "fps": 1e3 / frame_ms, "rays_per_s": R / (frame_ms * 1e-3),
                          "camera_ms": mean(tc), "traverse_ms": mean(tt), "trace_ms": mean(ts),
                          "normals_ms": mean(tn), "normal_step": h_fd,
+                         "traverse_candidates": n_cand, "traverse_algorithmic_GBps": trav_gbs,
+                         "traverse_hbm_frac": trav_gbs / HBM_PEAK_GBS,
                          "visible_px": int((status == ngl.HIT).sum()), "rays_with_voxels": int(
                              (buf.ray_off[1:] > buf.ray_off[:-1]).sum()),
                          "final_pairs": int(buf.counts[0]), "sdf_evals": n_eval,
@@ -349,6 +367,11 @@ def main():
         del src, dst
     if args.only is None and not args.no_batch:
         comp["batch"] = run_batch(dev, args.steps, args.warmup)
+    if args.only is None:
+        comp["decoder_bf16"] = run_decoder(S, dev, args.steps, args.warmup)
+        if do_h:
+            hq = comp["bf16_form"]["queries_per_s"] * DEC_MFMA_FLOPS / 1e12
+            comp["bf16_form"]["fused_decoder_mfma_frac"] = hq / BF16_PEAK_TFLOPS
 
     cpu = None
     if not args.no_cpu and do_q:
@@ -364,6 +387,38 @@ def main():
                       "queries": cfg.n_query, "image": [W_, H_], "train_points": S["xt"].shape[1]},
            "roofline": roof, "cpu_baseline": cpu, "components": comp}
     print(json.dumps(out), flush=True)
+
+
+BF16_PEAK_TFLOPS = 2500.0     # MI355X dense BF16 matrix peak
+DEC_MFMA_FLOPS = 2 * 32 * 128  # MFMA-eligible flops of one decoder on z (m = 32, h = 128)
+
+
+def run_decoder(S, dev, steps, warmup):
+    """The decoder alone (BF16 weights of the step's half-precision model)
+    on 2^20 points whose BF16 z rows (64 MB) and positions are resident on
+    the device: the split form of the query, for the matrix-core
+    utilisation of the decoder."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    half, cfg = S["half"], S["cfg"]
+    P = cfg.n_query
+    g = torch.Generator(device=dev)
+    g.manual_seed(1234)
+    z = (0.3 * torch.randn((P, cfg.feat_dim), generator=g, device=dev)).to(torch.bfloat16)
+    x = S["xq"]
+    out = torch.empty(P, dtype=torch.float32, device=dev)
+    for _ in range(warmup):
+        ngl.decode_sdf(half, cfg.num_lods, z, x=x, out=out)
+    tm = Timer()
+    for _ in range(steps):
+        with tm:
+            ngl.decode_sdf(half, cfg.num_lods, z, x=x, out=out)
+    torch.cuda.synchronize()
+    ms = float(np.median(tm.values()))
+    tf = DEC_MFMA_FLOPS * P / (ms * 1e-3) / 1e12
+    return {"points": P, "ms": ms, "points_per_s": P / (ms * 1e-3), "z_bytes": P * cfg.feat_dim * 2,
+            "mfma_tflops": tf, "mfma_frac_bf16": tf / BF16_PEAK_TFLOPS,
+            "note": "2*32*128 flops per point (first layer on z); inputs 80 B per point"}
 
 
 def run_batch(dev, steps, warmup):

@@ -172,6 +172,18 @@ typedef struct {
 int ngl_query_sdf(const ngl_model* m, const float* x, int64_t P, int32_t lod, float alpha,
                   const float* alpha_pp, float* sdf, uint8_t* valid, int32_t* vox_out, void* stream);
 
+/* Decoder only (Eq. 2's per-LOD MLP, Sec. 4.1): sdf[p] = b2 + w2 . ReLU(W1
+ * [x_p, z_p] + b1) of decoder `lod` for inputs the caller already holds —
+ * the query with the feature gather split off.  x: device [3][P] FP32
+ * (required iff with_xyz, else ignored); z: device [P][feat_dim] rows,
+ * z_dtype NGL_F32 or NGL_BF16, 16-byte aligned; sdf: device [P] FP32.  The
+ * decoder form follows the model's weights as in ngl_query_sdf (BF16
+ * weights: matrix cores with BF16 inputs; FP32: NGL_OPT_F32_DECODER).
+ * Errors: NGL_E_INVALID for bad arguments, NGL_E_UNSUPPORTED for an
+ * uncompiled feat_dim. */
+int ngl_decode_sdf(const ngl_model* m, int32_t lod, const float* x, const void* z, int32_t z_dtype, int64_t P,
+                   float* sdf, void* stream);
+
 /* Surface normals by central differences (App. A.4: normals are obtained by
  * finite differences).  For each point x_p (device x[3][P]) the gradient
  * g_a = (f(x + h e_a) - f(x - h e_a)) / (2h) of f = the SDF of

@@ -22,7 +22,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = ["-std=c++17", "-O3", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-Wno-unused-function"]
 DEVICE = ["--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-fno-gpu-flush-denormals-to-zero", "-fno-fast-math"]
+          "-fno-gpu-flush-denormals-to-zero", "-fno-fast-math",
+          # matrix-core results in ordinary VGPRs (no accumulator-register copies)
+          "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def sources():
@@ -41,11 +43,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libngl.so (always rebuilds)."""
+def _stale(src: str) -> bool:
+    """The object is missing or older than its source or any header."""
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, changed_only: bool = False) -> str:
+    """Compile the sources and link libngl.so.  Rebuilds everything unless
+    changed_only, which recompiles only stale objects."""
     srcs = sources()
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
+    todo = [s for s in srcs if _stale(s)] if changed_only else srcs
+    if todo:
+        with cf.ThreadPoolExecutor(max_workers=min(8, len(todo))) as ex:
+            list(ex.map(_compile, todo))
+    objs = [os.path.join(OBJDIR, os.path.basename(s) + ".o") for s in srcs]
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -58,5 +74,5 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, changed_only="--changed" in sys.argv[1:])
     sys.exit(0)

@@ -48,4 +48,15 @@ int check_model(const ngl_model* m, bool need_features);
 
 inline int din_of(const ngl_model& m) { return m.feat_dim + (m.with_xyz ? 3 : 0); }
 
+// Calls fn_m8 / fn_m16 / fn_m32 / fn_m64 (one translation unit per feature
+// width keeps the kernel instantiations of each width apart).
+#define NGL_BY_WIDTH(width, fn, ...)                                                   \
+  switch (width) {                                                                     \
+    case 8: return fn##_m8(__VA_ARGS__);                                               \
+    case 16: return fn##_m16(__VA_ARGS__);                                             \
+    case 32: return fn##_m32(__VA_ARGS__);                                             \
+    case 64: return fn##_m64(__VA_ARGS__);                                             \
+    default: NGL_FAIL(NGL_E_UNSUPPORTED, "feat_dim %d not compiled (8, 16, 32, 64)", int(width)); \
+  }
+
 }  // namespace ngl

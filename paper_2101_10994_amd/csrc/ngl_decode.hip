@@ -1,0 +1,283 @@
+// Decoder-only evaluation: the per-LOD MLP of Eq. 2 applied to inputs
+// [x, z] that the caller already holds (z = summed features, one row per
+// point).  This is the query with the gather split off; it runs the same
+// decoder forms:
+//   * BF16 weights, hidden width 32/64/128: the first layer for 16 points at
+//     a time on the matrix cores with every weight fragment held in
+//     registers and the inputs loaded straight into the B-operand layout
+//     (no LDS round trip), ReLU and the second layer on the accumulators;
+//   * otherwise the LDS-staged wavefront decoders of the query kernels
+//     (BF16 or FP32 matrix-core form) or the per-lane FP32 form.
+#include "ngl_common.h"
+#include "ngl_mfma.h"
+
+namespace ngl {
+
+struct DecodeArgs {
+  const float* x;  // [3][P], or null without the position input
+  const void* z;   // [P][m] rows, FP32 or BF16
+  int64_t P;
+  int lod;
+  float* sdf;      // [P]
+};
+
+// Eight consecutive features f0..f0+7 of row p as BF16 bits (RNE from FP32).
+template <int M, typename ZT>
+__device__ inline uint4 load_z8(const void* z, int64_t p, int f0) {
+  if constexpr (std::is_same<ZT, BF16>::value) {
+    return *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(z) + p * M + f0);
+  } else {
+    const float4* r = reinterpret_cast<const float4*>(static_cast<const float*>(z) + p * M + f0);
+    const float4 a = r[0], b = r[1];
+    return make_uint4(pack_bf16(a.x, a.y), pack_bf16(a.z, a.w), pack_bf16(b.x, b.y), pack_bf16(b.z, b.w));
+  }
+}
+
+// Row p of z as FP32.
+template <int M, typename ZT>
+__device__ inline void load_row(const void* z, int64_t p, float* out) {
+  if constexpr (std::is_same<ZT, BF16>::value) {
+    const uint4* r = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(z) + p * M);
+#pragma unroll
+    for (int q = 0; q < M / 8; ++q) {
+      const uint4 v = r[q];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        out[8 * q + 2 * e] = bf16_to_f32(w[e] & 0xffffu);
+        out[8 * q + 2 * e + 1] = bf16_to_f32(w[e] >> 16);
+      }
+    }
+  } else {
+    const float4* r = reinterpret_cast<const float4*>(static_cast<const float*>(z) + p * M);
+#pragma unroll
+    for (int q = 0; q < M / 4; ++q) {
+      const float4 v = r[q];
+      out[4 * q] = v.x;
+      out[4 * q + 1] = v.y;
+      out[4 * q + 2] = v.z;
+      out[4 * q + 3] = v.w;
+    }
+  }
+}
+
+// Register-resident BF16 form.  A wavefront takes U consecutive 16-point
+// tiles at a time; lane (g = lane/16, j = lane%16) loads features
+// 32s + 8g..+7 of point j of a tile for every K-step s, which is exactly its
+// B fragment, and the lanes of g = 0 carry the tile's [x_hi, x_lo, 1, 1]
+// step.  All U tiles' inputs are loaded before the first decode.
+// NH = hidden/16.
+template <int M, bool XYZ, int NH, typename ZT, int U, bool FULL>
+__device__ inline void decode_tiles(const DecodeArgs& A, int64_t p0, const bf16x8 (&fr)[NH][MfmaShape<M, XYZ>::KS],
+                                    const floatx4 (&w2v)[NH], float b2) {
+  using S = MfmaShape<M, XYZ>;
+  const int lane = threadIdx.x & 63, g = lane >> 4;
+  const int64_t P = A.P;
+  bf16x8 b[U][S::KS];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t p = p0 + 16 * u;
+    const bool in = FULL || p < P;
+    const int64_t pc = in ? p : P - 1;
+#pragma unroll
+    for (int s = 0; s < S::KZ; ++s) {
+      const int f0 = 32 * s + 8 * g;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (f0 < M) v = load_z8<M, ZT>(A.z, pc, f0);
+      b[u][s] = __builtin_bit_cast(bf16x8, v);
+    }
+    float x[3] = {0.0f, 0.0f, 0.0f};
+    if constexpr (XYZ) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) x[a] = A.x[a * P + pc];
+    }
+    const uint4 t = pos_bias_row<XYZ>(x);
+    const bool keep = g == 0;
+    b[u][S::KZ] = __builtin_bit_cast(bf16x8, make_uint4(keep ? t.x : 0u, keep ? t.y : 0u, keep ? t.z : 0u,
+                                                        keep ? t.w : 0u));
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    floatx4 acc[NH];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+      acc[h] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < S::KS; ++s)
+        acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[h][s], b[u][s], acc[h], 0, 0, 0);
+    }
+    float part = 0.0f;
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) part = fmaf(w2v[h][r], relu_bits(acc[h][r]), part);
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    const int64_t p = p0 + 16 * u;
+    if (g == 0 && (FULL || p < P)) A.sdf[p] = b2 + part;
+  }
+}
+
+template <int M, bool XYZ, int NH, typename ZT, int U>
+__global__ __launch_bounds__(256) void k_decode_rf(ngl_model md, DecodeArgs A) {
+  using S = MfmaShape<M, XYZ>;
+  __shared__ uint4 fl[NH * S::KS * 64];
+  __shared__ float w2l[16 * NH];
+  // fragments built cooperatively with a fixed trip count, so every
+  // thread's weight loads are in flight together
+  constexpr int NF = NH * S::KS * 64;
+#pragma unroll
+  for (int e0 = 0; e0 < NF; e0 += 256) {
+    const int e = e0 + int(threadIdx.x);
+    if (e < NF) fl[e] = frag_bf16<M, XYZ>(md, A.lod, (e >> 6) / S::KS, (e >> 6) % S::KS, e & 63);
+  }
+  if (threadIdx.x < 16 * NH) w2l[threadIdx.x] = md.w2[A.lod - 1][threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  bf16x8 fr[NH][S::KS];
+  floatx4 w2v[NH];
+#pragma unroll
+  for (int h = 0; h < NH; ++h) {
+#pragma unroll
+    for (int s = 0; s < S::KS; ++s) fr[h][s] = __builtin_bit_cast(bf16x8, fl[(h * S::KS + s) * 64 + lane]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) w2v[h][r] = w2l[16 * h + 4 * g + r];
+  }
+  const float b2 = md.b2[A.lod - 1];
+  const int64_t P = A.P;
+  const int64_t chunks = (P + 16 * U - 1) / (16 * U);
+  const int64_t nw = int64_t(gridDim.x) * (blockDim.x >> 6);
+  for (int64_t c = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); c < chunks; c += nw) {
+    const int64_t p0 = c * (16 * U) + j;
+    if ((c + 1) * (16 * U) <= P)
+      decode_tiles<M, XYZ, NH, ZT, U, true>(A, p0, fr, w2v, b2);
+    else
+      decode_tiles<M, XYZ, NH, ZT, U, false>(A, p0, fr, w2v, b2);
+  }
+}
+
+// LDS-staged policy decoders (as in the query kernels), or the per-lane FP32
+// form when MFMA is false.
+template <int M, bool XYZ, typename ZT, int NW, class DEC, bool MFMA>
+__global__ __launch_bounds__(64 * NW) void k_decode_lds(ngl_model md, DecodeArgs A) {
+  extern __shared__ __align__(16) char smem[];
+  const int H = md.hidden;
+  DecLds<DEC> S(smem, H, false);
+  if constexpr (MFMA) {
+    DEC::load(md, A.lod, S.frag0, S.w2s0);
+    __syncthreads();
+  }
+  const float b2 = md.b2[A.lod - 1];
+  const int64_t P = A.P;
+  for (int64_t base = int64_t(blockIdx.x) * (64 * NW); base < P; base += int64_t(gridDim.x) * (64 * NW)) {
+    const int64_t p = base + threadIdx.x;
+    const bool in = p < P;
+    float x[3] = {0.0f, 0.0f, 0.0f};
+    float z[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) z[k] = 0.0f;
+    if (in) {
+      if constexpr (XYZ) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x[a] = A.x[a * P + p];
+      }
+      load_row<M, ZT>(A.z, p, z);
+    }
+    float out;
+    if constexpr (MFMA) {
+      DEC::stage(S.stage, x, z);
+      wave_lds_sync();
+      out = DEC::decode(S.frag0, S.w2s0, b2, S.stage, H);
+      wave_lds_sync();
+    } else {
+      out = decode_f32<M, XYZ>(md, A.lod, x, z);
+    }
+    if (in) A.sdf[p] = out;
+  }
+}
+
+#ifndef NGL_DECODE_TILES
+#define NGL_DECODE_TILES 8
+#endif
+constexpr int kDecodeU = NGL_DECODE_TILES;  // 16-point tiles per wavefront iteration
+
+// One resident wave of blocks (each block builds the fragments once, so the
+// grid is sized to the occupancy and loops over the tiles).
+template <int M, bool XYZ, typename ZT, int NH>
+static int launch_rf(const ngl_model& md, const DecodeArgs& A, hipStream_t s) {
+  static int resident = 0;
+  if (!resident) {
+    int dev = 0, cus = 256, per = 1;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    const void* kern = reinterpret_cast<const void*>(&k_decode_rf<M, XYZ, NH, ZT, kDecodeU>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 256, 0) != hipSuccess || per < 1) per = 1;
+    resident = cus * per;
+  }
+  const int64_t T = (A.P + 15) / 16;
+  int64_t grid = (T + 3) / 4;
+  if (grid > resident) grid = resident;
+  k_decode_rf<M, XYZ, NH, ZT, kDecodeU><<<unsigned(grid), 256, 0, s>>>(md, A);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+template <int M, bool XYZ, typename ZT, class DEC, bool MFMA>
+static int launch_lds(const ngl_model& md, const DecodeArgs& A, hipStream_t s) {
+  const size_t lds = MFMA ? DecLds<DEC>::fixed_bytes(md.hidden, false) + 2 * DEC::STAGE_BYTES : 0;
+  int64_t grid = (A.P + 127) / 128;
+  if (grid > 4096) grid = 4096;
+  k_decode_lds<M, XYZ, ZT, 2, DEC, MFMA><<<unsigned(grid), 128, lds, s>>>(md, A);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+template <int M, bool XYZ, typename ZT>
+static int run_decode(const ngl_model& md, const DecodeArgs& A, hipStream_t s) {
+  if (md.w_dtype == NGL_BF16) {
+    switch (md.hidden) {
+      case 32: return launch_rf<M, XYZ, ZT, 2>(md, A, s);
+      case 64: return launch_rf<M, XYZ, ZT, 4>(md, A, s);
+      case 128: return launch_rf<M, XYZ, ZT, 8>(md, A, s);
+      default: return launch_lds<M, XYZ, ZT, DecBF16<M, XYZ>, true>(md, A, s);
+    }
+  }
+  if (option(NGL_OPT_F32_DECODER) == 1) return launch_lds<M, XYZ, ZT, DecF32<M, XYZ>, true>(md, A, s);
+  return launch_lds<M, XYZ, ZT, DecF32<M, XYZ>, false>(md, A, s);
+}
+
+template <int M>
+static int decode_m(const ngl_model& md, const DecodeArgs& A, int zt, hipStream_t s) {
+  if (md.with_xyz)
+    return zt == NGL_BF16 ? run_decode<M, true, BF16>(md, A, s) : run_decode<M, true, F32>(md, A, s);
+  return zt == NGL_BF16 ? run_decode<M, false, BF16>(md, A, s) : run_decode<M, false, F32>(md, A, s);
+}
+
+}  // namespace ngl
+
+extern "C" {
+
+int ngl_decode_sdf(const ngl_model* m, int32_t lod, const float* x, const void* z, int32_t z_dtype, int64_t P,
+                   float* sdf, void* stream) {
+  int rc = ngl::check_model(m, true);
+  if (rc) return rc;
+  NGL_REQUIRE(P >= 0, "negative point count");
+  NGL_REQUIRE(lod >= 1 && lod <= m->num_lods, "lod %d outside 1..%d", lod, m->num_lods);
+  NGL_REQUIRE(z_dtype == NGL_F32 || z_dtype == NGL_BF16, "z_dtype must be NGL_F32 or NGL_BF16");
+  if (P == 0) return NGL_OK;
+  NGL_REQUIRE(z != nullptr && sdf != nullptr, "z or sdf is null");
+  NGL_REQUIRE(!m->with_xyz || x != nullptr, "the model reads the position: x is required");
+  NGL_REQUIRE(reinterpret_cast<uintptr_t>(z) % 16 == 0, "z must be 16-byte aligned");
+  ngl::DecodeArgs A{x, z, P, int(lod), sdf};
+  hipStream_t s = (hipStream_t)stream;
+  switch (m->feat_dim) {
+    case 8: return ngl::decode_m<8>(*m, A, z_dtype, s);
+    case 16: return ngl::decode_m<16>(*m, A, z_dtype, s);
+    case 32: return ngl::decode_m<32>(*m, A, z_dtype, s);
+    case 64: return ngl::decode_m<64>(*m, A, z_dtype, s);
+    default: NGL_FAIL(NGL_E_UNSUPPORTED, "feat_dim %d not compiled (8, 16, 32, 64)", m->feat_dim);
+  }
+}
+
+}  // extern "C"

@@ -32,6 +32,17 @@ struct F32 {};
 struct F16 {};
 struct BF16 {};
 
+// F<M, FT, XYZ>::run(md, args...) for the model's feature dtype and position
+// input (M is fixed by the caller's translation unit).
+template <template <int, typename, bool> class F, int M, typename... Args>
+inline int dispatch_ft(const ngl_model& md, Args... args) {
+  switch (md.feat_dtype) {
+    case NGL_F32: return md.with_xyz ? F<M, F32, true>::run(md, args...) : F<M, F32, false>::run(md, args...);
+    case NGL_F16: return md.with_xyz ? F<M, F16, true>::run(md, args...) : F<M, F16, false>::run(md, args...);
+    default: return md.with_xyz ? F<M, BF16, true>::run(md, args...) : F<M, BF16, false>::run(md, args...);
+  }
+}
+
 __device__ inline float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
 __device__ inline float f16_to_f32(uint32_t bits16) {
   return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);

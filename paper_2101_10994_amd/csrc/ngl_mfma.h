@@ -31,6 +31,29 @@ __device__ inline uint32_t f32_to_bf16_bits(float f) {
   return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two FP32 values as packed BF16 bits, `lo` in the low half (one
+// v_cvt_pk_bf16_f32, round to nearest even).
+__device__ inline uint32_t pack_bf16(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
+}
+
+// The last K-step's B row of a point: [x_hi(3), x_lo(3), 1, 1] as BF16
+// (x = x_hi + x_lo to about 16 bits), or [1, 1, 0...] without the position.
+template <bool XYZ>
+__device__ inline uint4 pos_bias_row(const float x[3]) {
+  if constexpr (XYZ) {
+    const uint32_t h01 = pack_bf16(x[0], x[1]);
+    const uint32_t t1 = pack_bf16(x[2], x[0] - __uint_as_float(h01 << 16));
+    const uint32_t t2 = pack_bf16(x[1] - __uint_as_float(h01 & 0xffff0000u), x[2] - __uint_as_float(t1 << 16));
+    return make_uint4(h01, t1, t2, 0x3f80u | 0x3f80u << 16);
+  } else {
+    return make_uint4(0x3f80u | 0x3f80u << 16, 0u, 0u, 0u);
+  }
+}
+
 template <int M, bool XYZ>
 struct MfmaShape {
   static constexpr int OFF = XYZ ? 3 : 0;
@@ -41,46 +64,58 @@ struct MfmaShape {
   static constexpr int frag_bytes(int H) { return (H / 16) * KS * 64 * 16; }
 };
 
+// One lane's A fragment (16 bytes) of decoder L for hidden tile h and K-step
+// s: row i = 16h + lane%16, columns 8*(lane/16) + 0..7 of that step.
+template <int M, bool XYZ>
+__device__ inline uint4 frag_bf16(const ngl_model& md, int L, int h, int s, int lane) {
+  using S = MfmaShape<M, XYZ>;
+  const int din = M + S::OFF;
+  const uint16_t* W1 = static_cast<const uint16_t*>(md.W1[L - 1]);
+  const float* b1 = md.b1[L - 1];
+  const int i = 16 * h + (lane & 15);
+  const int g = lane >> 4;
+  uint32_t bits[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int kk = 8 * g + q;
+    uint32_t b = 0;
+    if (s < S::KZ) {
+      const int f = 32 * s + kk;
+      if (f < M) b = W1[i * din + S::OFF + f];
+    } else if (XYZ) {
+      if (kk < 3) b = W1[i * din + kk];
+      else if (kk < 6) b = W1[i * din + kk - 3];
+      else if (kk == 6) b = f32_to_bf16_bits(b1[i]);
+      else if (kk == 7) b = f32_to_bf16_bits(b1[i] - __uint_as_float(f32_to_bf16_bits(b1[i]) << 16));
+    } else {
+      if (kk == 0) b = f32_to_bf16_bits(b1[i]);
+      else if (kk == 1) b = f32_to_bf16_bits(b1[i] - __uint_as_float(f32_to_bf16_bits(b1[i]) << 16));
+    }
+    bits[q] = b;
+  }
+  return make_uint4(bits[0] | bits[1] << 16, bits[2] | bits[3] << 16, bits[4] | bits[5] << 16,
+                    bits[6] | bits[7] << 16);
+}
+
 // Block-cooperative: A fragments of decoder L (BF16 weights) into LDS, and
 // its w2 (FP32).  frag: [H/16][KS][64] 16-byte fragments.
 template <int M, bool XYZ>
 __device__ inline void load_frags(const ngl_model& md, int L, uint4* frag, float* w2s) {
   using S = MfmaShape<M, XYZ>;
   const int H = md.hidden;
-  const int din = M + S::OFF;
-  const uint16_t* W1 = static_cast<const uint16_t*>(md.W1[L - 1]);
-  const float* b1 = md.b1[L - 1];
   const int n = (H / 16) * S::KS * 64;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int lane = e & 63;
     const int s = (e >> 6) % S::KS;
     const int h = (e >> 6) / S::KS;
-    const int i = 16 * h + (lane & 15);
-    const int g = lane >> 4;
-    uint32_t bits[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int kk = 8 * g + q;
-      uint32_t b = 0;
-      if (s < S::KZ) {
-        const int f = 32 * s + kk;
-        if (f < M) b = W1[i * din + S::OFF + f];
-      } else if (XYZ) {
-        if (kk < 3) b = W1[i * din + kk];
-        else if (kk < 6) b = W1[i * din + kk - 3];
-        else if (kk == 6) b = f32_to_bf16_bits(b1[i]);
-        else if (kk == 7) b = f32_to_bf16_bits(b1[i] - __uint_as_float(f32_to_bf16_bits(b1[i]) << 16));
-      } else {
-        if (kk == 0) b = f32_to_bf16_bits(b1[i]);
-        else if (kk == 1) b = f32_to_bf16_bits(b1[i] - __uint_as_float(f32_to_bf16_bits(b1[i]) << 16));
-      }
-      bits[q] = b;
-    }
-    frag[e] = make_uint4(bits[0] | bits[1] << 16, bits[2] | bits[3] << 16, bits[4] | bits[5] << 16,
-                         bits[6] | bits[7] << 16);
+    frag[e] = frag_bf16<M, XYZ>(md, L, h, s, e & 63);
   }
   for (int k = threadIdx.x; k < H; k += blockDim.x) w2s[k] = md.w2[L - 1][k];
 }
+
+// max(a, 0) as one integer max on the bit pattern (negative floats, -0
+// included, are negative integers).  A NaN input may pass through; the
+// decoders' inputs are finite for every defined result.
+__device__ inline float relu_bits(float a) { return __int_as_float(max(__float_as_int(a), 0)); }
 
 // Orders this wavefront's LDS writes before its later LDS reads.
 __device__ inline void wave_lds_sync() {
@@ -99,31 +134,18 @@ __device__ inline void stage_row(uint16_t* stage, const float x[3], const float*
   for (int s = 0; s < S::KZ; ++s) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-      const int f0 = 32 * s + 2 * q, f1 = f0 + 1;
-      const uint32_t lo = f0 < M ? f32_to_bf16_bits(z[f0 < M ? f0 : 0]) : 0u;
-      const uint32_t hi = f1 < M ? f32_to_bf16_bits(z[f1 < M ? f1 : 0]) : 0u;
-      row[16 * s + q] = lo | hi << 16;
+      const int f0 = 32 * s + 2 * q;
+      row[16 * s + q] = f0 < M ? pack_bf16(z[f0 < M ? f0 : 0], z[f0 + 1 < M ? f0 + 1 : 0]) : 0u;
     }
   }
-  uint32_t t[16];
+  const uint4 t = pos_bias_row<XYZ>(x);
+  uint32_t* tail = row + 16 * S::KZ;
+  tail[0] = t.x;
+  tail[1] = t.y;
+  tail[2] = t.z;
+  tail[3] = t.w;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) t[q] = 0;
-  if (XYZ) {
-    uint32_t hi[3], lo[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      hi[a] = f32_to_bf16_bits(x[a]);
-      lo[a] = f32_to_bf16_bits(x[a] - __uint_as_float(hi[a] << 16));
-    }
-    t[0] = hi[0] | hi[1] << 16;
-    t[1] = hi[2] | lo[0] << 16;
-    t[2] = lo[1] | lo[2] << 16;
-    t[3] = 0x3f80u | 0x3f80u << 16;  // 1.0, 1.0
-  } else {
-    t[0] = 0x3f80u | 0x3f80u << 16;
-  }
-#pragma unroll
-  for (int q = 0; q < 16; ++q) row[16 * S::KZ + q] = t[q];
+  for (int q = 4; q < 16; ++q) tail[q] = 0u;
 }
 
 // First layer on the matrix cores, second layer and reduction in FP32: the
@@ -148,10 +170,10 @@ __device__ inline float wave_decode(const uint4* frag, const float* w2s, float b
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, frag[(h * S::KS + s) * 64 + lane]),
                                                       b[s], acc, 0, 0, 0);
       const float4 w = *reinterpret_cast<const float4*>(w2s + 16 * h + 4 * g);
-      part = fmaf(w.x, fmaxf(acc[0], 0.0f), part);
-      part = fmaf(w.y, fmaxf(acc[1], 0.0f), part);
-      part = fmaf(w.z, fmaxf(acc[2], 0.0f), part);
-      part = fmaf(w.w, fmaxf(acc[3], 0.0f), part);
+      part = fmaf(w.x, relu_bits(acc[0]), part);
+      part = fmaf(w.y, relu_bits(acc[1]), part);
+      part = fmaf(w.z, relu_bits(acc[2]), part);
+      part = fmaf(w.w, relu_bits(acc[3]), part);
     }
     // sum over the four row groups of the tile (lanes j, j+16, j+32, j+48)
     part += __shfl_xor(part, 16, 64);
@@ -228,10 +250,10 @@ __device__ inline float wave_decode32(const float* frag, const float* w2s, float
       for (int s = 0; s < S::KS; ++s)
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(h * S::KS + s) * 64 + lane], b[s], acc, 0, 0, 0);
       const float4 w = *reinterpret_cast<const float4*>(w2s + 16 * h + 4 * g);
-      part = fmaf(w.x, fmaxf(acc[0], 0.0f), part);
-      part = fmaf(w.y, fmaxf(acc[1], 0.0f), part);
-      part = fmaf(w.z, fmaxf(acc[2], 0.0f), part);
-      part = fmaf(w.w, fmaxf(acc[3], 0.0f), part);
+      part = fmaf(w.x, relu_bits(acc[0]), part);
+      part = fmaf(w.y, relu_bits(acc[1]), part);
+      part = fmaf(w.z, relu_bits(acc[2]), part);
+      part = fmaf(w.w, relu_bits(acc[3]), part);
     }
     part += __shfl_xor(part, 16, 64);
     part += __shfl_xor(part, 32, 64);

@@ -3,375 +3,8 @@
 // One lane per point: exact location of the finest needed cell, one descent
 // of the octree that yields the voxel of every level, the trilinear corner
 // gather summed across levels in registers, then the per-LOD decoder.
-#include "ngl_common.h"
-#include "ngl_device.h"
-#include "ngl_mfma.h"
+#include "ngl_query_impl.h"
 
-namespace ngl {
-
-// Locate x at feature levels 1..Lp: vox[l-1] (or -1) and the level's cell;
-// *vlast = voxel of level Lp, *vnext = voxel of level `next` (both or -1).
-template <int MAXL>
-__device__ inline void locate(const ngl_model& md, const float x[3], int Lp, int* vox, int* cx, int* cy, int* cz,
-                              int* vlast, int next = -1, int* vnext = nullptr) {
-  const int Dp = Lp + 1;
-  if (!in_box(x[0], x[1], x[2])) {
-#pragma unroll
-    for (int l = 0; l < MAXL; ++l) vox[l] = -1;
-    *cx = *cy = *cz = 0;
-    *vlast = -1;
-    if (vnext) *vnext = -1;
-    return;
-  }
-  const int r = 1 << Dp;
-  *cx = cell_of(x[0], r);
-  *cy = cell_of(x[1], r);
-  *cz = cell_of(x[2], r);
-  descend<MAXL>(md, *cx, *cy, *cz, Dp, vox, vlast, next, vnext);
-}
-
-template <int M, typename FT, bool XYZ>
-__global__ __launch_bounds__(kBlock) void k_query(ngl_model md, const float* __restrict__ xs, int64_t P, int lod,
-                                                  float alpha, const float* __restrict__ alpha_pp,
-                                                  float* __restrict__ sdf, uint8_t* __restrict__ valid,
-                                                  int32_t* __restrict__ vox_out) {
-  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (p >= P) return;
-  const float x[3] = {xs[p], xs[P + p], xs[2 * P + p]};
-  const bool blend = alpha_pp != nullptr || alpha > 0.0f;
-  const int Lp = blend ? lod + 1 : lod;
-  const float a = alpha_pp ? alpha_pp[p] : alpha;
-  int vox[NGL_MAX_LODS];
-  int cx, cy, cz, vlast, vn;
-  locate<NGL_MAX_LODS>(md, x, Lp, vox, &cx, &cy, &cz, &vlast, lod + 1, &vn);
-  float z[M];
-#pragma unroll
-  for (int k = 0; k < M; ++k) z[k] = 0.0f;
-  // Level loops are unrolled over the compile-time maximum so that the
-  // per-level arrays stay in registers.
-#pragma unroll
-  for (int l = 1; l <= NGL_MAX_LODS; ++l)
-    if (l <= lod && vox[l - 1] >= 0) interp_level<M, FT>(md, l, vox[l - 1], cx >> (Lp - l), cy >> (Lp - l), cz >> (Lp - l), x, z);
-  float out = decode_f32<M, XYZ>(md, lod, x, z);
-  if (blend) {
-    // z_{L+1} = z_L + psi_{L+1}
-    if (vn >= 0) interp_level<M, FT>(md, lod + 1, vn, cx, cy, cz, x, z);
-    out = (1.0f - a) * out + a * decode_f32<M, XYZ>(md, lod + 1, x, z);
-  }
-  sdf[p] = out;
-  if (valid) valid[p] = vlast >= 0 ? 1 : 0;
-  if (vox_out) {
-#pragma unroll
-    for (int l = 1; l <= NGL_MAX_LODS; ++l)
-      if (l <= Lp) vox_out[int64_t(l - 1) * P + p] = vox[l - 1];
-  }
-}
-
-// All discrete LODs: the level sum is shared, one decoder per LOD.
-template <int M, typename FT, bool XYZ>
-__global__ __launch_bounds__(kBlock) void k_query_all(ngl_model md, const float* __restrict__ xs, int64_t P,
-                                                      float* __restrict__ sdf_all) {
-  const int64_t p = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (p >= P) return;
-  const float x[3] = {xs[p], xs[P + p], xs[2 * P + p]};
-  const int Lm = md.num_lods;
-  int vox[NGL_MAX_LODS];
-  int cx, cy, cz, vlast;
-  locate<NGL_MAX_LODS>(md, x, Lm, vox, &cx, &cy, &cz, &vlast);
-  float z[M];
-#pragma unroll
-  for (int k = 0; k < M; ++k) z[k] = 0.0f;
-#pragma unroll
-  for (int l = 1; l <= NGL_MAX_LODS; ++l) {
-    if (l <= Lm) {
-      const int s = Lm - l;
-      if (vox[l - 1] >= 0) interp_level<M, FT>(md, l, vox[l - 1], cx >> s, cy >> s, cz >> s, x, z);
-      sdf_all[int64_t(l - 1) * P + p] = decode_f32<M, XYZ>(md, l, x, z);
-    }
-  }
-}
-
-// Matrix-core decoder (BF16 or FP32 form): the same location and gather per
-// lane, then the first decoder layer for the wavefront's 64 points on the
-// matrix cores.  Grid-stride over points so each block stages the decoder
-// fragments in LDS once; inside the loop only wavefront-level LDS ordering
-// is needed.
-template <int M, typename FT, bool XYZ, int NW, class DEC>
-__global__ __launch_bounds__(64 * NW) void k_query_mfma(ngl_model md, const float* __restrict__ xs, int64_t P,
-                                                        int lod, float alpha, const float* __restrict__ alpha_pp,
-                                                        float* __restrict__ sdf, uint8_t* __restrict__ valid,
-                                                        int32_t* __restrict__ vox_out) {
-  extern __shared__ __align__(16) char smem[];
-  const int H = md.hidden;
-  const bool blend = alpha_pp != nullptr || alpha > 0.0f;
-  DecLds<DEC> S(smem, H, blend);
-  DEC::load(md, lod, S.frag0, S.w2s0);
-  if (blend) DEC::load(md, lod + 1, S.frag1, S.w2s1);
-  __syncthreads();
-  const float b2a = md.b2[lod - 1];
-  const float b2b = blend ? md.b2[lod] : 0.0f;
-  const int Lp = blend ? lod + 1 : lod;
-  for (int64_t base = int64_t(blockIdx.x) * (64 * NW); base < P; base += int64_t(gridDim.x) * (64 * NW)) {
-    const int64_t p = base + threadIdx.x;
-    const bool act = p < P;
-    float x[3] = {0.0f, 0.0f, 0.0f};
-    if (act) {
-      x[0] = xs[p];
-      x[1] = xs[P + p];
-      x[2] = xs[2 * P + p];
-    }
-    int vox[NGL_MAX_LODS];
-    int cx, cy, cz, vlast, vn;
-    locate<NGL_MAX_LODS>(md, x, Lp, vox, &cx, &cy, &cz, &vlast, lod + 1, &vn);
-    if (!act) {
-#pragma unroll
-      for (int l = 0; l < NGL_MAX_LODS; ++l) vox[l] = -1;
-      vlast = vn = -1;
-    }
-    float z[M];
-#pragma unroll
-    for (int k = 0; k < M; ++k) z[k] = 0.0f;
-#pragma unroll
-    for (int l = 1; l <= NGL_MAX_LODS; ++l)
-      if (l <= lod && vox[l - 1] >= 0)
-        interp_level<M, FT>(md, l, vox[l - 1], cx >> (Lp - l), cy >> (Lp - l), cz >> (Lp - l), x, z);
-    DEC::stage(S.stage, x, z);
-    wave_lds_sync();
-    float out = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H);
-    if (blend) {
-      if (vn >= 0) interp_level<M, FT>(md, lod + 1, vn, cx, cy, cz, x, z);
-      wave_lds_sync();
-      DEC::stage(S.stage, x, z);
-      wave_lds_sync();
-      const float a = act ? (alpha_pp ? alpha_pp[p] : alpha) : 0.0f;
-      out = (1.0f - a) * out + a * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H);
-    }
-    wave_lds_sync();
-    if (act) {
-      sdf[p] = out;
-      if (valid) valid[p] = vlast >= 0 ? 1 : 0;
-      if (vox_out) {
-#pragma unroll
-        for (int l = 1; l <= NGL_MAX_LODS; ++l)
-          if (l <= Lp) vox_out[int64_t(l - 1) * P + p] = vox[l - 1];
-      }
-    }
-  }
-}
-
-template <int M, typename FT, bool XYZ, int NW, class DEC>
-static int launch_query_mfma_nw(const ngl_model& md, const float* x, int64_t P, int lod, float alpha,
-                                const float* app, float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s,
-                                size_t lds) {
-  int64_t grid = (P + 64 * NW - 1) / (64 * NW);
-  if (grid > 4096) grid = 4096;
-  k_query_mfma<M, FT, XYZ, NW, DEC><<<unsigned(grid), 64 * NW, lds, s>>>(md, x, P, lod, alpha, app, sdf, valid, vox);
-  NGL_LAUNCHED();
-  return NGL_OK;
-}
-
-template <int M, typename FT, bool XYZ, class DEC>
-static int launch_query_mfma(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app,
-                             float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s) {
-  const bool blend = app != nullptr || alpha > 0.0f;
-  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, blend);
-  if (fixed + 4 * DEC::STAGE_BYTES <= 65536)
-    return launch_query_mfma_nw<M, FT, XYZ, 4, DEC>(md, x, P, lod, alpha, app, sdf, valid, vox, s,
-                                                    fixed + 4 * DEC::STAGE_BYTES);
-  if (fixed + 2 * DEC::STAGE_BYTES <= 65536)
-    return launch_query_mfma_nw<M, FT, XYZ, 2, DEC>(md, x, P, lod, alpha, app, sdf, valid, vox, s,
-                                                    fixed + 2 * DEC::STAGE_BYTES);
-  return launch_query_mfma_nw<M, FT, XYZ, 1, DEC>(md, x, P, lod, alpha, app, sdf, valid, vox, s,
-                                                  fixed + DEC::STAGE_BYTES);
-}
-
-// Central-difference normals: six queries per point.  MFMA selects the
-// matrix-core decoder (every lane joins each of the six decodes).
-struct NormalArgs {
-  const float* x;       // points [3][P], or null with rays below
-  const float* o;
-  const float* d;
-  const float* t_hit;
-  const uint8_t* status;
-  int64_t P;
-  int lod;
-  float alpha;
-  float h;
-  float* normals;       // [3][P]
-};
-
-template <int M, typename FT, bool XYZ>
-__device__ inline void query_z(const ngl_model& md, const float x[3], int lod, bool blend, float* z, float* zn) {
-  const int Lp = blend ? lod + 1 : lod;
-  int vox[NGL_MAX_LODS];
-  int cx, cy, cz, vlast, vn;
-  locate<NGL_MAX_LODS>(md, x, Lp, vox, &cx, &cy, &cz, &vlast, lod + 1, &vn);
-#pragma unroll
-  for (int k = 0; k < M; ++k) z[k] = 0.0f;
-#pragma unroll
-  for (int l = 1; l <= NGL_MAX_LODS; ++l)
-    if (l <= lod && vox[l - 1] >= 0)
-      interp_level<M, FT>(md, l, vox[l - 1], cx >> (Lp - l), cy >> (Lp - l), cz >> (Lp - l), x, z);
-  if (blend) {
-#pragma unroll
-    for (int k = 0; k < M; ++k) zn[k] = z[k];
-    if (vn >= 0) interp_level<M, FT>(md, lod + 1, vn, cx, cy, cz, x, zn);
-  }
-}
-
-template <int M, typename FT, bool XYZ, int NW, class DEC, bool MFMA>
-__global__ __launch_bounds__(64 * NW) void k_normals(ngl_model md, NormalArgs A) {
-  extern __shared__ __align__(16) char smem[];
-  const int H = md.hidden;
-  const bool blend = A.alpha > 0.0f;
-  DecLds<DEC> S(smem, H, blend && MFMA);
-  if constexpr (MFMA) {
-    DEC::load(md, A.lod, S.frag0, S.w2s0);
-    if (blend) DEC::load(md, A.lod + 1, S.frag1, S.w2s1);
-    __syncthreads();
-  }
-  const float b2a = md.b2[A.lod - 1];
-  const float b2b = blend ? md.b2[A.lod] : 0.0f;
-  const int64_t P = A.P;
-  for (int64_t base = int64_t(blockIdx.x) * (64 * NW); base < P; base += int64_t(gridDim.x) * (64 * NW)) {
-    const int64_t p = base + threadIdx.x;
-    bool act = p < P;
-    float x0[3] = {0.0f, 0.0f, 0.0f};
-    if (act) {
-      if (A.status) {
-        act = A.status[p] == NGL_RAY_HIT;
-        const float t = A.t_hit[p];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) x0[a] = fmaf(t, A.d[a * P + p], A.o[a * P + p]);
-      } else {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) x0[a] = A.x[a * P + p];
-      }
-    }
-    float g[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int e = 0; e < 6; ++e) {
-      const int a = e >> 1;
-      const float sgn = (e & 1) ? -1.0f : 1.0f;
-      float x[3] = {x0[0], x0[1], x0[2]};
-      x[a] = x0[a] + sgn * A.h;
-      float z[M], zn[M];
-      query_z<M, FT, XYZ>(md, x, A.lod, blend, z, zn);
-      float f;
-      if constexpr (MFMA) {
-        DEC::stage(S.stage, x, z);
-        wave_lds_sync();
-        f = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H);
-        if (blend) {
-          wave_lds_sync();
-          DEC::stage(S.stage, x, zn);
-          wave_lds_sync();
-          f = (1.0f - A.alpha) * f + A.alpha * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H);
-        }
-        wave_lds_sync();
-      } else {
-        f = decode_f32<M, XYZ>(md, A.lod, x, z);
-        if (blend) f = (1.0f - A.alpha) * f + A.alpha * decode_f32<M, XYZ>(md, A.lod + 1, x, zn);
-      }
-      g[a] += sgn * f;
-    }
-    if (p < P) {
-      float n[3] = {0.0f, 0.0f, 0.0f};
-      if (act) {
-        const float inv2h = 0.5f / A.h;
-        const float gx = g[0] * inv2h, gy = g[1] * inv2h, gz = g[2] * inv2h;
-        const float len = sqrtf(gx * gx + gy * gy + gz * gz);
-        if (len > 0.0f) {
-          n[0] = gx / len;
-          n[1] = gy / len;
-          n[2] = gz / len;
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < 3; ++a) A.normals[a * P + p] = n[a];
-    }
-  }
-}
-
-template <int M, typename FT, bool XYZ, class DEC, bool MFMA>
-static int launch_normals(const ngl_model& md, const NormalArgs& A, hipStream_t s) {
-  const bool blend = A.alpha > 0.0f;
-  const size_t lds = MFMA ? DecLds<DEC>::fixed_bytes(md.hidden, blend) + 2 * DEC::STAGE_BYTES : 0;
-  int64_t grid = (A.P + 127) / 128;
-  if (grid > 4096) grid = 4096;
-  k_normals<M, FT, XYZ, 2, DEC, MFMA><<<unsigned(grid), 128, lds, s>>>(md, A);
-  NGL_LAUNCHED();
-  return NGL_OK;
-}
-
-template <int M, typename FT, bool XYZ>
-struct NormalOp {
-  static int run(const ngl_model& md, const NormalArgs& A, hipStream_t s) {
-    if (md.w_dtype == NGL_BF16) return launch_normals<M, FT, XYZ, DecBF16<M, XYZ>, true>(md, A, s);
-    if (option(NGL_OPT_F32_DECODER) == 1) return launch_normals<M, FT, XYZ, DecF32<M, XYZ>, true>(md, A, s);
-    return launch_normals<M, FT, XYZ, DecF32<M, XYZ>, false>(md, A, s);
-  }
-};
-
-template <int M, typename FT, bool XYZ>
-static int launch_query(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app,
-                        float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s) {
-  const unsigned grid = unsigned((P + kBlock - 1) / kBlock);
-  k_query<M, FT, XYZ><<<grid, kBlock, 0, s>>>(md, x, P, lod, alpha, app, sdf, valid, vox);
-  NGL_LAUNCHED();
-  return NGL_OK;
-}
-
-template <int M, typename FT, bool XYZ>
-static int launch_query_all(const ngl_model& md, const float* x, int64_t P, float* out, hipStream_t s) {
-  const unsigned grid = unsigned((P + kBlock - 1) / kBlock);
-  k_query_all<M, FT, XYZ><<<grid, kBlock, 0, s>>>(md, x, P, out);
-  NGL_LAUNCHED();
-  return NGL_OK;
-}
-
-// Dispatch over feature width, feature dtype and decoder input layout.
-template <template <int, typename, bool> class F, typename... Args>
-static int dispatch(const ngl_model& md, Args... args) {
-#define NGL_CASE_XYZ(M_, FT_)                                          \
-  return md.with_xyz ? F<M_, FT_, true>::run(md, args...) : F<M_, FT_, false>::run(md, args...)
-#define NGL_CASE_FT(M_)                                                \
-  switch (md.feat_dtype) {                                             \
-    case NGL_F32: NGL_CASE_XYZ(M_, F32);                               \
-    case NGL_F16: NGL_CASE_XYZ(M_, F16);                               \
-    default: NGL_CASE_XYZ(M_, BF16);                                   \
-  }
-  switch (md.feat_dim) {
-    case 8: NGL_CASE_FT(8);
-    case 16: NGL_CASE_FT(16);
-    case 32: NGL_CASE_FT(32);
-    case 64: NGL_CASE_FT(64);
-    default: NGL_FAIL(NGL_E_UNSUPPORTED, "feat_dim %d not compiled (8, 16, 32, 64)", md.feat_dim);
-  }
-#undef NGL_CASE_FT
-#undef NGL_CASE_XYZ
-}
-
-template <int M, typename FT, bool XYZ>
-struct QueryOp {
-  static int run(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app, float* sdf,
-                 uint8_t* valid, int32_t* vox, hipStream_t s) {
-    if (md.w_dtype == NGL_BF16)
-      return launch_query_mfma<M, FT, XYZ, DecBF16<M, XYZ>>(md, x, P, lod, alpha, app, sdf, valid, vox, s);
-    if (option(NGL_OPT_F32_DECODER) == 1)
-      return launch_query_mfma<M, FT, XYZ, DecF32<M, XYZ>>(md, x, P, lod, alpha, app, sdf, valid, vox, s);
-    return launch_query<M, FT, XYZ>(md, x, P, lod, alpha, app, sdf, valid, vox, s);
-  }
-};
-
-template <int M, typename FT, bool XYZ>
-struct QueryAllOp {
-  static int run(const ngl_model& md, const float* x, int64_t P, float* out, hipStream_t s) {
-    return launch_query_all<M, FT, XYZ>(md, x, P, out, s);
-  }
-};
-
-}  // namespace ngl
 
 extern "C" {
 
@@ -385,8 +18,8 @@ int ngl_query_sdf(const ngl_model* m, const float* x, int64_t P, int32_t lod, fl
   NGL_REQUIRE(!(alpha > 0.0f || alpha_pp) || lod < m->num_lods, "blending needs lod < num_lods");
   if (P == 0) return NGL_OK;
   NGL_REQUIRE(x && sdf, "x or sdf is null");
-  return ngl::dispatch<ngl::QueryOp>(*m, x, P, int(lod), alpha, alpha_pp, sdf, valid, vox_out,
-                                     (hipStream_t)stream);
+  using namespace ngl;
+  NGL_BY_WIDTH(m->feat_dim, query_run, *m, x, P, int(lod), alpha, alpha_pp, sdf, valid, vox_out, (hipStream_t)stream)
 }
 
 int ngl_query_sdf_all_lods(const ngl_model* m, const float* x, int64_t P, float* sdf_all, void* stream) {
@@ -396,7 +29,8 @@ int ngl_query_sdf_all_lods(const ngl_model* m, const float* x, int64_t P, float*
   if (P == 0) return NGL_OK;
   NGL_REQUIRE(x && sdf_all, "x or sdf_all is null");
   if (m->w_dtype != NGL_F32) NGL_FAIL(NGL_E_UNSUPPORTED, "all-LOD queries need FP32 decoder weights");
-  return ngl::dispatch<ngl::QueryAllOp>(*m, x, P, sdf_all, (hipStream_t)stream);
+  using namespace ngl;
+  NGL_BY_WIDTH(m->feat_dim, query_all_run, *m, x, P, sdf_all, (hipStream_t)stream)
 }
 
 int ngl_sdf_normals(const ngl_model* m, const float* x, const float* o, const float* d, const float* t_hit,
@@ -413,7 +47,8 @@ int ngl_sdf_normals(const ngl_model* m, const float* x, const float* o, const fl
   NGL_REQUIRE(normals != nullptr, "normals is null");
   NGL_REQUIRE(status ? (o && d && t_hit) : (x != nullptr), "points, or rays with t_hit and status, are required");
   ngl::NormalArgs A{status ? nullptr : x, o, d, t_hit, status, P, int(lod), alpha, h, normals};
-  return ngl::dispatch<ngl::NormalOp>(*m, A, (hipStream_t)stream);
+  using namespace ngl;
+  NGL_BY_WIDTH(m->feat_dim, normals_run, *m, A, (hipStream_t)stream)
 }
 
 }  // extern "C"

@@ -3,438 +3,7 @@
 // ray-octree intersection: outside the current voxel it jumps to the voxel's
 // entry, inside it evaluates the SDF from that voxel and its ancestors and
 // takes a sphere-tracing step.
-#include "ngl_common.h"
-#include "ngl_device.h"
-#include "ngl_mfma.h"
-
-namespace ngl {
-
-struct TraceArgs {
-  const float* o;         // this view's rays, SoA [3][stride]
-  const float* d;
-  int64_t stride;         // SoA stride of o and d
-  int64_t base;           // index of this view's first ray in the outputs
-  int64_t R;              // rays of this view
-  int lod;
-  float alpha;
-  const int32_t* pair_vox;  // this view's hit lists
-  const float* t_in;
-  const float* t_out;
-  const int32_t* ray_off;   // [R+1]
-  ngl_trace_params prm;
-  float* t_hit;           // outputs indexed base + ray
-  uint8_t* status;
-  int32_t* steps;
-  int32_t* hit_vox;
-  unsigned int* counter;  // this view's work queue head (zeroed before the launch)
-  unsigned int* live;     // nullable: rays of this view not yet finished
-  uint64_t* done_clock;   // nullable: timestamp when the view's last ray ends
-};
-
-// One wavefront serves a view's ray queue.  Each lane keeps one ray; a lane
-// whose ray terminates takes the next ray from the queue, so every step is
-// evaluated on a compacted set of active rays.  Every ray ends after at most
-// max_steps evaluations and one pass over its pairs, and the queue is finite,
-// so the loop ends.  All lanes of the wavefront reach the matrix-core decode
-// together (idle lanes stage zeros).
-template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, class DEC>
-__device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLds<DEC>& S, float b2a, float b2b) {
-  const int lane = threadIdx.x & 63;
-  const int64_t R = A.R;
-  const bool blend = A.alpha > 0.0f;
-  const int lod = A.lod;
-  const int Lp = blend ? lod + 1 : lod;
-  const int64_t nv_t = ANALYTIC ? 0 : md.nvox[Lp + 1];
-  const int H = md.hidden;
-  int ray = -1, p = 0, e = 0, k = 0, cp = -1;
-  bool ready = false;
-  float t = 0.0f, prev = __builtin_inff();
-  float oo[3] = {0.0f, 0.0f, 0.0f}, dd[3] = {0.0f, 0.0f, 0.0f};
-  int vox[NGL_MAX_LODS];
-  uint32_t cell[NGL_MAX_LODS];
-#pragma unroll
-  for (int l = 0; l < NGL_MAX_LODS; ++l) {
-    vox[l] = 0;
-    cell[l] = 0;
-  }
-  bool exhausted = false;  // wave-uniform
-  unsigned nfin = 0;       // rays this lane finished since the last report
-#define NGL_FINISH(st_, hv_)            \
-  do {                                  \
-    const int64_t g_ = A.base + ray;    \
-    A.t_hit[g_] = t;                    \
-    A.status[g_] = (st_);               \
-    A.steps[g_] = k;                    \
-    A.hit_vox[g_] = (hv_);              \
-    ray = -1;                           \
-    ready = false;                      \
-    ++nfin;                             \
-  } while (0)
-  for (;;) {
-    // 1. refill idle lanes and move every ray to an evaluable state
-    for (int round = 0; round < 8; ++round) {
-      const uint64_t need = __ballot(ray < 0);
-      if (need && !exhausted) {
-        const int n = __popcll(need);
-        const int first = __ffsll((unsigned long long)need) - 1;
-        unsigned int base = 0;
-        if (lane == first) base = atomicAdd(A.counter, unsigned(n));
-        base = __shfl(base, first, 64);
-        if (int64_t(base) + n >= R) exhausted = true;
-        if (ray < 0) {
-          const int64_t my = int64_t(base) + __popcll(need & ((1ull << lane) - 1ull));
-          if (my < R) {
-            ray = int(my);
-            p = A.ray_off[ray];
-            e = A.ray_off[ray + 1];
-            k = 0;
-            cp = -1;
-            prev = __builtin_inff();
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              oo[a] = A.o[a * A.stride + ray];
-              dd[a] = A.d[a * A.stride + ray];
-            }
-            t = p < e ? A.t_in[p] : 0.0f;
-            bool bad = false;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) bad = bad || !__builtin_isfinite(oo[a]) || !__builtin_isfinite(dd[a]);
-            if (bad) NGL_FINISH(NGL_RAY_INVALID, -1);
-          }
-        }
-      }
-      if (ray >= 0 && !ready) {
-        while (p < e && t > A.t_out[p]) ++p;  // empty space: next voxel
-        if (p == e) {
-          NGL_FINISH(NGL_RAY_MISS, -1);
-        } else {
-          const float ti = A.t_in[p];
-          if (t < ti) t = ti;  // outside the voxel: jump to its entry
-          if (t > A.prm.t_far) NGL_FINISH(NGL_RAY_FAR, -1);
-          else if (k == A.prm.max_steps) NGL_FINISH(NGL_RAY_MAX_STEPS, -1);
-          else ready = true;
-        }
-      }
-      const bool waiting = (ray < 0 && !exhausted) || (ray >= 0 && !ready);
-      if (__ballot(waiting) == 0) break;
-    }
-    const bool act = ray >= 0 && ready;
-    const bool any_act = __ballot(act) != 0;
-    const bool done = !any_act && exhausted && __ballot(ray >= 0) == 0;
-    if (any_act) {
-      // 2. one SDF evaluation per active lane
-      float dist = 0.0f;
-      int32_t v = -1;
-      float x[3] = {0.0f, 0.0f, 0.0f};
-      float z[M];
-#pragma unroll
-      for (int q = 0; q < M; ++q) z[q] = 0.0f;
-      bool ok = false;  // this lane evaluates the model
-      if (act) {
-        x[0] = fmaf(t, dd[0], oo[0]);
-        x[1] = fmaf(t, dd[1], oo[1]);
-        x[2] = fmaf(t, dd[2], oo[2]);
-        v = A.pair_vox[p];
-        if constexpr (ANALYTIC) {
-          const float q0 = x[0] - A.prm.sphere[0], q1 = x[1] - A.prm.sphere[1], q2 = x[2] - A.prm.sphere[2];
-          dist = sqrtf(q0 * q0 + q1 * q1 + q2 * q2) - A.prm.sphere[3];
-        } else {
-          if (v < 0 || int64_t(v) >= nv_t) {
-            NGL_FINISH(NGL_RAY_INVALID, -1);  // hit list does not belong to this depth
-          } else {
-            if (p != cp) {
-              // ancestor chain of the pair's voxel (parents always exist)
-              int w = v;
-#pragma unroll
-              for (int l = NGL_MAX_LODS; l >= 1; --l) {
-                if (l <= Lp) {
-                  vox[l - 1] = w;
-                  cell[l - 1] = md.cell[l + 1][w];
-                  w = md.parent[l + 1][w];
-                }
-              }
-              cp = p;
-            }
-#pragma unroll
-            for (int l = 1; l <= NGL_MAX_LODS; ++l)
-              if (l <= lod)
-                interp_level<M, FT>(md, l, vox[l - 1], cell_x(cell[l - 1]), cell_y(cell[l - 1]), cell_z(cell[l - 1]),
-                                    x, z);
-            ok = true;
-          }
-        }
-      }
-      if constexpr (!ANALYTIC) {
-        if constexpr (MFMA) {
-          DEC::stage(S.stage, x, z);
-          wave_lds_sync();
-          dist = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H);
-          if (blend) {
-            // with alpha > 0 the pair voxel is the level lod+1 voxel
-            if (ok) {
-              const uint32_t c = md.cell[Lp + 1][v];
-              interp_level<M, FT>(md, lod + 1, v, cell_x(c), cell_y(c), cell_z(c), x, z);
-            }
-            wave_lds_sync();
-            DEC::stage(S.stage, x, z);
-            wave_lds_sync();
-            dist = (1.0f - A.alpha) * dist + A.alpha * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H);
-          }
-          wave_lds_sync();
-        } else if (ok) {
-          dist = decode_f32<M, XYZ>(md, lod, x, z);
-          if (blend) {
-            const uint32_t c = md.cell[Lp + 1][v];
-            interp_level<M, FT>(md, lod + 1, v, cell_x(c), cell_y(c), cell_z(c), x, z);
-            dist = (1.0f - A.alpha) * dist + A.alpha * decode_f32<M, XYZ>(md, lod + 1, x, z);
-          }
-        }
-      }
-      // 3. step
-      if (act && ray >= 0) {
-        ++k;
-        if (dist < A.prm.delta) {
-          NGL_FINISH(NGL_RAY_HIT, v);
-        } else if (A.prm.osc_check && fabsf(dist - prev) < 6.0f * A.prm.delta) {
-          NGL_FINISH(NGL_RAY_STALLED, -1);
-        } else {
-          prev = dist;
-          t += dist;
-          ready = false;
-        }
-      }
-    }
-    if (A.live) {
-      // report finished rays once per iteration; the wavefront that takes
-      // the count to zero stamps the view's end time
-      unsigned tot = nfin;
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off, 64);
-      nfin = 0;
-      if (lane == 0 && tot > 0) {
-        const unsigned old = atomicSub(A.live, tot);
-        if (old == tot && A.done_clock) *A.done_clock = wall_clock64();
-      }
-    }
-    if (done) break;
-  }
-}
-
-#undef NGL_FINISH
-
-template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW, class DEC>
-__global__ __launch_bounds__(64 * NW) void k_sphere_trace(ngl_model md, TraceArgs A) {
-  extern __shared__ __align__(16) char smem[];
-  const bool blend = A.alpha > 0.0f;
-  const int H = md.hidden;
-  DecLds<DEC> S(smem, H, blend && MFMA);
-  float b2a = 0.0f, b2b = 0.0f;
-  if constexpr (MFMA) {
-    DEC::load(md, A.lod, S.frag0, S.w2s0);
-    if (blend) DEC::load(md, A.lod + 1, S.frag1, S.w2s1);
-    __syncthreads();
-    b2a = md.b2[A.lod - 1];
-    b2b = blend ? md.b2[A.lod] : 0.0f;
-  }
-  serve_queue<M, FT, XYZ, ANALYTIC, MFMA, DEC>(md, A, S, b2a, b2b);
-}
-
-// Batched form: views in one launch.  Each block walks the views once, in
-// rotation from its own start; at each view that still has queued rays it
-// copies the model into LDS, stages its decoder and serves the view's queue
-// with all its wavefronts, then moves on.  Every block visits each view at
-// most once, so the grid drains.
-struct BatchView {
-  int64_t base;      // first ray of the view in the concatenated arrays
-  int64_t R;
-  int32_t lod;
-  float alpha;
-};
-
-struct BatchArgs {
-  const ngl_model* table;  // device [n]
-  int n;
-  BatchView view[NGL_MAX_BATCH];
-  const float* o;          // view i's rays: SoA block [3][R_i] at 3 * base_i
-  const float* d;
-  int64_t cap;             // pair capacity per view
-  const int32_t* pair_vox;  // [n][cap]
-  const float* t_in;
-  const float* t_out;
-  const int32_t* ray_off;   // view i at base_i + i, [R_i + 1]
-  ngl_trace_params prm;
-  float* t_hit;
-  uint8_t* status;
-  int32_t* steps;
-  int32_t* hit_vox;
-  unsigned int* counters;   // [n] queue heads
-  unsigned int* live;       // [n] unfinished rays
-  uint64_t* clock;          // nullable [n+1]
-};
-
-template <int M, typename FT, bool XYZ, int NW, class DEC>
-__global__ __launch_bounds__(64 * NW) void k_trace_batch(BatchArgs B) {
-  extern __shared__ __align__(16) char smem[];
-  __shared__ ngl_model smd;
-  __shared__ int s_has;
-  const int H = B.table[0].hidden;
-  for (int step = 0; step < B.n; ++step) {
-    const int v = (int(blockIdx.x) + step) % B.n;
-    if (threadIdx.x == 0) s_has = int64_t(__atomic_load_n(&B.counters[v], __ATOMIC_RELAXED)) < B.view[v].R;
-    __syncthreads();
-    if (!s_has) {
-      __syncthreads();
-      continue;
-    }
-    {
-      const uint32_t* src = reinterpret_cast<const uint32_t*>(B.table + v);
-      uint32_t* dst = reinterpret_cast<uint32_t*>(&smd);
-      for (int w = threadIdx.x; w < int(sizeof(ngl_model) / 4); w += blockDim.x) dst[w] = src[w];
-    }
-    __syncthreads();
-    TraceArgs A{};
-    A.o = B.o + 3 * B.view[v].base;  // each view's rays are one SoA block
-    A.d = B.d + 3 * B.view[v].base;
-    A.stride = B.view[v].R;
-    A.base = B.view[v].base;
-    A.R = B.view[v].R;
-    A.lod = B.view[v].lod;
-    A.alpha = B.view[v].alpha;
-    A.pair_vox = B.pair_vox + int64_t(v) * B.cap;
-    A.t_in = B.t_in + int64_t(v) * B.cap;
-    A.t_out = B.t_out + int64_t(v) * B.cap;
-    A.ray_off = B.ray_off + B.view[v].base + v;
-    A.prm = B.prm;
-    A.t_hit = B.t_hit;
-    A.status = B.status;
-    A.steps = B.steps;
-    A.hit_vox = B.hit_vox;
-    A.counter = B.counters + v;
-    A.live = B.live + v;
-    A.done_clock = B.clock ? B.clock + 1 + v : nullptr;
-    const bool blend = A.alpha > 0.0f;
-    DecLds<DEC> S(smem, H, blend);
-    DEC::load(smd, A.lod, S.frag0, S.w2s0);
-    if (blend) DEC::load(smd, A.lod + 1, S.frag1, S.w2s1);
-    __syncthreads();
-    serve_queue<M, FT, XYZ, false, true, DEC>(smd, A, S, smd.b2[A.lod - 1], blend ? smd.b2[A.lod] : 0.0f);
-    __syncthreads();  // every wavefront is done with this view's LDS
-  }
-}
-
-__global__ void k_zero_counter(unsigned int* c) {
-  if (threadIdx.x == 0) *c = 0u;
-}
-
-// Enough blocks to fill every CU at the kernel's occupancy (one value per
-// instantiation, computed on first use).
-template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW, class DEC>
-static int persistent_grid(size_t lds) {
-  static int cached = 0;
-  if (cached) return cached;
-  int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 1024;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
-  const void* kern = reinterpret_cast<const void*>(&k_sphere_trace<M, FT, XYZ, ANALYTIC, MFMA, NW, DEC>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
-  cached = cus * per;
-  return cached;
-}
-
-template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW, class DEC>
-static int launch_trace_nw(const ngl_model& md, const TraceArgs& A, hipStream_t s, size_t lds) {
-  k_zero_counter<<<1, 64, 0, s>>>(A.counter);
-  int grid = persistent_grid<M, FT, XYZ, ANALYTIC, MFMA, NW, DEC>(lds);
-  const int bpc = option(NGL_OPT_TRACE_BLOCKS_PER_CU);
-  if (bpc > 0) {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (cus * bpc < grid) grid = cus * bpc;
-  }
-  const int64_t need = (A.R + 64 * NW - 1) / (64 * NW);
-  if (need < grid) grid = int(need);
-  k_sphere_trace<M, FT, XYZ, ANALYTIC, MFMA, NW, DEC><<<grid, 64 * NW, lds, s>>>(md, A);
-  NGL_LAUNCHED();
-  return NGL_OK;
-}
-
-template <int M, typename FT, bool XYZ, class DEC>
-static int launch_trace_mfma(const ngl_model& md, const TraceArgs& A, hipStream_t s) {
-  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, A.alpha > 0.0f);
-  const int want = option(NGL_OPT_TRACE_WAVES);
-  if ((want == 0 || want >= 4) && fixed + 4 * DEC::STAGE_BYTES <= 65536)
-    return launch_trace_nw<M, FT, XYZ, false, true, 4, DEC>(md, A, s, fixed + 4 * DEC::STAGE_BYTES);
-  if ((want == 0 || want >= 2) && fixed + 2 * DEC::STAGE_BYTES <= 65536)
-    return launch_trace_nw<M, FT, XYZ, false, true, 2, DEC>(md, A, s, fixed + 2 * DEC::STAGE_BYTES);
-  return launch_trace_nw<M, FT, XYZ, false, true, 1, DEC>(md, A, s, fixed + DEC::STAGE_BYTES);
-}
-
-template <int M, typename FT, bool XYZ, bool ANALYTIC>
-static int launch_trace(const ngl_model& md, const TraceArgs& A, hipStream_t s) {
-  if (ANALYTIC) return launch_trace_nw<M, FT, XYZ, true, false, 4, DecF32<M, XYZ>>(md, A, s, 0);
-  if (md.w_dtype == NGL_BF16) return launch_trace_mfma<M, FT, XYZ, DecBF16<M, XYZ>>(md, A, s);
-  if (option(NGL_OPT_F32_DECODER) == 1) return launch_trace_mfma<M, FT, XYZ, DecF32<M, XYZ>>(md, A, s);
-  return launch_trace_nw<M, FT, XYZ, false, false, 4, DecF32<M, XYZ>>(md, A, s, 0);
-}
-
-template <int M, typename FT, bool XYZ, int NW, class DEC>
-static int launch_batch_nw(const BatchArgs& B, hipStream_t s, size_t lds) {
-  static int per = 0;
-  static int cus = 0;
-  if (!per) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    const void* kern = reinterpret_cast<const void*>(&k_trace_batch<M, FT, XYZ, NW, DEC>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
-  }
-  int grid = cus * per;
-  const int cap = option(NGL_OPT_TRACE_BLOCKS_PER_CU);
-  if (cap > 0 && cap < per) grid = cus * cap;
-  k_trace_batch<M, FT, XYZ, NW, DEC><<<grid, 64 * NW, lds, s>>>(B);
-  NGL_LAUNCHED();
-  return NGL_OK;
-}
-
-template <int M, typename FT, bool XYZ, class DEC>
-static int launch_batch(const BatchArgs& B, bool any_blend, int H, hipStream_t s) {
-  const size_t fixed = DecLds<DEC>::fixed_bytes(H, any_blend);
-  const int want = option(NGL_OPT_TRACE_WAVES);
-  if ((want == 0 || want >= 4) && fixed + 4 * DEC::STAGE_BYTES <= 65536)
-    return launch_batch_nw<M, FT, XYZ, 4, DEC>(B, s, fixed + 4 * DEC::STAGE_BYTES);
-  if ((want == 0 || want >= 2) && fixed + 2 * DEC::STAGE_BYTES <= 65536)
-    return launch_batch_nw<M, FT, XYZ, 2, DEC>(B, s, fixed + 2 * DEC::STAGE_BYTES);
-  return launch_batch_nw<M, FT, XYZ, 1, DEC>(B, s, fixed + DEC::STAGE_BYTES);
-}
-
-template <int M, typename FT, bool XYZ>
-struct BatchOp {
-  static int run(const ngl_model& md, const BatchArgs& B, bool any_blend, hipStream_t s) {
-    if (md.w_dtype == NGL_BF16) return launch_batch<M, FT, XYZ, DecBF16<M, XYZ>>(B, any_blend, md.hidden, s);
-    return launch_batch<M, FT, XYZ, DecF32<M, XYZ>>(B, any_blend, md.hidden, s);
-  }
-};
-
-struct BatchInit {
-  int n;
-  int64_t R[NGL_MAX_BATCH];
-};
-
-__global__ void k_batch_init(unsigned int* counters, unsigned int* live, BatchInit I, uint64_t* clock) {
-  const int i = threadIdx.x;
-  if (i < I.n) {
-    counters[i] = 0u;
-    live[i] = unsigned(I.R[i]);
-  }
-  if (i == 0 && clock) clock[0] = wall_clock64();
-}
-
-template <int M, typename FT, bool XYZ>
-struct TraceOp {
-  static int run(const ngl_model& md, const TraceArgs& A, hipStream_t s) { return launch_trace<M, FT, XYZ, false>(md, A, s); }
-};
-
-}  // namespace ngl
+#include "ngl_trace_impl.h"
 
 extern "C" {
 
@@ -466,25 +35,8 @@ int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t
   hipStream_t s = (hipStream_t)stream;
   TraceArgs A{o, d, R, 0, R, int(lod), alpha, pair_vox, t_in, t_out, ray_off, *params, t_hit, status, steps,
               hit_vox, static_cast<unsigned int*>(ws), nullptr, nullptr};
-  if (analytic) return launch_trace<8, F32, true, true>(*m, A, s);
-  const ngl_model& md = *m;
-#define NGL_TRACE_XYZ(M_, FT_) \
-  return md.with_xyz ? TraceOp<M_, FT_, true>::run(md, A, s) : TraceOp<M_, FT_, false>::run(md, A, s)
-#define NGL_TRACE_FT(M_)                   \
-  switch (md.feat_dtype) {                 \
-    case NGL_F32: NGL_TRACE_XYZ(M_, F32);  \
-    case NGL_F16: NGL_TRACE_XYZ(M_, F16);  \
-    default: NGL_TRACE_XYZ(M_, BF16);      \
-  }
-  switch (md.feat_dim) {
-    case 8: NGL_TRACE_FT(8);
-    case 16: NGL_TRACE_FT(16);
-    case 32: NGL_TRACE_FT(32);
-    case 64: NGL_TRACE_FT(64);
-    default: NGL_FAIL(NGL_E_UNSUPPORTED, "feat_dim %d not compiled (8, 16, 32, 64)", md.feat_dim);
-  }
-#undef NGL_TRACE_FT
-#undef NGL_TRACE_XYZ
+  if (analytic) return trace_run_analytic(*m, A, s);
+  NGL_BY_WIDTH(m->feat_dim, trace_run, *m, A, s)
 }
 
 int ngl_model_table_bytes(int32_t n, size_t* bytes) {
@@ -631,23 +183,7 @@ int ngl_render_batch(const ngl_model* models, const void* table, const ngl_view*
   B.counters = L.counters;
   B.live = L.live;
   B.clock = frame_clock;
-#define NGL_BATCH_XYZ(M_, FT_) \
-  return m0.with_xyz ? BatchOp<M_, FT_, true>::run(m0, B, any_blend, s) : BatchOp<M_, FT_, false>::run(m0, B, any_blend, s)
-#define NGL_BATCH_FT(M_)                   \
-  switch (m0.feat_dtype) {                 \
-    case NGL_F32: NGL_BATCH_XYZ(M_, F32);  \
-    case NGL_F16: NGL_BATCH_XYZ(M_, F16);  \
-    default: NGL_BATCH_XYZ(M_, BF16);      \
-  }
-  switch (m0.feat_dim) {
-    case 8: NGL_BATCH_FT(8);
-    case 16: NGL_BATCH_FT(16);
-    case 32: NGL_BATCH_FT(32);
-    case 64: NGL_BATCH_FT(64);
-    default: NGL_FAIL(NGL_E_UNSUPPORTED, "feat_dim %d not compiled (8, 16, 32, 64)", m0.feat_dim);
-  }
-#undef NGL_BATCH_FT
-#undef NGL_BATCH_XYZ
+  NGL_BY_WIDTH(m0.feat_dim, batch_run, m0, B, any_blend, s)
 }
 
 }  // extern "C"

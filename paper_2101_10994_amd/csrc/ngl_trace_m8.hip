@@ -1,0 +1,11 @@
+// Sphere-tracing kernel instantiations for feature width 8.
+#include "ngl_trace_impl.h"
+
+namespace ngl {
+
+NGL_TRACE_DEFINE(8)
+int trace_run_analytic(const ngl_model& md, const TraceArgs& A, hipStream_t s) {
+  return launch_trace<8, F32, true, true>(md, A, s);
+}
+
+}  // namespace ngl

@@ -74,6 +74,7 @@ EXPORTS = {
     "ngl_octree_fill": (C.c_int, [P, i64, i32, P]),
     "ngl_query_sdf": (C.c_int, [P, P, i64, i32, C.c_float, P, P, P, P, P]),
     "ngl_query_sdf_all_lods": (C.c_int, [P, P, i64, P, P]),
+    "ngl_decode_sdf": (C.c_int, [P, i32, P, P, i32, i64, P, P]),
     "ngl_sdf_normals": (C.c_int, [P, P, P, P, P, P, i64, i32, C.c_float, C.c_float, P, P]),
     "ngl_camera_rays": (C.c_int, [P, P, P, C.c_float, i32, i32, P, P, P]),
     "ngl_trace_octree_workspace": (C.c_int, [i64, i64, P]),
@@ -318,6 +319,20 @@ def query_sdf_all_lods(model: Model, x: torch.Tensor, out: torch.Tensor = None) 
     o = out if out is not None else torch.empty((model.num_lods, Pn), dtype=torch.float32, device=x.device)
     _check(lib().ngl_query_sdf_all_lods(model.ref, _ptr(x), Pn, _ptr(o), _stream()))
     return o
+
+
+def decode_sdf(model: Model, lod: int, z: torch.Tensor, x: torch.Tensor = None, out: torch.Tensor = None):
+    """Decoder `lod` on given inputs: z [P][m] (float32 or bfloat16 rows,
+    device), x [3][P] float32 when the model reads the position."""
+    if z.dtype not in (torch.float32, torch.bfloat16) or not z.is_cuda or not z.is_contiguous():
+        raise NGLError("z must be a contiguous float32 or bfloat16 device tensor")
+    Pn = z.shape[0]
+    if x is not None:
+        _dev(x, torch.float32)
+    sdf = out if out is not None else torch.empty(Pn, dtype=torch.float32, device=z.device)
+    zt = BF16 if z.dtype == torch.bfloat16 else F32
+    _check(lib().ngl_decode_sdf(model.ref, int(lod), _ptr(x), _ptr(z), zt, Pn, _ptr(sdf), _stream()))
+    return sdf
 
 
 def default_normal_step(model: "Model") -> float:

@@ -1,0 +1,95 @@
+"""GPU parity: the decoder alone (Eq. 2's per-LOD MLP) on given [x, z]
+against the FP64 oracle.  FP32 weights: |d| <= 1e-5 s; BF16 weights (inputs
+rounded to BF16 on the GPU): |d| <= 2e-3 s1, with s and s1 the oracle's
+magnitude scales of each point."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2101_10994_amd import workloads as W
+
+from cases import make_case
+
+pytestmark = pytest.mark.gpu
+TOL, TOL16 = 1e-5, 2e-3
+
+
+def run(case, lod, P, zdt, seed=0, scale=0.3):
+    import torch
+    from paper_2101_10994_amd import ngl
+    rng = np.random.default_rng(seed)
+    z = rng.normal(0.0, scale, size=(P, case.m))
+    x = W.soa(rng.uniform(-1, 1, size=(P, 3)))
+    zt = torch.tensor(z, dtype=torch.float64).to(torch.bfloat16 if zdt == "bf16" else torch.float32)
+    z_stored = zt.to(torch.float64).numpy()
+    gm = case.gpu_model()
+    xd = torch.from_numpy(x).cuda() if case.with_xyz else None
+    g = ngl.decode_sdf(gm, lod, zt.cuda().contiguous(), x=xd).cpu().numpy().astype(np.float64)
+    o = oracle.decode(case.oracle_model(), lod, z_stored, x)
+    return g, o
+
+
+def check(g, o, tol, key):
+    err = np.abs(g - o["sdf"])
+    bound = tol * o[key]
+    bad = np.nonzero(err > bound)[0]
+    assert bad.size == 0, (bad[:10], err[bad[:10]], bound[bad[:10]])
+
+
+@pytest.mark.parametrize("m,H", [(8, 32), (16, 64), (32, 128), (64, 128), (32, 256), (32, 16)])
+@pytest.mark.parametrize("zdt", ["bf16", "f32"])
+def test_bf16_weights(m, H, zdt):
+    case = make_case(W.tiny_shape(), 16, 3, m, H, seed=m + H, w_dtype="bf16")
+    for lod in (1, 3):
+        g, o = run(case, lod, 4099, zdt, seed=lod)
+        check(g, o, TOL16, "scale1")
+
+
+@pytest.mark.parametrize("with_xyz", [True, False])
+def test_without_position_and_ragged_sizes(with_xyz):
+    case = make_case(W.tiny_shape(), 16, 3, 32, 128, seed=3, w_dtype="bf16", with_xyz=with_xyz)
+    for P in (1, 15, 16, 17, 63, 65, 1000):
+        g, o = run(case, 2, P, "bf16", seed=P)
+        check(g, o, TOL16, "scale1")
+
+
+@pytest.mark.parametrize("zdt", ["bf16", "f32"])
+def test_fp32_weights(zdt, f32_decoder):
+    case = make_case(W.tiny_shape(), 16, 3, 32, 128, seed=4)
+    g, o = run(case, 3, 5000, zdt, seed=9)
+    check(g, o, TOL, "scale")
+
+
+def test_paper_scale_decoder():
+    """2^20 points, m = 32, h = 128, BF16 weights and BF16 z; every 97th
+    point compared."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    case = make_case(W.paper_shape(0), 64, 5, 32, 128, seed=5, w_dtype="bf16")
+    P = 1 << 20
+    rng = np.random.default_rng(5)
+    z = torch.tensor(rng.normal(0.0, 0.3, size=(P, 32)), dtype=torch.float64).to(torch.bfloat16)
+    x = W.soa(rng.uniform(-1, 1, size=(P, 3)))
+    g = ngl.decode_sdf(case.gpu_model(), 5, z.cuda(), x=torch.from_numpy(x).cuda()).cpu().numpy()
+    idx = np.arange(0, P, 97)
+    o = oracle.decode(case.oracle_model(), 5, z.to(torch.float64).numpy()[idx], np.ascontiguousarray(x[:, idx]))
+    check(g[idx].astype(np.float64), o, TOL16, "scale1")
+
+
+def test_arguments():
+    import torch
+    from paper_2101_10994_amd import ngl
+    case = make_case(W.tiny_shape(), 16, 3, 8, 32, seed=6, w_dtype="bf16")
+    gm = case.gpu_model()
+    z = torch.zeros((10, 8), dtype=torch.bfloat16, device="cuda")
+    x = torch.zeros((3, 10), dtype=torch.float32, device="cuda")
+    assert ngl.decode_sdf(gm, 1, z[:0], x=x[:, :0]).shape == (0,)
+    with pytest.raises(ngl.NGLError):
+        ngl.decode_sdf(gm, 4, z, x=x)
+    with pytest.raises(ngl.NGLError):
+        ngl.decode_sdf(gm, 1, z)  # position input missing
+    zz = torch.zeros(10 * 8 + 1, dtype=torch.bfloat16, device="cuda")[1:].view(10, 8)
+    with pytest.raises(ngl.NGLError):
+        ngl.decode_sdf(gm, 1, zz, x=x)  # misaligned rows
+    with pytest.raises(ngl.NGLError):
+        ngl.decode_sdf(gm, 1, z.half(), x=x)
