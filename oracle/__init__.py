@@ -15,6 +15,8 @@ Entry points and the passage each one follows:
 * ``camera_rays``     -- pinhole primary rays (the ray set of Alg. 1)
 * ``sphere_trace``    -- adaptive-stepping sphere tracing (Sec. 3.4, Fig. 3;
                          stopping rules of App. A.4)
+* ``lod_select``      -- per-pixel LOD from distance (Sec. 3.4, LOD Selection)
+* ``sphere_trace_pp`` -- sphere tracing with a LOD and blend weight per ray
 * ``normals``         -- surface normals by central finite differences of
                          ``query`` (App. A.4), at points or ray hit points
 * ``train_fwd_bwd``   -- Eq. 4 loss and its gradient (Sec. 3.3)
@@ -98,6 +100,9 @@ def _setup(lib):
     lib.orc_sphere_trace.restype = C.c_int
     lib.orc_sphere_trace.argtypes = [P, P, P, P, i64, C.c_int, C.c_double, P, P, P, P, P,
                                      P, P, P, P, P]
+    lib.orc_sphere_trace_pp.restype = C.c_int
+    lib.orc_sphere_trace_pp.argtypes = [P, P, P, P, i64, C.c_int, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_lod_select.argtypes = [C.c_float, C.c_float, C.c_float, C.c_float, C.c_int, C.c_float, P, P, P]
     lib.orc_train_fwd_bwd.restype = C.c_int
     lib.orc_train_fwd_bwd.argtypes = [P, P, P, P, i64, P, P, P, P, P, P, P]
 
@@ -376,6 +381,65 @@ def sphere_trace(tree: Octree, model: Model, o_soa, d_soa, lod: int, alpha: floa
                                   _ptr(status), _ptr(steps), _ptr(hv), _ptr(marg))
     if rc != 0:
         raise ValueError("oracle sphere_trace: invalid arguments")
+    return dict(t=t_hit, status=status, steps=steps, hit_vox=hv, marginal=marg)
+
+
+def lod_select(d_near: float, d_far: float, lod_near: float, lod_far: float, num_lods: int, dist):
+    """Per-ray continuous LOD from a distance, in FP32 (see orc_lod_select).
+    Returns (lod_cont float32, lod_int int32, alpha float32) arrays."""
+    dist = np.atleast_1d(np.asarray(dist, np.float32))
+    Lc = np.zeros(len(dist), np.float32)
+    Li = np.zeros(len(dist), np.int32)
+    al = np.zeros(len(dist), np.float32)
+    lib = _load()
+    out_c, out_i, out_a = C.c_float(), C.c_int32(), C.c_float()
+    for k, v in enumerate(dist):
+        lib.orc_lod_select(float(d_near), float(d_far), float(lod_near), float(lod_far), int(num_lods), float(v),
+                           C.byref(out_c), C.byref(out_i), C.byref(out_a))
+        Lc[k], Li[k], al[k] = out_c.value, out_i.value, out_a.value
+    return Lc, Li, al
+
+
+def first_pair_distance(hits: dict, R: int, t_far: float):
+    """Entry distance of each ray's first pair (t_far when it has none)."""
+    off = np.asarray(hits["ray_off"], np.int64)
+    t_in = np.asarray(hits["t_in"], np.float32)
+    has = off[1:] > off[:-1]
+    dist = np.full(R, np.float32(t_far), np.float32)
+    dist[has] = t_in[off[:-1][has]]
+    return dist
+
+
+def sphere_trace_pp(tree: Octree, model: Model, o_soa, d_soa, pair_depth: int, lod_pp, alpha_pp, hits: dict,
+                    max_steps: int, delta: float, t_far: float = 5.0, osc_check: bool = False,
+                    margin_sdf: float = 0.0, margin_t: float = 0.0):
+    """Sphere trace with per-ray LOD and blend weight over hit lists at
+    `pair_depth` (see orc_sphere_trace_pp)."""
+    o = _c(o_soa, np.float32)
+    d = _c(d_soa, np.float32)
+    R = o.shape[1]
+    prm = _TraceParams()
+    prm.max_steps = int(max_steps)
+    prm.delta = float(delta)
+    prm.t_far = float(t_far)
+    prm.osc_check = int(osc_check)
+    prm.analytic = 0
+    prm.margin_sdf = float(margin_sdf)
+    prm.margin_t = float(margin_t)
+    t_hit = np.zeros(R)
+    status = np.zeros(R, np.uint8)
+    steps = np.zeros(R, np.int32)
+    hv = np.zeros(R, np.int32)
+    marg = np.zeros(R, np.uint8)
+    ms = model.struct()
+    lp = _c(lod_pp, np.int32)
+    ap = _c(alpha_pp, np.float32)
+    rc = _load().orc_sphere_trace_pp(tree._h, C.addressof(ms), _ptr(o), _ptr(d), R, int(pair_depth), _ptr(lp),
+                                     _ptr(ap), _ptr(hits["vox"]), _ptr(hits["t_in"]), _ptr(hits["t_out"]),
+                                     _ptr(_c(hits["ray_off"], np.int64)), C.addressof(prm), _ptr(t_hit),
+                                     _ptr(status), _ptr(steps), _ptr(hv), _ptr(marg))
+    if rc != 0:
+        raise ValueError("oracle sphere_trace_pp: invalid arguments")
     return dict(t=t_hit, status=status, steps=steps, hit_vox=hv, marginal=marg)
 
 

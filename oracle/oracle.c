@@ -604,16 +604,16 @@ typedef struct {
 /* SDF at x using the voxel `v` of depth Lt+1 and its ancestors (Sec. 3.4:
  * the parents of a traced voxel always exist).  Lt = lod, or lod+1 when
  * blending with alpha > 0. */
-static double query_in_voxel(const orc_octree* t, const orc_model* M, int lod, double alpha, int64_t v,
-                             const double x[3], double* scale) {
+static double query_in_voxel(const orc_octree* t, const orc_model* M, int lod, double alpha, int pair_depth,
+                             int64_t v, const double x[3], double* scale) {
   int Lp = alpha > 0.0 ? lod + 1 : lod;
   int m = M->m;
   int64_t vx, vy, vz;
-  demorton3(t->code[Lp + 1][v], &vx, &vy, &vz);
+  demorton3(t->code[pair_depth][v], &vx, &vy, &vz);
   double z[64], zn[64], psi[64];
   for (int k = 0; k < m; ++k) z[k] = zn[k] = 0.0;
   for (int l = 1; l <= Lp; ++l) {
-    int s = Lp - l;
+    int s = (pair_depth - 1) - l; /* level l lives at depth l + 1 */
     int64_t cell[3] = {vx >> s, vy >> s, vz >> s};
     interp_level(t, M, l, cell, x, psi);
     if (l <= lod) for (int k = 0; k < m; ++k) z[k] += psi[k];
@@ -642,58 +642,116 @@ static double query_in_voxel(const orc_octree* t, const orc_model* M, int lod, d
  * `marginal` flag for rays whose outcome could flip under small
  * perturbations (see orc_trace_params).
  */
+static void trace_ray(const orc_octree* t, const orc_model* M, const float* o, const float* d, int64_t R,
+                      int64_t i, int lod, double alpha, int pair_depth, const int32_t* pair_vox,
+                      const float* t_in, const float* t_out, const int64_t* ray_off,
+                      const orc_trace_params* prm, double* t_hit, uint8_t* status, int32_t* steps,
+                      int32_t* hit_vox, uint8_t* marginal) {
+  double oo[3] = {o[i], o[R + i], o[2 * R + i]};
+  double dd[3] = {d[i], d[R + i], d[2 * R + i]};
+  int64_t b = ray_off[i], e = ray_off[i + 1];
+  int64_t p = b;
+  double t_cur = b < e ? (double)t_in[b] : 0.0;
+  int k = 0;
+  double prev = INFINITY;
+  uint8_t st = ORC_MISS, marg = 0;
+  int32_t hv = -1;
+  int bad = 0;
+  for (int a = 0; a < 3; ++a) if (!isfinite(oo[a]) || !isfinite(dd[a])) bad = 1;
+  if (bad) { st = ORC_INVALID; e = b; }
+  for (;;) {
+    if (bad) break;
+    while (p < e && t_cur > (double)t_out[p]) {
+      if (fabs(t_cur - (double)t_out[p]) <= prm->margin_t * (1.0 + fabs(t_cur))) marg = 1;
+      ++p;
+    }
+    if (p < e && fabs(t_cur - (double)t_out[p]) <= prm->margin_t * (1.0 + fabs(t_cur))) marg = 1;
+    if (p == e) { st = ORC_MISS; break; }
+    if (t_cur < (double)t_in[p]) t_cur = (double)t_in[p];
+    if (t_cur > prm->t_far) { st = ORC_FAR; break; }
+    if (k == prm->max_steps) { st = ORC_MAX_STEPS; break; }
+    double x[3] = {oo[0] + t_cur * dd[0], oo[1] + t_cur * dd[1], oo[2] + t_cur * dd[2]};
+    double scale = 1.0, dist;
+    if (prm->analytic) {
+      double q0 = x[0] - prm->sphere[0], q1 = x[1] - prm->sphere[1], q2 = x[2] - prm->sphere[2];
+      dist = sqrt(q0 * q0 + q1 * q1 + q2 * q2) - prm->sphere[3];
+    } else {
+      dist = query_in_voxel(t, M, lod, alpha, pair_depth, pair_vox[p], x, &scale);
+    }
+    ++k;
+    if (fabs(dist - prm->delta) <= prm->margin_sdf * scale) marg = 1;
+    if (dist < prm->delta) { st = ORC_HIT; hv = pair_vox[p]; break; }
+    if (prm->osc_check && fabs(dist - prev) < 6.0 * prm->delta) { st = ORC_STALLED; break; }
+    prev = dist;
+    t_cur += dist;
+  }
+  t_hit[i] = t_cur;
+  status[i] = st;
+  steps[i] = k;
+  hit_vox[i] = hv;
+  if (marginal) marginal[i] = marg;
+}
+
 int orc_sphere_trace(const orc_octree* t, const orc_model* M, const float* o, const float* d, int64_t R,
                      int lod, double alpha, const int32_t* pair_vox, const float* t_in, const float* t_out,
                      const int64_t* ray_off, const orc_trace_params* prm, double* t_hit, uint8_t* status,
                      int32_t* steps, int32_t* hit_vox, uint8_t* marginal) {
   if (!prm->analytic && (lod < 1 || lod > M->num_lods || M->m > 64)) return -1;
   if (!prm->analytic && alpha > 0.0 && lod >= M->num_lods) return -1;
+  int pair_depth = (alpha > 0.0 ? lod + 1 : lod) + 1;
 #pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < R; ++i)
+    trace_ray(t, M, o, d, R, i, lod, alpha, pair_depth, pair_vox, t_in, t_out, ray_off, prm, t_hit, status, steps,
+              hit_vox, marginal);
+  return 0;
+}
+
+/*
+ * Per-pixel LOD selection by distance (Sec. 3.4, LOD Selection): the LOD
+ * moves linearly from lod_near at distance d_near to lod_far at d_far and
+ * is constant outside.  Evaluated in FP32 in this order (every operation
+ * rounded, no fused multiply-add):
+ *   u = (dist - d_near) / (d_far - d_near), clamped to [0, 1];
+ *   L~ = lod_near + (lod_far - lod_near) * u;
+ *   L* = floor(L~) and alpha = L~ - L*, except L* = num_lods, alpha = 0
+ *   when L~ >= num_lods.
+ */
+void orc_lod_select(float d_near, float d_far, float lod_near, float lod_far, int num_lods, float dist,
+                    float* lod_cont, int32_t* lod_int, float* alpha) {
+  float u = (dist - d_near) / (d_far - d_near);
+  if (u < 0.0f) u = 0.0f;
+  if (u > 1.0f) u = 1.0f;
+  float span = lod_far - lod_near;
+  float prod = span * u;
+  float L = lod_near + prod;
+  int Li = (int)floorf(L);
+  float a = L - (float)Li;
+  if (Li >= num_lods) { Li = num_lods; a = 0.0f; }
+  *lod_cont = L;
+  *lod_int = Li;
+  *alpha = a;
+}
+
+/*
+ * Sphere trace with a LOD and blend weight per ray (lod_pp, alpha_pp) over
+ * hit lists at any depth pair_depth >= (lod + (alpha > 0)) + 1 for every
+ * ray: the SDF of a ray is evaluated at its own LOD from the ancestors of
+ * the pair's voxel.
+ */
+int orc_sphere_trace_pp(const orc_octree* t, const orc_model* M, const float* o, const float* d, int64_t R,
+                        int pair_depth, const int32_t* lod_pp, const float* alpha_pp, const int32_t* pair_vox,
+                        const float* t_in, const float* t_out, const int64_t* ray_off,
+                        const orc_trace_params* prm, double* t_hit, uint8_t* status, int32_t* steps,
+                        int32_t* hit_vox, uint8_t* marginal) {
+  if (M->m > 64 || pair_depth < 2 || pair_depth > M->num_lods + 1) return -1;
   for (int64_t i = 0; i < R; ++i) {
-    double oo[3] = {o[i], o[R + i], o[2 * R + i]};
-    double dd[3] = {d[i], d[R + i], d[2 * R + i]};
-    int64_t b = ray_off[i], e = ray_off[i + 1];
-    int64_t p = b;
-    double t_cur = b < e ? (double)t_in[b] : 0.0;
-    int k = 0;
-    double prev = INFINITY;
-    uint8_t st = ORC_MISS, marg = 0;
-    int32_t hv = -1;
-    int bad = 0;
-    for (int a = 0; a < 3; ++a) if (!isfinite(oo[a]) || !isfinite(dd[a])) bad = 1;
-    if (bad) { st = ORC_INVALID; e = b; }
-    for (;;) {
-      if (bad) break;
-      while (p < e && t_cur > (double)t_out[p]) {
-        if (fabs(t_cur - (double)t_out[p]) <= prm->margin_t * (1.0 + fabs(t_cur))) marg = 1;
-        ++p;
-      }
-      if (p < e && fabs(t_cur - (double)t_out[p]) <= prm->margin_t * (1.0 + fabs(t_cur))) marg = 1;
-      if (p == e) { st = ORC_MISS; break; }
-      if (t_cur < (double)t_in[p]) t_cur = (double)t_in[p];
-      if (t_cur > prm->t_far) { st = ORC_FAR; break; }
-      if (k == prm->max_steps) { st = ORC_MAX_STEPS; break; }
-      double x[3] = {oo[0] + t_cur * dd[0], oo[1] + t_cur * dd[1], oo[2] + t_cur * dd[2]};
-      double scale = 1.0, dist;
-      if (prm->analytic) {
-        double q0 = x[0] - prm->sphere[0], q1 = x[1] - prm->sphere[1], q2 = x[2] - prm->sphere[2];
-        dist = sqrt(q0 * q0 + q1 * q1 + q2 * q2) - prm->sphere[3];
-      } else {
-        dist = query_in_voxel(t, M, lod, alpha, pair_vox[p], x, &scale);
-      }
-      ++k;
-      if (fabs(dist - prm->delta) <= prm->margin_sdf * scale) marg = 1;
-      if (dist < prm->delta) { st = ORC_HIT; hv = pair_vox[p]; break; }
-      if (prm->osc_check && fabs(dist - prev) < 6.0 * prm->delta) { st = ORC_STALLED; break; }
-      prev = dist;
-      t_cur += dist;
-    }
-    t_hit[i] = t_cur;
-    status[i] = st;
-    steps[i] = k;
-    hit_vox[i] = hv;
-    if (marginal) marginal[i] = marg;
+    int need = lod_pp[i] + (alpha_pp[i] > 0.0f ? 1 : 0);
+    if (lod_pp[i] < 1 || lod_pp[i] > M->num_lods || need > M->num_lods || need + 1 > pair_depth) return -1;
   }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t i = 0; i < R; ++i)
+    trace_ray(t, M, o, d, R, i, lod_pp[i], (double)alpha_pp[i], pair_depth, pair_vox, t_in, t_out, ray_off, prm,
+              t_hit, status, steps, hit_vox, marginal);
   return 0;
 }
 
