@@ -369,6 +369,7 @@ def main():
         comp["batch"] = run_batch(dev, args.steps, args.warmup)
     if args.only is None:
         comp["decoder_bf16"] = run_decoder(S, dev, args.steps, args.warmup)
+        comp["frame_lod_select"] = run_lod_select(model, cfg, o, d, buf, args.steps, args.warmup)
         if do_h:
             hq = comp["bf16_form"]["queries_per_s"] * DEC_MFMA_FLOPS / 1e12
             comp["bf16_form"]["fused_decoder_mfma_frac"] = hq / BF16_PEAK_TFLOPS
@@ -419,6 +420,37 @@ def run_decoder(S, dev, steps, warmup):
     return {"points": P, "ms": ms, "points_per_s": P / (ms * 1e-3), "z_bytes": P * cfg.feat_dim * 2,
             "mfma_tflops": tf, "mfma_frac_bf16": tf / BF16_PEAK_TFLOPS,
             "note": "2*32*128 flops per point (first layer on z); inputs 80 B per point"}
+
+
+def run_lod_select(model, cfg, o, d, buf, steps, warmup):
+    """The step's 1024^2 frame with per-pixel LOD selection: LOD 5 up to
+    distance 1.6 from the eye, LOD 2 from 3.2 on, linear in between (the
+    traversal runs to the LOD-5 depth; rays are grouped by LOD on the
+    device and each group is traced with its two decoders)."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    sel = ngl.lod_select(1.6, 3.2, 5.0, 2.0)
+    hits = dict(vox=buf.vox, t_in=buf.t_in, t_out=buf.t_out, ray_off=buf.ray_off)
+    tt, ts = Timer(), Timer()
+    out = None
+    for k in range(warmup + steps):
+        if k < warmup:
+            ngl.trace_octree_into(model, o, d, cfg.num_lods + 1, buf)
+            out = ngl.sphere_trace_lod(model, o, d, cfg.num_lods + 1, sel, hits, cfg.max_steps, cfg.delta, out=out)
+            continue
+        with tt:
+            ngl.trace_octree_into(model, o, d, cfg.num_lods + 1, buf)
+        with ts:
+            out = ngl.sphere_trace_lod(model, o, d, cfg.num_lods + 1, sel, hits, cfg.max_steps, cfg.delta, out=out)
+    torch.cuda.synchronize()
+    lod = out["lod"].cpu().numpy()
+    st = out["status"].cpu().numpy()
+    hit = st == ngl.HIT
+    trav, trace = float(np.mean(tt.values())), float(np.mean(ts.values()))
+    return {"selection": {"d_near": 1.6, "d_far": 3.2, "lod_near": 5.0, "lod_far": 2.0},
+            "traverse_ms": trav, "trace_ms": trace, "ms": trav + trace, "visible_px": int(hit.sum()),
+            "sdf_evals": int(out["steps"].sum()), "mean_lod_of_hits": float(lod[hit].mean()) if hit.any() else None,
+            "rays_per_lod": {str(L): int(((np.floor(lod) == L) | ((L == 5) & (lod >= 5))).sum()) for L in (2, 3, 4, 5)}}
 
 
 def run_batch(dev, steps, warmup):

@@ -282,6 +282,37 @@ int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t
  * concurrently. */
 int ngl_sphere_trace_workspace(size_t* bytes);
 
+/* Per-pixel LOD selection (Sec. 3.4, LOD Selection): the continuous LOD of
+ * a ray moves linearly from lod_near at distance d_near to lod_far at
+ * d_far (constant outside), where the distance is the entry t of the ray's
+ * first hit pair (params->t_far for a ray without pairs).  Evaluated in
+ * FP32, each operation rounded in this order:
+ *   u = clamp((dist - d_near) / (d_far - d_near), 0, 1)
+ *   L = lod_near + (lod_far - lod_near) * u, clamped to [min, max] of the
+ *       two LODs
+ *   L* = floor(L), alpha = L - L*; L* = num_lods, alpha = 0 if L >= num_lods. */
+typedef struct {
+  float d_near, d_far;     /* d_far > d_near */
+  float lod_near, lod_far; /* continuous LODs in [1, num_lods] */
+} ngl_lod_select;
+
+/* Sphere trace in which each ray uses its own LOD L* + alpha (Eq. 3) from
+ * the heuristic above.  The hit lists (ngl_trace_octree output) are at
+ * pair_depth, which must reach every selected level:
+ * pair_depth - 1 >= ceil(max(lod_near, lod_far)), pair_depth <= num_lods+1;
+ * each SDF evaluation of a ray uses the ancestors of its current pair's
+ * voxel.  Rays are grouped by L* on the device and each group is traced by
+ * one persistent launch with the decoders L* and L*+1.  Outputs as in
+ * ngl_sphere_trace (hit_vox is a voxel at pair_depth), plus lod_out
+ * (nullable, device [R]): each ray's continuous LOD L.  ws: device bytes
+ * from ngl_sphere_trace_lod_workspace(R); calls sharing it must not
+ * overlap. */
+int ngl_sphere_trace_lod_workspace(int64_t R, size_t* bytes);
+int ngl_sphere_trace_lod(const ngl_model* m, const float* o, const float* d, int64_t R, int32_t pair_depth,
+                         const ngl_lod_select* sel, const int32_t* pair_vox, const float* t_in, const float* t_out,
+                         const int32_t* ray_off, const ngl_trace_params* params, float* t_hit, uint8_t* status,
+                         int32_t* steps, int32_t* hit_vox, float* lod_out, void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------ */
 /* 3b. Batched rendering of several models (each its own octree, camera   */
 /*     and LOD) with one persistent sphere-tracing launch.                */

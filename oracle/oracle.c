@@ -712,7 +712,8 @@ int orc_sphere_trace(const orc_octree* t, const orc_model* M, const float* o, co
  * is constant outside.  Evaluated in FP32 in this order (every operation
  * rounded, no fused multiply-add):
  *   u = (dist - d_near) / (d_far - d_near), clamped to [0, 1];
- *   L~ = lod_near + (lod_far - lod_near) * u;
+ *   L~ = lod_near + (lod_far - lod_near) * u, clamped to [min, max] of the
+ *        two LODs (rounding may leave that range by an ulp);
  *   L* = floor(L~) and alpha = L~ - L*, except L* = num_lods, alpha = 0
  *   when L~ >= num_lods.
  */
@@ -724,6 +725,9 @@ void orc_lod_select(float d_near, float d_far, float lod_near, float lod_far, in
   float span = lod_far - lod_near;
   float prod = span * u;
   float L = lod_near + prod;
+  float lo = lod_near < lod_far ? lod_near : lod_far, hi = lod_near < lod_far ? lod_far : lod_near;
+  if (L < lo) L = lo; /* rounding may leave the range by an ulp */
+  if (L > hi) L = hi;
   int Li = (int)floorf(L);
   float a = L - (float)Li;
   if (Li >= num_lods) { Li = num_lods; a = 0.0f; }

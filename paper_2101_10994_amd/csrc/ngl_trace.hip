@@ -5,6 +5,91 @@
 // takes a sphere-tracing step.
 #include "ngl_trace_impl.h"
 
+#include <algorithm>
+#include <cmath>
+
+namespace ngl {
+
+static int trace_by_width(const ngl_model& m, const TraceArgs& A, hipStream_t s) {
+  NGL_BY_WIDTH(m.feat_dim, trace_run, m, A, s)
+}
+
+// Workspace of the per-ray LOD trace: [3][NGL_MAX_LODS] counters (group
+// sizes, scatter cursors, queue heads), ray ids grouped by L*, blend weight
+// and L* per ray.
+struct LodWS {
+  unsigned* counts;
+  int32_t* ids;
+  float* alpha;
+  uint8_t* lint;
+  static size_t align(size_t b) { return (b + 255) & ~size_t(255); }
+  static size_t bytes(int64_t R) { return 256 + align(4 * size_t(R)) + align(4 * size_t(R)) + align(size_t(R)); }
+  LodWS(void* ws, int64_t R) {
+    char* p = static_cast<char*>(ws);
+    counts = reinterpret_cast<unsigned*>(p);
+    p += 256;
+    ids = reinterpret_cast<int32_t*>(p);
+    p += align(4 * size_t(R));
+    alpha = reinterpret_cast<float*>(p);
+    p += align(4 * size_t(R));
+    lint = reinterpret_cast<uint8_t*>(p);
+  }
+};
+
+__global__ void k_lod_init(unsigned* c) {
+  if (threadIdx.x < 3 * NGL_MAX_LODS) c[threadIdx.x] = 0u;
+}
+
+// L* and alpha per ray; group sizes counted per block in LDS, then one
+// global add per group and block.
+__global__ __launch_bounds__(256) void k_lod_select(ngl_lod_select sel, int num_lods, int64_t R,
+                                                    const int32_t* __restrict__ ray_off,
+                                                    const float* __restrict__ t_in, float t_far, float* lod_out,
+                                                    float* alpha, uint8_t* lint, unsigned* counts) {
+  __shared__ unsigned cnt[NGL_MAX_LODS];
+  if (threadIdx.x < NGL_MAX_LODS) cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r < R) {
+    const int b = ray_off[r], e = ray_off[r + 1];
+    const float dist = b < e ? t_in[b] : t_far;
+    float Lc, a;
+    int li;
+    lod_of_distance(sel, num_lods, dist, &Lc, &li, &a);
+    if (lod_out) lod_out[r] = Lc;
+    alpha[r] = a;
+    lint[r] = uint8_t(li);
+    atomicAdd(&cnt[li - 1], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < NGL_MAX_LODS && cnt[threadIdx.x]) atomicAdd(&counts[threadIdx.x], cnt[threadIdx.x]);
+}
+
+// Ray ids grouped by L*: ranks within the block from LDS counters, one
+// global range reservation per group and block.
+__global__ __launch_bounds__(256) void k_lod_scatter(int64_t R, const uint8_t* __restrict__ lint,
+                                                     const unsigned* __restrict__ counts, unsigned* cursor,
+                                                     int32_t* ids) {
+  __shared__ unsigned cnt[NGL_MAX_LODS], base[NGL_MAX_LODS];
+  if (threadIdx.x < NGL_MAX_LODS) cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const bool in = r < R;
+  const int li = in ? int(lint[r]) : 1;
+  unsigned rank = 0;
+  if (in) rank = atomicAdd(&cnt[li - 1], 1u);
+  __syncthreads();
+  if (threadIdx.x < NGL_MAX_LODS && cnt[threadIdx.x]) {
+    unsigned off = 0;
+    for (unsigned b = 0; b < threadIdx.x; ++b) off += counts[b];
+    base[threadIdx.x] = off + atomicAdd(&cursor[threadIdx.x], cnt[threadIdx.x]);
+  }
+  __syncthreads();
+  if (in) ids[base[li - 1] + rank] = int32_t(r);
+}
+
+}  // namespace ngl
+
 extern "C" {
 
 int ngl_sphere_trace_workspace(size_t* bytes) {
@@ -37,6 +122,61 @@ int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t
               hit_vox, static_cast<unsigned int*>(ws), nullptr, nullptr};
   if (analytic) return trace_run_analytic(*m, A, s);
   NGL_BY_WIDTH(m->feat_dim, trace_run, *m, A, s)
+}
+
+int ngl_sphere_trace_lod_workspace(int64_t R, size_t* bytes) {
+  NGL_REQUIRE(bytes != nullptr && R >= 0, "bad arguments");
+  *bytes = ngl::LodWS::bytes(R);
+  return NGL_OK;
+}
+
+int ngl_sphere_trace_lod(const ngl_model* m, const float* o, const float* d, int64_t R, int32_t pair_depth,
+                         const ngl_lod_select* sel, const int32_t* pair_vox, const float* t_in, const float* t_out,
+                         const int32_t* ray_off, const ngl_trace_params* params, float* t_hit, uint8_t* status,
+                         int32_t* steps, int32_t* hit_vox, float* lod_out, void* ws, size_t ws_bytes, void* stream) {
+  using namespace ngl;
+  NGL_REQUIRE(params != nullptr && sel != nullptr, "params or sel is null");
+  NGL_REQUIRE(params->analytic == 0, "analytic mode has no LOD");
+  int rc = check_model(m, true);
+  if (rc) return rc;
+  NGL_REQUIRE(R >= 0 && R < (int64_t(1) << 31), "ray count out of range");
+  NGL_REQUIRE(params->max_steps >= 0, "max_steps must be >= 0");
+  const int L = m->num_lods;
+  NGL_REQUIRE(std::isfinite(sel->d_near) && std::isfinite(sel->d_far) && sel->d_far > sel->d_near,
+              "need finite d_near < d_far");
+  NGL_REQUIRE(sel->lod_near >= 1.0f && sel->lod_near <= float(L) && sel->lod_far >= 1.0f && sel->lod_far <= float(L),
+              "lod_near and lod_far must be in [1, %d]", L);
+  const float lmax = std::max(sel->lod_near, sel->lod_far), lmin = std::min(sel->lod_near, sel->lod_far);
+  NGL_REQUIRE(pair_depth >= 2 && pair_depth <= L + 1 && float(pair_depth - 1) >= std::ceil(lmax),
+              "pair_depth %d does not reach LOD %g (need depth >= %d, <= %d)", pair_depth, double(lmax),
+              int(std::ceil(lmax)) + 1, L + 1);
+  if (R == 0) return NGL_OK;
+  NGL_REQUIRE(o && d && ray_off && t_hit && status && steps && hit_vox, "null buffer");
+  NGL_REQUIRE(ws != nullptr && ws_bytes >= LodWS::bytes(R), "workspace too small: %zu < %zu bytes", ws_bytes,
+              LodWS::bytes(R));
+  hipStream_t s = (hipStream_t)stream;
+  LodWS W(ws, R);
+  k_lod_init<<<1, 64, 0, s>>>(W.counts);
+  NGL_LAUNCHED();
+  const unsigned g = unsigned((R + 255) / 256);
+  k_lod_select<<<g, 256, 0, s>>>(*sel, L, R, ray_off, t_in, params->t_far, lod_out, W.alpha, W.lint, W.counts);
+  NGL_LAUNCHED();
+  k_lod_scatter<<<g, 256, 0, s>>>(R, W.lint, W.counts, W.counts + NGL_MAX_LODS, W.ids);
+  NGL_LAUNCHED();
+  const int first = std::max(1, int(std::floor(lmin)));
+  const int last = std::min(L, int(std::floor(lmax)));
+  for (int lod = first; lod <= last; ++lod) {
+    TraceArgs A{o, d, R, 0, R, lod, 0.0f, pair_vox, t_in, t_out, ray_off, *params, t_hit, status, steps, hit_vox,
+                W.counts + 2 * NGL_MAX_LODS + (lod - 1), nullptr, nullptr};
+    A.pair_depth = pair_depth;
+    A.ray_ids = W.ids;
+    A.bucket_counts = W.counts;
+    A.bucket = lod - 1;
+    A.alpha_pp = lod < L ? W.alpha : nullptr;
+    rc = trace_by_width(*m, A, s);
+    if (rc) return rc;
+  }
+  return NGL_OK;
 }
 
 int ngl_model_table_bytes(int32_t n, size_t* bytes) {

@@ -29,7 +29,45 @@ struct TraceArgs {
   unsigned int* counter;  // this view's work queue head (zeroed before the launch)
   unsigned int* live;     // nullable: rays of this view not yet finished
   uint64_t* done_clock;   // nullable: timestamp when the view's last ray ends
+  // Per-ray LOD selection (all zero/null otherwise):
+  int pair_depth;                     // depth of the hit lists (0: that of lod, +1 when blending)
+  const int32_t* ray_ids;             // nullable: the queue serves these ray ids
+  const unsigned int* bucket_counts;  // nullable: ray_ids is split into buckets of these sizes ...
+  int bucket;                         // ... and this launch serves bucket `bucket`
+  const float* alpha_pp;              // nullable: blend weight per ray (replaces alpha)
 };
+
+// The launch evaluates decoders lod and lod+1.
+__host__ __device__ inline bool trace_blend(const TraceArgs& A) { return A.alpha > 0.0f || A.alpha_pp != nullptr; }
+
+// Continuous LOD from a distance (Sec. 3.4, LOD Selection), in FP32 with
+// every operation rounded in this order (the oracle's orc_lod_select):
+// u = clamp((dist - d_near) / (d_far - d_near), 0, 1),
+// L = lod_near + (lod_far - lod_near) * u clamped to the LODs' range,
+// L* = floor(L), alpha = L - L*
+// (L* = num_lods and alpha = 0 when L >= num_lods).
+__device__ inline void lod_of_distance(const ngl_lod_select& s, int num_lods, float dist, float* Lc, int* Li,
+                                       float* alpha) {
+#pragma clang fp contract(off)
+  float u = (dist - s.d_near) / (s.d_far - s.d_near);
+  if (u < 0.0f) u = 0.0f;
+  if (u > 1.0f) u = 1.0f;
+  const float span = s.lod_far - s.lod_near;
+  const float prod = span * u;
+  float L = s.lod_near + prod;
+  const float lo = fminf(s.lod_near, s.lod_far), hi = fmaxf(s.lod_near, s.lod_far);
+  if (L < lo) L = lo;
+  if (L > hi) L = hi;
+  int li = int(floorf(L));
+  float a = L - float(li);
+  if (li >= num_lods) {
+    li = num_lods;
+    a = 0.0f;
+  }
+  *Lc = L;
+  *Li = li;
+  *alpha = a;
+}
 
 // One wavefront serves a view's ray queue.  Each lane keeps one ray; a lane
 // whose ray terminates takes the next ray from the queue, so every step is
@@ -40,11 +78,21 @@ struct TraceArgs {
 template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, class DEC>
 __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLds<DEC>& S, float b2a, float b2b) {
   const int lane = threadIdx.x & 63;
-  const int64_t R = A.R;
-  const bool blend = A.alpha > 0.0f;
+  const bool blend = trace_blend(A);
   const int lod = A.lod;
   const int Lp = blend ? lod + 1 : lod;
-  const int64_t nv_t = ANALYTIC ? 0 : md.nvox[Lp + 1];
+  const int PD = A.pair_depth > 0 ? A.pair_depth : Lp + 1;  // depth of the pairs
+  const int Lpair = PD - 1;                                 // their feature level
+  const int64_t nv_t = ANALYTIC ? 0 : md.nvox[PD];
+  int64_t R = A.R;  // queue length
+  const int32_t* ids = A.ray_ids;
+  if (A.bucket_counts) {
+    unsigned off = 0;
+    for (int b = 0; b < A.bucket; ++b) off += A.bucket_counts[b];
+    R = A.bucket_counts[A.bucket];
+    ids += off;
+  }
+  float al = A.alpha;  // this lane's blend weight
   const int H = md.hidden;
   int ray = -1, p = 0, e = 0, k = 0, cp = -1;
   bool ready = false;
@@ -84,7 +132,8 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
         if (ray < 0) {
           const int64_t my = int64_t(base) + __popcll(need & ((1ull << lane) - 1ull));
           if (my < R) {
-            ray = int(my);
+            ray = ids ? ids[my] : int(my);
+            if (A.alpha_pp) al = A.alpha_pp[ray];
             p = A.ray_off[ray];
             e = A.ray_off[ray + 1];
             k = 0;
@@ -147,9 +196,11 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
               int w = v;
 #pragma unroll
               for (int l = NGL_MAX_LODS; l >= 1; --l) {
-                if (l <= Lp) {
-                  vox[l - 1] = w;
-                  cell[l - 1] = md.cell[l + 1][w];
+                if (l <= Lpair) {
+                  if (l <= Lp) {
+                    vox[l - 1] = w;
+                    cell[l - 1] = md.cell[l + 1][w];
+                  }
                   w = md.parent[l + 1][w];
                 }
               }
@@ -169,24 +220,21 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
           DEC::stage(S.stage, x, z);
           wave_lds_sync();
           dist = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H);
-          if (blend) {
-            // with alpha > 0 the pair voxel is the level lod+1 voxel
-            if (ok) {
-              const uint32_t c = md.cell[Lp + 1][v];
-              interp_level<M, FT>(md, lod + 1, v, cell_x(c), cell_y(c), cell_z(c), x, z);
-            }
+          const bool mix = ok && al > 0.0f;  // Eq. 3 blend with the level lod+1 voxel
+          if (blend && __ballot(mix)) {
+            if (mix) interp_level<M, FT>(md, lod + 1, vox[lod], cell_x(cell[lod]), cell_y(cell[lod]), cell_z(cell[lod]), x, z);
             wave_lds_sync();
             DEC::stage(S.stage, x, z);
             wave_lds_sync();
-            dist = (1.0f - A.alpha) * dist + A.alpha * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H);
+            const float d1 = DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H);
+            if (mix) dist = (1.0f - al) * dist + al * d1;
           }
           wave_lds_sync();
         } else if (ok) {
           dist = decode_f32<M, XYZ>(md, lod, x, z);
-          if (blend) {
-            const uint32_t c = md.cell[Lp + 1][v];
-            interp_level<M, FT>(md, lod + 1, v, cell_x(c), cell_y(c), cell_z(c), x, z);
-            dist = (1.0f - A.alpha) * dist + A.alpha * decode_f32<M, XYZ>(md, lod + 1, x, z);
+          if (blend && al > 0.0f) {
+            interp_level<M, FT>(md, lod + 1, vox[lod], cell_x(cell[lod]), cell_y(cell[lod]), cell_z(cell[lod]), x, z);
+            dist = (1.0f - al) * dist + al * decode_f32<M, XYZ>(md, lod + 1, x, z);
           }
         }
       }
@@ -225,7 +273,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
 template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW, class DEC>
 __global__ __launch_bounds__(64 * NW) void k_sphere_trace(ngl_model md, TraceArgs A) {
   extern __shared__ __align__(16) char smem[];
-  const bool blend = A.alpha > 0.0f;
+  const bool blend = trace_blend(A);
   const int H = md.hidden;
   DecLds<DEC> S(smem, H, blend && MFMA);
   float b2a = 0.0f, b2b = 0.0f;
@@ -361,7 +409,7 @@ static int launch_trace_nw(const ngl_model& md, const TraceArgs& A, hipStream_t 
 
 template <int M, typename FT, bool XYZ, class DEC>
 static int launch_trace_mfma(const ngl_model& md, const TraceArgs& A, hipStream_t s) {
-  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, A.alpha > 0.0f);
+  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, trace_blend(A));
   const int want = option(NGL_OPT_TRACE_WAVES);
   if ((want == 0 || want >= 4) && fixed + 4 * DEC::STAGE_BYTES <= 65536)
     return launch_trace_nw<M, FT, XYZ, false, true, 4, DEC>(md, A, s, fixed + 4 * DEC::STAGE_BYTES);

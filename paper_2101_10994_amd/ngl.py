@@ -64,6 +64,10 @@ class ngl_trace_params(C.Structure):
                 ("analytic", i32), ("sphere", C.c_float * 4)]
 
 
+class ngl_lod_select(C.Structure):
+    _fields_ = [("d_near", C.c_float), ("d_far", C.c_float), ("lod_near", C.c_float), ("lod_far", C.c_float)]
+
+
 EXPORTS = {
     "ngl_status_str": (C.c_char_p, [C.c_int]),
     "ngl_last_error": (C.c_char_p, []),
@@ -81,6 +85,8 @@ EXPORTS = {
     "ngl_trace_octree": (C.c_int, [P, P, P, i64, i32, i64, P, C.c_size_t, P, P, P, P, P, P, P]),
     "ngl_sphere_trace": (C.c_int, [P, P, P, i64, i32, C.c_float, P, P, P, P, P, P, P, P, P, P, C.c_size_t, P]),
     "ngl_sphere_trace_workspace": (C.c_int, [P]),
+    "ngl_sphere_trace_lod_workspace": (C.c_int, [i64, P]),
+    "ngl_sphere_trace_lod": (C.c_int, [P, P, P, i64, i32, P, P, P, P, P, P, P, P, P, P, P, P, C.c_size_t, P]),
     "ngl_model_table_bytes": (C.c_int, [i32, P]),
     "ngl_model_table_upload": (C.c_int, [P, i32, P, P]),
     "ngl_render_batch_workspace": (C.c_int, [P, i32, i64, P]),
@@ -462,6 +468,38 @@ def sphere_trace(model: Model, o, d, lod: int, alpha: float, hits: dict, max_ste
                                   _ptr(hits["t_in"]), _ptr(hits["t_out"]), _ptr(hits["ray_off"]), C.addressof(prm),
                                   _ptr(out["t"]), _ptr(out["status"]), _ptr(out["steps"]), _ptr(out["hit_vox"]),
                                   _ptr(out["ws"]), out["ws"].numel(), _stream()))
+    return out
+
+
+def lod_select(d_near: float, d_far: float, lod_near: float, lod_far: float) -> ngl_lod_select:
+    s = ngl_lod_select()
+    s.d_near, s.d_far, s.lod_near, s.lod_far = float(d_near), float(d_far), float(lod_near), float(lod_far)
+    return s
+
+
+def sphere_trace_lod(model: Model, o, d, pair_depth: int, sel: ngl_lod_select, hits: dict, max_steps: int,
+                     delta: float, t_far: float = 5.0, osc_check: bool = False, out=None):
+    """Sphere trace with per-pixel LOD selection (ngl_sphere_trace_lod);
+    hits at pair_depth.  Returns t, status, steps, hit_vox and each ray's
+    continuous LOD."""
+    R = o.shape[1]
+    dev = o.device
+    if out is None:
+        out = dict(t=torch.empty(R, dtype=torch.float32, device=dev),
+                   status=torch.empty(R, dtype=torch.uint8, device=dev),
+                   steps=torch.empty(R, dtype=torch.int32, device=dev),
+                   hit_vox=torch.empty(R, dtype=torch.int32, device=dev),
+                   lod=torch.empty(R, dtype=torch.float32, device=dev))
+    prm = trace_params(max_steps, delta, t_far, osc_check)
+    if "ws" not in out:
+        nb = C.c_size_t()
+        _check(lib().ngl_sphere_trace_lod_workspace(R, C.addressof(nb)))
+        out["ws"] = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
+    _check(lib().ngl_sphere_trace_lod(model.ref, _ptr(o), _ptr(d), R, int(pair_depth), C.addressof(sel),
+                                      _ptr(hits["vox"]), _ptr(hits["t_in"]), _ptr(hits["t_out"]),
+                                      _ptr(hits["ray_off"]), C.addressof(prm), _ptr(out["t"]), _ptr(out["status"]),
+                                      _ptr(out["steps"]), _ptr(out["hit_vox"]), _ptr(out.get("lod")),
+                                      _ptr(out["ws"]), out["ws"].numel(), _stream()))
     return out
 
 

@@ -115,3 +115,19 @@ def test_coarse_plane_through_deep_lists_hits_closed_form():
     th = res["t"][inside]
     assert np.all(th <= tstar[inside] + 1e-12)
     assert np.all(th >= tstar[inside] - delta / np.abs(nd[inside]) - 1e-9)
+
+
+def test_heuristic_stays_within_the_two_lods():
+    """Rounding of the FP32 blend may not leave [min, max] of the LODs (an
+    integer end value must stay integral, with alpha 0)."""
+    rng = np.random.default_rng(9)
+    for _ in range(200):
+        ln, lf = rng.uniform(1, 5, 2).astype(np.float32)
+        if rng.uniform() < 0.5:
+            lf = np.float32(np.round(lf))
+        dn = np.float32(rng.uniform(0.5, 2.0))
+        df = np.float32(dn + rng.uniform(0.1, 2.0))
+        d = rng.uniform(0, 5, 64).astype(np.float32)
+        Lc, Li, al = oracle.lod_select(dn, df, ln, lf, 5, d)
+        assert np.all(Lc >= min(ln, lf)) and np.all(Lc <= max(ln, lf))
+        assert np.all(Li >= np.floor(min(ln, lf))) and np.all(Li <= np.floor(max(ln, lf)))
