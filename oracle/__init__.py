@@ -103,6 +103,12 @@ def _setup(lib):
     lib.orc_sphere_trace_pp.restype = C.c_int
     lib.orc_sphere_trace_pp.argtypes = [P, P, P, P, i64, C.c_int, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.orc_lod_select.argtypes = [C.c_float, C.c_float, C.c_float, C.c_float, C.c_int, C.c_float, P, P, P]
+    lib.orc_train_fwd_bwd_w.restype = C.c_int
+    lib.orc_train_fwd_bwd_w.argtypes = [P, P, P, P, i64, P, P, P, P, P, P, P, P]
+    lib.orc_shape_sdf_many.argtypes = [C.c_int, P, C.c_int, P, P, i64, P]
+    lib.orc_sample_surface.argtypes = [C.c_int, P, C.c_int, P, P, i64, C.c_int, C.c_double, C.c_double, P, P, P]
+    lib.orc_training_points.restype = C.c_int
+    lib.orc_training_points.argtypes = [C.c_int, P, C.c_int, P, P, i64, P, i64, C.c_double, P, P]
     lib.orc_train_fwd_bwd.restype = C.c_int
     lib.orc_train_fwd_bwd.argtypes = [P, P, P, P, i64, P, P, P, P, P, P, P]
 
@@ -443,8 +449,9 @@ def sphere_trace_pp(tree: Octree, model: Model, o_soa, d_soa, pair_depth: int, l
     return dict(t=t_hit, status=status, steps=steps, hit_vox=hv, marginal=marg)
 
 
-def train_fwd_bwd(tree: Octree, model: Model, x_soa, target, want_sdf=False, grads=True):
-    """Eq. 4 loss and gradients (float64), laid out like the parameters."""
+def train_fwd_bwd(tree: Octree, model: Model, x_soa, target, want_sdf=False, grads=True, lod_weight=None):
+    """Eq. 4 loss and gradients (float64), laid out like the parameters;
+    lod_weight (optional, [L]) weights each LOD's term."""
     x = _c(x_soa, np.float32)
     tg = _c(target, np.float32)
     Pn = x.shape[1]
@@ -465,8 +472,9 @@ def train_fwd_bwd(tree: Octree, model: Model, x_soa, target, want_sdf=False, gra
         db2 = None
     sdf_all = np.zeros((L, Pn)) if want_sdf else None
     ms = model.struct()
-    rc = _load().orc_train_fwd_bwd(tree._h, C.addressof(ms), _ptr(x), _ptr(tg), Pn, _ptr(loss),
-                                   pF, pW1, pb1, pw2, _ptr(db2), _ptr(sdf_all))
+    lw = None if lod_weight is None else _c(lod_weight, np.float64)
+    rc = _load().orc_train_fwd_bwd_w(tree._h, C.addressof(ms), _ptr(x), _ptr(tg), Pn, _ptr(lw), _ptr(loss),
+                                     pF, pW1, pb1, pw2, _ptr(db2), _ptr(sdf_all))
     if rc != 0:
         raise ValueError("oracle train_fwd_bwd: invalid arguments")
     out["loss"] = float(loss[0])
@@ -477,3 +485,66 @@ def train_fwd_bwd(tree: Octree, model: Model, x_soa, target, want_sdf=False, gra
 
 def loss(tree: Octree, model: Model, x_soa, target) -> float:
     return train_fwd_bwd(tree, model, x_soa, target, grads=False)["loss"]
+
+
+# ---------------------------------------------------------------------------
+# Fitting (training appendix): analytic shapes, samplers, Adam
+# ---------------------------------------------------------------------------
+def _shape_arrays(spheres, tori):
+    sph = _c(np.asarray(spheres, np.float64).reshape(-1, 4), np.float64)
+    tor = _c(np.asarray(tori, np.float64).reshape(-1, 6), np.float64)
+    return sph, tor
+
+
+def shape_sdf(spheres, tori, x_soa):
+    """Exact union SDF (float64) at float32 points [3][P]."""
+    sph, tor = _shape_arrays(spheres, tori)
+    x = _c(x_soa, np.float32)
+    out = np.zeros(x.shape[1])
+    _load().orc_shape_sdf_many(len(sph), _ptr(sph), len(tor), _ptr(tor), _ptr(x), x.shape[1], _ptr(out))
+    return out
+
+
+def sample_surface(spheres, tori, u, max_steps: int, delta: float, margin: float = 0.0):
+    """SDF surface sampler (see orc_sample_surface); u: [5][n] float32."""
+    sph, tor = _shape_arrays(spheres, tori)
+    uu = _c(u, np.float32)
+    n = uu.shape[1]
+    pts = np.zeros((3, n))
+    hit = np.zeros(n, np.uint8)
+    marg = np.zeros(n, np.uint8)
+    _load().orc_sample_surface(len(sph), _ptr(sph), len(tor), _ptr(tor), _ptr(uu), n, int(max_steps), float(delta),
+                               float(margin), _ptr(pts), _ptr(hit), _ptr(marg))
+    return dict(points=pts, hit=hit.astype(bool), marginal=marg.astype(bool))
+
+
+def training_points(spheres, tori, surface_pts, uni, sigma: float = 0.01):
+    """2:2:1 surface/near/uniform training set (see orc_training_points).
+    surface_pts: [3][ns] float64, uni: [4][N] float32.  Returns float32
+    points [3][N] and float64 targets [N]."""
+    sph, tor = _shape_arrays(spheres, tori)
+    S = _c(surface_pts, np.float64)
+    un = _c(uni, np.float32)
+    N = un.shape[1]
+    xs = np.zeros((3, N), np.float32)
+    tg = np.zeros(N)
+    rc = _load().orc_training_points(len(sph), _ptr(sph), len(tor), _ptr(tor), _ptr(S), S.shape[1], _ptr(un), N,
+                                     float(sigma), _ptr(xs), _ptr(tg))
+    if rc != 0:
+        raise ValueError("oracle training_points: no surface samples")
+    return xs, tg
+
+
+def adam_step(params, grads, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba 2015, Algorithm 1) in float64, in
+    place on lists of arrays: m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
+    theta <- theta - lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)."""
+    c1 = 1.0 / (1.0 - beta1 ** step)
+    c2 = 1.0 / (1.0 - beta2 ** step)
+    for th, g, mm, vv in zip(params, grads, m, v):
+        mm *= beta1
+        mm += (1.0 - beta1) * g
+        vv *= beta2
+        vv += (1.0 - beta2) * g * g
+        th -= lr * (mm * c1) / (np.sqrt(vv * c2) + eps)
+

@@ -763,8 +763,10 @@ int orc_sphere_trace_pp(const orc_octree* t, const orc_model* M, const float* o,
 /* Training objective (Eq. 4) and its gradient                          */
 /* ------------------------------------------------------------------ */
 /*
- * J = (1/P) sum_p sum_{L=1..Lmax} (f_{theta_L}([x_p, z(x_p; L)]) - d_p)^2
- * Reverse mode, per point and LOD L with g = 2 (dhat_L - d)/P:
+ * J = (1/P) sum_p sum_{L=1..Lmax} w_L (f_{theta_L}([x_p, z(x_p; L)]) - d_p)^2
+ * with w_L = 1 (Eq. 4), or per-LOD weights (0/1 for the progressive
+ * schedule of the training appendix: LODs not yet trainable have weight 0).
+ * Reverse mode, per point and LOD L with g = 2 w_L (dhat_L - d)/P:
  *   dW2_L += g h,  db2_L += g,  ga = w2 . 1[a > 0] g,
  *   dW1_L += ga (x) [x; z_L],  db1_L += ga,  dz_L = W1_z^T ga,
  *   dpsi_l = sum_{L >= l} dz_L,  dZ_l[corner(v_l, j)] += w_j dpsi_l.
@@ -772,9 +774,10 @@ int orc_sphere_trace_pp(const orc_octree* t, const orc_model* M, const float* o,
  * Gradients are written (not accumulated) into the caller's buffers, laid
  * out like the parameters.  sdf_all (nullable) receives dhat_L [Lmax][P].
  */
-int orc_train_fwd_bwd(const orc_octree* t, const orc_model* M, const float* xs, const float* target,
-                      int64_t P, double* loss, double* const* dfeat, double* const* dW1,
-                      double* const* db1, double* const* dw2, double* db2, double* sdf_all) {
+int orc_train_fwd_bwd_w(const orc_octree* t, const orc_model* M, const float* xs, const float* target,
+                        int64_t P, const double* lod_weight, double* loss, double* const* dfeat,
+                        double* const* dW1, double* const* db1, double* const* dw2, double* db2,
+                        double* sdf_all) {
   int Lm = M->num_lods, m = M->m, H = M->hidden, din = din_of(M);
   if (Lm != t->num_lods || m > 64) return -1;
   int nth = 1;
@@ -854,8 +857,9 @@ int orc_train_fwd_bwd(const orc_octree* t, const orc_model* M, const float* xs, 
         }
         if (sdf_all) sdf_all[(size_t)(L - 1) * P + p] = out;
         double res = out - (double)target[p];
-        *gloss += res * res / (double)P;
-        double g = 2.0 * res / (double)P;
+        double wL = lod_weight ? lod_weight[L - 1] : 1.0;
+        *gloss += wL * res * res / (double)P;
+        double g = 2.0 * wL * res / (double)P;
         gb2[L - 1] += g;
         for (int q = 0; q < m; ++q) dz[L - 1][q] = 0.0;
         for (int k = 0; k < H; ++k) {
@@ -912,8 +916,147 @@ int orc_train_fwd_bwd(const orc_octree* t, const orc_model* M, const float* xs, 
   return 0;
 }
 
+int orc_train_fwd_bwd(const orc_octree* t, const orc_model* M, const float* xs, const float* target,
+                      int64_t P, double* loss, double* const* dfeat, double* const* dW1,
+                      double* const* db1, double* const* dw2, double* db2, double* sdf_all) {
+  return orc_train_fwd_bwd_w(t, M, xs, target, P, NULL, loss, dfeat, dW1, db1, dw2, db2, sdf_all);
+}
+
 /* Loss only (Eq. 4), for finite-difference checks. */
 int orc_loss(const orc_octree* t, const orc_model* M, const float* xs, const float* target, int64_t P,
              double* loss) {
   return orc_train_fwd_bwd(t, M, xs, target, P, loss, NULL, NULL, NULL, NULL, NULL, NULL);
 }
+
+/* ------------------------------------------------------------------ */
+/* Analytic shapes and the SDF surface sampler (training appendix)      */
+/* ------------------------------------------------------------------ */
+/*
+ * Union of spheres (cx, cy, cz, R) and tori (cx, cy, cz, R, r, axis): the
+ * minimum of the primitives' exact signed distances.  A torus with axis a
+ * has its ring in the plane of the other two coordinates.
+ */
+double orc_shape_sdf(int ns, const double* sph, int nt, const double* tor, const double x[3]) {
+  double best = INFINITY;
+  for (int i = 0; i < ns; ++i) {
+    const double* c = sph + 4 * i;
+    double q0 = x[0] - c[0], q1 = x[1] - c[1], q2 = x[2] - c[2];
+    double dist = sqrt(q0 * q0 + q1 * q1 + q2 * q2) - c[3];
+    if (dist < best) best = dist;
+  }
+  for (int i = 0; i < nt; ++i) {
+    const double* c = tor + 6 * i;
+    double q[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+    int a = (int)c[5];
+    int u = a == 0 ? 1 : 0, v = a == 2 ? 1 : 2;
+    double ring = sqrt(q[u] * q[u] + q[v] * q[v]) - c[3];
+    double dist = sqrt(ring * ring + q[a] * q[a]) - c[4];
+    if (dist < best) best = dist;
+  }
+  return best;
+}
+
+int orc_shape_sdf_many(int ns, const double* sph, int nt, const double* tor, const float* xs, int64_t P,
+                       double* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t p = 0; p < P; ++p) {
+    double x[3] = {xs[p], xs[P + p], xs[2 * P + p]};
+    out[p] = orc_shape_sdf(ns, sph, nt, tor, x);
+  }
+  return 0;
+}
+
+/*
+ * SDF surface sampler: ray i starts at a uniform point of the box,
+ * o = -1 + 2 (u0, u1, u2), with a uniform direction on the sphere,
+ * z = 1 - 2 u3, phi = 2 pi u4, d = (sqrt(1 - z^2) cos phi,
+ * sqrt(1 - z^2) sin phi, z); it is sphere traced with steps |SDF| from
+ * t = 0 and hits when |SDF| < delta (the point is returned), misses when it
+ * leaves the box or after max_steps.  u: [5][n] uniforms in [0, 1).
+ * marginal (nullable) flags rays whose outcome could flip under rounding:
+ * a step ending within margin of the box or |SDF| within margin of delta.
+ */
+int orc_sample_surface(int ns, const double* sph, int nt, const double* tor, const float* u, int64_t n,
+                       int max_steps, double delta, double margin, double* pts, uint8_t* hit, uint8_t* marginal) {
+  const double two_pi = 6.283185307179586476925286766559;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double o[3], d[3];
+    for (int a = 0; a < 3; ++a) o[a] = -1.0 + 2.0 * (double)u[(size_t)a * (size_t)n + (size_t)i];
+    double z = 1.0 - 2.0 * (double)u[3 * (size_t)n + (size_t)i];
+    double phi = two_pi * (double)u[4 * (size_t)n + (size_t)i];
+    double rxy = sqrt(fmax(0.0, 1.0 - z * z));
+    d[0] = rxy * cos(phi);
+    d[1] = rxy * sin(phi);
+    d[2] = z;
+    double t = 0.0;
+    uint8_t h = 0, mg = 0;
+    double x[3] = {o[0], o[1], o[2]};
+    for (int k = 0; k < max_steps; ++k) {
+      for (int a = 0; a < 3; ++a) x[a] = o[a] + t * d[a];
+      int out = 0;
+      for (int a = 0; a < 3; ++a) {
+        if (fabs(x[a]) > 1.0) out = 1;
+        if (fabs(fabs(x[a]) - 1.0) <= margin) mg = 1;
+      }
+      if (out) break;
+      double sd = orc_shape_sdf(ns, sph, nt, tor, x);
+      if (fabs(fabs(sd) - delta) <= margin) mg = 1;
+      if (fabs(sd) < delta) { h = 1; break; }
+      t += fabs(sd);
+    }
+    for (int a = 0; a < 3; ++a) pts[(size_t)a * (size_t)n + (size_t)i] = h ? x[a] : 0.0;
+    hit[i] = h;
+    if (marginal) marginal[i] = mg;
+  }
+  return 0;
+}
+
+/*
+ * Training points in the 2:2:1 surface : near : uniform split of the
+ * training appendix, interleaved so every run of five points holds the
+ * ratio: point i with q = i / 5, c = i % 5 is
+ *   c = 0, 1: surface sample S[2q + c];
+ *   c = 2, 3: near sample S[2q + c - 2] + sigma * g, g a standard normal
+ *             triple from Box-Muller on (u0, u1), (u2, u3);
+ *   c = 4:    uniform -1 + 2 (u0, u1, u2);
+ * with u = uni[.][i] ([4][N] uniforms in [0, 1]; a radius input u0 or u2
+ * of 0 is read as 1).  The
+ * surface samples S ([3][ns_pts]) are used cyclically.  The target is the
+ * shape's SDF at the (float32) point.
+ */
+int orc_training_points(int ns, const double* sph, int nt, const double* tor, const double* S, int64_t ns_pts,
+                        const float* uni, int64_t N, double sigma, float* xs, double* target) {
+  if (ns_pts <= 0) return -1;
+  const double two_pi = 6.283185307179586476925286766559;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t q = i / 5;
+    int c = (int)(i % 5);
+    double u[4];
+    for (int a = 0; a < 4; ++a) u[a] = (double)uni[(size_t)a * (size_t)N + (size_t)i];
+    double x[3];
+    if (c < 4) {
+      int64_t k = (2 * q + (c < 2 ? c : c - 2)) % ns_pts;
+      for (int a = 0; a < 3; ++a) x[a] = S[(size_t)a * (size_t)ns_pts + (size_t)k];
+      if (c >= 2) {
+        double r1 = sqrt(-2.0 * log(u[0] > 0.0 ? u[0] : 1.0)), r2 = sqrt(-2.0 * log(u[2] > 0.0 ? u[2] : 1.0));
+        double g0 = r1 * cos(two_pi * u[1]), g1 = r1 * sin(two_pi * u[1]), g2 = r2 * cos(two_pi * u[3]);
+        x[0] += sigma * g0;
+        x[1] += sigma * g1;
+        x[2] += sigma * g2;
+      }
+    } else {
+      for (int a = 0; a < 3; ++a) x[a] = -1.0 + 2.0 * u[a];
+    }
+    double xf[3];
+    for (int a = 0; a < 3; ++a) {
+      float f = (float)x[a];
+      xs[(size_t)a * (size_t)N + (size_t)i] = f;
+      xf[a] = (double)f;
+    }
+    target[i] = orc_shape_sdf(ns, sph, nt, tor, xf);
+  }
+  return 0;
+}
+
