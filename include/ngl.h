@@ -384,6 +384,69 @@ int ngl_train_fwd_bwd(const ngl_model* m, const float* x, const float* target, i
                       float* const* db1, float* const* dw2, float* db2, void* ws,
                       size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------ */
+/* 5. Fitting (training appendix): analytic shapes, samplers, Adam        */
+/* ------------------------------------------------------------------ */
+/* Synthetic ground-truth shape: union of spheres [cx, cy, cz, R] and tori
+ * [cx, cy, cz, R, r, axis] (axis 0/1/2 = x/y/z; the ring lies in the plane
+ * of the other two coordinates), FP32 device arrays.  Its SDF is the
+ * minimum of the primitives' exact signed distances. */
+typedef struct {
+  int32_t n_spheres, n_tori;
+  const float* spheres; /* device [n_spheres][4] */
+  const float* tori;    /* device [n_tori][6] */
+} ngl_shape;
+
+/* sdf[p] = union SDF at x[.][p] (device [3][P] in, device [P] out). */
+int ngl_shape_sdf(const ngl_shape* shape, const float* x, int64_t P, float* sdf, void* stream);
+
+/* SDF surface sampler (training appendix, Sampling): candidate ray i starts
+ * at -1 + 2 (u0, u1, u2) with direction (sqrt(1-z^2) cos phi,
+ * sqrt(1-z^2) sin phi, z), z = 1 - 2 u3, phi = 2 pi u4 (u: device [5][n]
+ * uniforms in [0, 1]); it takes |SDF| steps from t = 0 and hits when
+ * |SDF| < delta, misses on leaving [-1, 1]^3 or after max_steps.  The hit
+ * points are written compacted in ray order to pts (device [3][n], stride
+ * n) and their number to *count (device int64).  ws: device bytes from
+ * ngl_sample_surface_workspace(n). */
+int ngl_sample_surface_workspace(int64_t n, size_t* bytes);
+int ngl_sample_surface(const ngl_shape* shape, const float* u, int64_t n, int32_t max_steps, float delta,
+                       float* pts, int64_t* count, void* ws, size_t ws_bytes, void* stream);
+
+/* Training set of N points (training appendix: 2:2:1 surface, near,
+ * uniform), interleaved so that point i (q = i / 5, c = i % 5) is surface
+ * sample S[2q + c] (c = 0, 1), S[2q + c - 2] plus sigma times a standard
+ * normal triple from Box-Muller on (u0, u1), (u2, u3) (c = 2, 3; a radius
+ * input of 0 reads as 1), or -1 + 2 (u0, u1, u2) (c = 4), with u = uniforms
+ * [.][i] (device [4][N]) and the n_surface samples S (device [3][stride])
+ * used cyclically.  x is written batch-major, device [N/batch][3][batch]
+ * (N a multiple of batch), target[i] (device [N]) = the shape's SDF at
+ * point i. */
+int ngl_training_points(const ngl_shape* shape, const float* surface, int64_t n_surface, int64_t surface_stride,
+                        const float* uniforms, int64_t N, int64_t batch, float sigma, float* x, float* target,
+                        void* stream);
+
+/* One Adam step (Kingma and Ba 2015, Algorithm 1) over n <= 64 FP32 device
+ * tensors in one launch: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * theta -= lr (m c1) / (sqrt(v c2) + eps), c1 = 1/(1 - b1^step),
+ * c2 = 1/(1 - b2^step) (host FP64, rounded to FP32).  param/grad/m/v: host
+ * arrays of n device pointers, numel: host [n].  step >= 1. */
+#define NGL_MAX_ADAM_TENSORS 64
+typedef struct {
+  float lr, beta1, beta2, eps;
+  int32_t step;
+} ngl_adam_params;
+int ngl_adam_step(const ngl_adam_params* p, int32_t n, float* const* param, const float* const* grad,
+                  float* const* m, float* const* v, const int64_t* numel, void* stream);
+
+/* Eq. 4 with a weight per LOD (host [num_lods], finite, >= 0):
+ * J = (1/P) sum_p sum_L w_L (dhat_L - d)^2.  Weight 0 removes a LOD's
+ * term (progressive schedule of the training appendix); all ones is
+ * ngl_train_fwd_bwd. */
+int ngl_train_fwd_bwd_lods(const ngl_model* m, const float* x, const float* target, int64_t P,
+                           const float* lod_weight, float* loss, float* sdf_all, float* const* dfeat,
+                           float* const* dW1, float* const* db1, float* const* dw2, float* db2, void* ws,
+                           size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

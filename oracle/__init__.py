@@ -106,7 +106,8 @@ def _setup(lib):
     lib.orc_train_fwd_bwd_w.restype = C.c_int
     lib.orc_train_fwd_bwd_w.argtypes = [P, P, P, P, i64, P, P, P, P, P, P, P, P]
     lib.orc_shape_sdf_many.argtypes = [C.c_int, P, C.c_int, P, P, i64, P]
-    lib.orc_sample_surface.argtypes = [C.c_int, P, C.c_int, P, P, i64, C.c_int, C.c_double, C.c_double, P, P, P]
+    lib.orc_sample_surface.argtypes = [C.c_int, P, C.c_int, P, P, i64, C.c_int, C.c_double, C.c_double, C.c_double,
+                                       P, P, P]
     lib.orc_training_points.restype = C.c_int
     lib.orc_training_points.argtypes = [C.c_int, P, C.c_int, P, P, i64, P, i64, C.c_double, P, P]
     lib.orc_train_fwd_bwd.restype = C.c_int
@@ -505,7 +506,7 @@ def shape_sdf(spheres, tori, x_soa):
     return out
 
 
-def sample_surface(spheres, tori, u, max_steps: int, delta: float, margin: float = 0.0):
+def sample_surface(spheres, tori, u, max_steps: int, delta: float, margin_box: float = 0.0, margin_sdf: float = 0.0):
     """SDF surface sampler (see orc_sample_surface); u: [5][n] float32."""
     sph, tor = _shape_arrays(spheres, tori)
     uu = _c(u, np.float32)
@@ -514,7 +515,7 @@ def sample_surface(spheres, tori, u, max_steps: int, delta: float, margin: float
     hit = np.zeros(n, np.uint8)
     marg = np.zeros(n, np.uint8)
     _load().orc_sample_surface(len(sph), _ptr(sph), len(tor), _ptr(tor), _ptr(uu), n, int(max_steps), float(delta),
-                               float(margin), _ptr(pts), _ptr(hit), _ptr(marg))
+                               float(margin_box), float(margin_sdf), _ptr(pts), _ptr(hit), _ptr(marg))
     return dict(points=pts, hit=hit.astype(bool), marginal=marg.astype(bool))
 
 

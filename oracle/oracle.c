@@ -974,10 +974,12 @@ int orc_shape_sdf_many(int ns, const double* sph, int nt, const double* tor, con
  * t = 0 and hits when |SDF| < delta (the point is returned), misses when it
  * leaves the box or after max_steps.  u: [5][n] uniforms in [0, 1).
  * marginal (nullable) flags rays whose outcome could flip under rounding:
- * a step ending within margin of the box or |SDF| within margin of delta.
+ * a step ending within margin_box of the box's faces, or with |SDF| within
+ * margin_sdf of delta.
  */
 int orc_sample_surface(int ns, const double* sph, int nt, const double* tor, const float* u, int64_t n,
-                       int max_steps, double delta, double margin, double* pts, uint8_t* hit, uint8_t* marginal) {
+                       int max_steps, double delta, double margin_box, double margin_sdf, double* pts, uint8_t* hit,
+                       uint8_t* marginal) {
   const double two_pi = 6.283185307179586476925286766559;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) {
@@ -997,11 +999,11 @@ int orc_sample_surface(int ns, const double* sph, int nt, const double* tor, con
       int out = 0;
       for (int a = 0; a < 3; ++a) {
         if (fabs(x[a]) > 1.0) out = 1;
-        if (fabs(fabs(x[a]) - 1.0) <= margin) mg = 1;
+        if (fabs(fabs(x[a]) - 1.0) <= margin_box) mg = 1;
       }
       if (out) break;
       double sd = orc_shape_sdf(ns, sph, nt, tor, x);
-      if (fabs(fabs(sd) - delta) <= margin) mg = 1;
+      if (fabs(fabs(sd) - delta) <= margin_sdf) mg = 1;
       if (fabs(sd) < delta) { h = 1; break; }
       t += fabs(sd);
     }

@@ -15,6 +15,8 @@
 //      k_vox_reduce sums each voxel's records; k_corner gathers, for every
 //      corner, the partials of the (voxel, slot) pairs that share it.
 #include "ngl_common.h"
+
+#include <cmath>
 #include "ngl_device.h"
 
 namespace ngl {
@@ -168,6 +170,7 @@ struct PointArgs {
   const float* target;      // training: [P] (original order)
   const float* grad;        // backward only: [L][P] (original order)
   float inv_p;
+  float lod_w[NGL_MAX_LODS];  // training: weight of each LOD's loss term
   float* sdf_all;           // nullable [L][P] (original order)
   float* zrows;             // [L][P][M] z_L in sorted order
   float* drows;             // [L][P][M] dpsi_l in sorted order
@@ -245,9 +248,9 @@ __global__ __launch_bounds__(kBlock) void k_point(ngl_model md, PointArgs A) {
       }
       float g;
       if constexpr (TRAIN) {
-        const float res = out - tgt;
-        lossacc = fmaf(res, res, lossacc);
-        g = 2.0f * res * A.inv_p;
+        const float wres = A.lod_w[l - 1] * (out - tgt);
+        lossacc = fmaf(wres, out - tgt, lossacc);
+        g = 2.0f * wres * A.inv_p;
       } else {
         g = A.grad[int64_t(l - 1) * P + id];
       }
@@ -655,8 +658,8 @@ static int check_train(const ngl_model* m) {
 
 template <int M, bool XYZ>
 static int run_train(const ngl_model& md, const float* x, const float* target, const float* grad, int64_t P,
-                     float* loss, float* sdf_all, float* const* dfeat, float* const* dW1, float* const* db1,
-                     float* const* dw2, float* db2, const TrainWS& w, hipStream_t s) {
+                     const float* lod_weight, float* loss, float* sdf_all, float* const* dfeat, float* const* dW1,
+                     float* const* db1, float* const* dw2, float* db2, const TrainWS& w, hipStream_t s) {
   const int Lm = md.num_lods;
   const int D = Lm + 1;
   const unsigned pgrid = unsigned((P + kBlock - 1) / kBlock);
@@ -680,6 +683,7 @@ static int run_train(const ngl_model& md, const float* x, const float* target, c
   A.target = target;
   A.grad = grad;
   A.inv_p = 1.0f / float(P);
+  for (int l = 0; l < NGL_MAX_LODS; ++l) A.lod_w[l] = lod_weight && l < Lm ? lod_weight[l] : 1.0f;
   A.sdf_all = sdf_all;
   A.zrows = w.zrows;
   A.drows = w.drows;
@@ -755,7 +759,7 @@ static int zero_grads(const ngl_model& md, float* loss, float* const* dfeat, flo
 }
 
 static int train_entry(const ngl_model* m, const float* x, const float* target, const float* grad, int64_t P,
-                       float* loss, float* sdf_all, float* const* dfeat, float* const* dW1, float* const* db1,
+                       const float* lod_weight, float* loss, float* sdf_all, float* const* dfeat, float* const* dW1, float* const* db1,
                        float* const* dw2, float* db2, void* ws, size_t ws_bytes, void* stream) {
   int rc = check_train(m);
   if (rc) return rc;
@@ -772,7 +776,7 @@ static int train_entry(const ngl_model* m, const float* x, const float* target, 
   NGL_REQUIRE(ws != nullptr && ws_bytes >= w.bytes, "workspace too small: %zu < %zu bytes", ws_bytes, w.bytes);
   const ngl_model& md = *m;
 #define NGL_TRAIN_CALL(M_, X_) \
-  return run_train<M_, X_>(md, x, target, grad, P, loss, sdf_all, dfeat, dW1, db1, dw2, db2, w, s)
+  return run_train<M_, X_>(md, x, target, grad, P, lod_weight, loss, sdf_all, dfeat, dW1, db1, dw2, db2, w, s)
 #define NGL_TRAIN_M(M_)          \
   if (md.with_xyz) NGL_TRAIN_CALL(M_, true); \
   else NGL_TRAIN_CALL(M_, false);
@@ -802,8 +806,8 @@ int ngl_backward_all_lods(const ngl_model* m, const float* x, int64_t P, const f
                           float* const* dW1, float* const* db1, float* const* dw2, float* db2, void* ws,
                           size_t ws_bytes, void* stream) {
   NGL_REQUIRE(P == 0 || grad_sdf != nullptr, "grad_sdf is null");
-  return ngl::train_entry(m, x, nullptr, grad_sdf, P, nullptr, nullptr, dfeat, dW1, db1, dw2, db2, ws, ws_bytes,
-                          stream);
+  return ngl::train_entry(m, x, nullptr, grad_sdf, P, nullptr, nullptr, nullptr, dfeat, dW1, db1, dw2, db2, ws,
+                          ws_bytes, stream);
 }
 
 int ngl_train_fwd_bwd(const ngl_model* m, const float* x, const float* target, int64_t P, float* loss,
@@ -811,7 +815,21 @@ int ngl_train_fwd_bwd(const ngl_model* m, const float* x, const float* target, i
                       float* db2, void* ws, size_t ws_bytes, void* stream) {
   NGL_REQUIRE(P == 0 || target != nullptr, "target is null");
   NGL_REQUIRE(loss != nullptr, "loss is null");
-  return ngl::train_entry(m, x, target, nullptr, P, loss, sdf_all, dfeat, dW1, db1, dw2, db2, ws, ws_bytes, stream);
+  return ngl::train_entry(m, x, target, nullptr, P, nullptr, loss, sdf_all, dfeat, dW1, db1, dw2, db2, ws, ws_bytes,
+                          stream);
+}
+
+int ngl_train_fwd_bwd_lods(const ngl_model* m, const float* x, const float* target, int64_t P,
+                           const float* lod_weight, float* loss, float* sdf_all, float* const* dfeat,
+                           float* const* dW1, float* const* db1, float* const* dw2, float* db2, void* ws,
+                           size_t ws_bytes, void* stream) {
+  NGL_REQUIRE(P == 0 || target != nullptr, "target is null");
+  NGL_REQUIRE(loss != nullptr && lod_weight != nullptr, "loss or lod_weight is null");
+  NGL_REQUIRE(m != nullptr, "model is null");
+  for (int l = 0; l < m->num_lods && l < NGL_MAX_LODS; ++l)
+    NGL_REQUIRE(std::isfinite(lod_weight[l]) && lod_weight[l] >= 0.0f, "lod_weight[%d] must be finite and >= 0", l);
+  return ngl::train_entry(m, x, target, nullptr, P, lod_weight, loss, sdf_all, dfeat, dW1, db1, dw2, db2, ws,
+                          ws_bytes, stream);
 }
 
 }  // extern "C"

@@ -64,6 +64,14 @@ class ngl_trace_params(C.Structure):
                 ("analytic", i32), ("sphere", C.c_float * 4)]
 
 
+class ngl_shape(C.Structure):
+    _fields_ = [("n_spheres", i32), ("n_tori", i32), ("spheres", P), ("tori", P)]
+
+
+class ngl_adam_params(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float), ("step", i32)]
+
+
 class ngl_lod_select(C.Structure):
     _fields_ = [("d_near", C.c_float), ("d_far", C.c_float), ("lod_near", C.c_float), ("lod_far", C.c_float)]
 
@@ -94,6 +102,12 @@ EXPORTS = {
     "ngl_train_workspace": (C.c_int, [P, i64, P]),
     "ngl_backward_all_lods": (C.c_int, [P, P, i64, P, P, P, P, P, P, P, C.c_size_t, P]),
     "ngl_train_fwd_bwd": (C.c_int, [P, P, P, i64, P, P, P, P, P, P, P, P, C.c_size_t, P]),
+    "ngl_train_fwd_bwd_lods": (C.c_int, [P, P, P, i64, P, P, P, P, P, P, P, P, P, C.c_size_t, P]),
+    "ngl_shape_sdf": (C.c_int, [P, P, i64, P, P]),
+    "ngl_sample_surface_workspace": (C.c_int, [i64, P]),
+    "ngl_sample_surface": (C.c_int, [P, P, i64, i32, C.c_float, P, P, P, C.c_size_t, P]),
+    "ngl_training_points": (C.c_int, [P, P, i64, i64, P, i64, i64, C.c_float, P, P, P]),
+    "ngl_adam_step": (C.c_int, [P, i32, P, P, P, P, P, P]),
 }
 
 
@@ -643,3 +657,90 @@ class NGLODSdf(torch.autograd.Function):
 def parameters(model: Model):
     """The model's tensors in the order NGLODSdf.backward returns gradients."""
     return [*model.feats, *model.W1, *model.b1, *model.w2, model.b2]
+
+
+# ---------------------------------------------------------------------------
+# 5. Fitting pieces: analytic shapes, samplers, Adam, per-LOD loss weights
+# ---------------------------------------------------------------------------
+class DeviceShape:
+    """A sphere/torus union (spheres [n][4], tori [n][6]) in device memory."""
+
+    def __init__(self, spheres, tori, device="cuda"):
+        sph = torch.tensor(np.asarray(spheres, np.float64).reshape(-1, 4), dtype=torch.float32, device=device)
+        tor = torch.tensor(np.asarray(tori, np.float64).reshape(-1, 6), dtype=torch.float32, device=device)
+        self.spheres, self.tori = sph.contiguous(), tor.contiguous()
+        self.s = ngl_shape()
+        self.s.n_spheres, self.s.n_tori = sph.shape[0], tor.shape[0]
+        self.s.spheres, self.s.tori = _ptr(self.spheres), _ptr(self.tori)
+        self.ref = C.addressof(self.s)
+
+    def host(self):
+        """The FP32-rounded primitives as float64 arrays."""
+        return (self.spheres.double().cpu().numpy().reshape(-1, 4), self.tori.double().cpu().numpy().reshape(-1, 6))
+
+
+def shape_sdf(shape: DeviceShape, x: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
+    _dev(x, torch.float32)
+    o = out if out is not None else torch.empty(x.shape[1], dtype=torch.float32, device=x.device)
+    _check(lib().ngl_shape_sdf(shape.ref, _ptr(x), x.shape[1], _ptr(o), _stream()))
+    return o
+
+
+def sample_surface(shape: DeviceShape, u: torch.Tensor, max_steps: int, delta: float, out: dict = None) -> dict:
+    """SDF surface sampler: u [5][n] uniforms; returns pts [3][n] (the first
+    `count` columns are the hits, in ray order) and a device count."""
+    _dev(u, torch.float32)
+    n = u.shape[1]
+    dev = u.device
+    if out is None:
+        nb = C.c_size_t()
+        _check(lib().ngl_sample_surface_workspace(n, C.addressof(nb)))
+        out = dict(pts=torch.empty((3, n), dtype=torch.float32, device=dev),
+                   count=torch.zeros(1, dtype=torch.int64, device=dev),
+                   ws=torch.empty(max(int(nb.value), 4), dtype=torch.uint8, device=dev))
+    _check(lib().ngl_sample_surface(shape.ref, _ptr(u), n, int(max_steps), float(delta), _ptr(out["pts"]),
+                                    _ptr(out["count"]), _ptr(out["ws"]), out["ws"].numel(), _stream()))
+    return out
+
+
+def training_points(shape: DeviceShape, surface: torch.Tensor, n_surface: int, uniforms: torch.Tensor, batch: int,
+                    sigma: float = 0.01, x: torch.Tensor = None, target: torch.Tensor = None):
+    """2:2:1 training set: x [N/batch][3][batch] and targets [N]."""
+    _dev(surface, torch.float32)
+    _dev(uniforms, torch.float32)
+    N = uniforms.shape[1]
+    dev = uniforms.device
+    x = x if x is not None else torch.empty((N // batch, 3, batch), dtype=torch.float32, device=dev)
+    target = target if target is not None else torch.empty(N, dtype=torch.float32, device=dev)
+    _check(lib().ngl_training_points(shape.ref, _ptr(surface), int(n_surface), surface.shape[1], _ptr(uniforms), N,
+                                     int(batch), float(sigma), _ptr(x), _ptr(target), _stream()))
+    return x, target
+
+
+def adam_step(params, grads, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Fused Adam over lists of FP32 device tensors (in place)."""
+    n = len(params)
+    prm = ngl_adam_params()
+    prm.lr, prm.beta1, prm.beta2, prm.eps, prm.step = float(lr), float(beta1), float(beta2), float(eps), int(step)
+    arr = lambda lst: (P * max(n, 1))(*[_ptr(t) for t in lst])
+    numel = (i64 * max(n, 1))(*[t.numel() for t in params])
+    a = [arr(params), arr(grads), arr(m), arr(v)]
+    _check(lib().ngl_adam_step(C.addressof(prm), n, C.addressof(a[0]), C.addressof(a[1]), C.addressof(a[2]),
+                               C.addressof(a[3]), C.addressof(numel), _stream()))
+
+
+def train_fwd_bwd_lods(model: Model, x: torch.Tensor, target: torch.Tensor, lod_weight, grads: Grads = None,
+                       ws: torch.Tensor = None, loss: torch.Tensor = None, sdf_all: torch.Tensor = None):
+    """Eq. 4 with per-LOD weights (host list of num_lods floats)."""
+    _dev(x, torch.float32)
+    _dev(target, torch.float32)
+    Pn = x.shape[1]
+    g = grads if grads is not None else Grads(model)
+    w = ws if ws is not None else train_workspace(model, Pn, x.device)
+    ls = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=x.device)
+    lw = (C.c_float * MAX_LODS)(*([float(v) for v in lod_weight] + [0.0] * (MAX_LODS - len(lod_weight))))
+    _check(lib().ngl_train_fwd_bwd_lods(model.ref, _ptr(x), _ptr(target), Pn, C.addressof(lw), _ptr(ls),
+                                        _ptr(sdf_all), g.ptrs[0], g.ptrs[1], g.ptrs[2], g.ptrs[3], _ptr(g.db2),
+                                        _ptr(w), w.numel(), _stream()))
+    return ls, g
+
