@@ -370,6 +370,7 @@ def main():
     if args.only is None:
         comp["decoder_bf16"] = run_decoder(S, dev, args.steps, args.warmup)
         comp["frame_lod_select"] = run_lod_select(model, cfg, o, d, buf, args.steps, args.warmup)
+        comp["fit"] = run_fit(S, dev)
         if do_h:
             hq = comp["bf16_form"]["queries_per_s"] * DEC_MFMA_FLOPS / 1e12
             comp["bf16_form"]["fused_decoder_mfma_frac"] = hq / BF16_PEAK_TFLOPS
@@ -451,6 +452,38 @@ def run_lod_select(model, cfg, o, d, buf, steps, warmup):
             "traverse_ms": trav, "trace_ms": trace, "ms": trav + trace, "visible_px": int(hit.sum()),
             "sdf_evals": int(out["steps"].sum()), "mean_lod_of_hits": float(lod[hit].mean()) if hit.any() else None,
             "rays_per_lod": {str(L): int(((np.floor(lod) == L) | ((L == 5) & (lod >= 5))).sum()) for L in (2, 3, 4, 5)}}
+
+
+def run_fit(S, dev):
+    """The fitting loop of the training appendix on the paper-scale shape
+    and octree, from a random FP32 init: 500,000 points per epoch in the
+    2:2:1 split (surface samples from the SDF sampler), Adam at lr 1e-3,
+    all LODs jointly; one warm-up epoch, then one timed epoch at the
+    paper's batch of 512 and one at a batch of 16,384."""
+    import torch
+    from paper_2101_10994_amd import fit, ngl
+    from paper_2101_10994_amd import workloads as W
+    cfg, tree, shape = S["cfg"], S["tree"], S["shape"]
+    rs = W.rngs(7)
+    feats = W.features(rs[W.STREAM_FEAT], tree.ncorner, cfg.feat_dim)
+    dec = W.decoders(rs[W.STREAM_DEC], cfg.num_lods, cfg.feat_dim + 3, cfg.hidden)
+    f32 = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+    model = ngl.Model(tree, [f32(f) for f in feats], [f32(w) for w in dec["W1"]], [f32(b) for b in dec["b1"]],
+                      [f32(w) for w in dec["w2"]], f32(dec["b2"]))
+    ds = ngl.DeviceShape(shape.spheres, shape.tori, device=dev)
+    out = {"points_per_epoch": 500000, "lr": 1e-3, "schedule": "joint"}
+    for batch in (512, 16384):
+        f = fit.Fitter(model, ds, points=500000, batch=batch, seed=batch)
+        first = f.run_epoch()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        last = f.run_epoch()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        out["batch_%d" % batch] = {"epoch_ms": ms, "points_per_s": f.N / (ms * 1e-3), "steps": f.N // batch,
+                                   "loss_epoch1": first, "loss_epoch2": last,
+                                   "surface_samples": int(f.sampler["count"].item())}
+    return out
 
 
 def run_batch(dev, steps, warmup):

@@ -16,13 +16,20 @@
 //      corner, the partials of the (voxel, slot) pairs that share it.
 #include "ngl_common.h"
 
+#include <algorithm>
 #include <cmath>
 #include "ngl_device.h"
 
 namespace ngl {
 
-constexpr int kSortGrid = 512;  // blocks of the radix-sort passes
-constexpr int kDecGrid = 128;   // blocks per LOD of the decoder-gradient pass
+constexpr int kSortGrid = 512;  // most blocks of the radix-sort passes
+constexpr int kDecGrid = 128;   // most blocks per LOD of the decoder-gradient pass
+
+// Grids sized to the batch (small batches of the fitting loop would
+// otherwise pay for the full grids): about 1024 keys per sort block and
+// 256 points per decoder-gradient block.  Deterministic for a given P.
+inline int sort_grid(int64_t P) { return int(std::min<int64_t>(kSortGrid, std::max<int64_t>(1, (P + 1023) / 1024))); }
+inline int dec_grid(int64_t P) { return int(std::min<int64_t>(kDecGrid, std::max<int64_t>(1, (P + 255) / 256))); }
 constexpr int kTile = 64;       // sorted points per record tile (one wavefront)
 
 __device__ inline uint32_t spread3_10(uint32_t v) {
@@ -52,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(const float* __restrict__ xs, i
 }
 
 __device__ inline void sort_chunk(int64_t n, int64_t& begin, int64_t& end) {
-  int64_t chunk = (n + kSortGrid - 1) / kSortGrid;
+  int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   chunk = (chunk + kBlock - 1) / kBlock * kBlock;
   begin = int64_t(blockIdx.x) * chunk;
   end = begin + chunk < n ? begin + chunk : n;
@@ -67,7 +74,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __restric
   sort_chunk(n, begin, end);
   for (int64_t t = begin + threadIdx.x; t < end; t += kBlock) atomicAdd(&h[(key[t] >> shift) & 255u], 1u);
   __syncthreads();
-  hist[threadIdx.x * kSortGrid + blockIdx.x] = h[threadIdx.x];
+  hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
 // Exclusive scan of n uint32 values in place by one block of 1024 lanes;
@@ -122,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint32_t* __rest
                                                           int64_t n, int shift, const uint32_t* __restrict__ offs) {
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[kBlock / 64][256];
-  run[threadIdx.x] = offs[threadIdx.x * kSortGrid + blockIdx.x];
+  run[threadIdx.x] = offs[threadIdx.x * gridDim.x + blockIdx.x];
   int64_t begin, end;
   sort_chunk(n, begin, end);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -345,7 +352,7 @@ struct DecArgs {
   const uint32_t* sidx;
   const float* zrows;
   const float* gs;
-  float* part;      // [L][kDecGrid][PH][H][din+2]
+  float* part;      // [L][kDecGrid][PH][H][din+2] (the first gridDim.x blocks)
   float* part_b2;   // [L][kDecGrid]
 };
 
@@ -371,7 +378,7 @@ __global__ __launch_bounds__(kBlock) void k_dec_grad(ngl_model md, DecArgs A) {
 #pragma unroll
   for (int i = 0; i < DIN; ++i) acc[i] = 0.0f;
   float ab1 = 0.0f, aw2 = 0.0f, ab2 = 0.0f;
-  int64_t chunk = (P + kDecGrid - 1) / kDecGrid;
+  int64_t chunk = (P + gridDim.x - 1) / gridDim.x;
   chunk = (chunk + kTile - 1) / kTile * kTile;
   const int64_t begin = int64_t(blockIdx.x) * chunk;
   const int64_t end = begin + chunk < P ? begin + chunk : P;
@@ -423,14 +430,14 @@ struct DecOut {
 
 __global__ __launch_bounds__(kBlock) void k_dec_reduce(const float* __restrict__ part,
                                                        const float* __restrict__ part_b2, int H, int din, int PH,
-                                                       DecOut O) {
+                                                       int nblk, DecOut O) {
   const int L = blockIdx.y + 1;
   const int e = blockIdx.x * kBlock + threadIdx.x;  // entry of [H][din+2]
   const int W = din + 2;
   if (e < H * W) {
     const int k = e / W, i = e % W;
     float s = 0.0f;
-    for (int b = 0; b < kDecGrid; ++b)
+    for (int b = 0; b < nblk; ++b)
       for (int ph = 0; ph < PH; ++ph) s += part[(((int64_t(L - 1) * kDecGrid + b) * PH + ph) * H + k) * W + i];
     if (i < din) O.dW1[L - 1][k * din + i] = s;
     else if (i == din) O.db1[L - 1][k] = s;
@@ -438,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_dec_reduce(const float* __restrict__
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     float s = 0.0f;
-    for (int b = 0; b < kDecGrid; ++b) s += part_b2[int64_t(L - 1) * kDecGrid + b];
+    for (int b = 0; b < nblk; ++b) s += part_b2[int64_t(L - 1) * kDecGrid + b];
     O.db2[L - 1] = s;
   }
 }
@@ -666,11 +673,12 @@ static int run_train(const ngl_model& md, const float* x, const float* target, c
   // 1. sort by finest-cell Morton code (3D+1 key bits)
   k_keys<<<pgrid, kBlock, 0, s>>>(x, P, D, w.key[0], w.val[0]);
   const int bits = 3 * D + 1;
+  const int sgrid = sort_grid(P);
   int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
-    k_radix_hist<<<kSortGrid, kBlock, 0, s>>>(w.key[cur], P, shift, w.hist);
-    k_scan_inplace<<<1, 1024, 0, s>>>(w.hist, int64_t(256) * kSortGrid, nullptr);
-    k_radix_scatter<<<kSortGrid, kBlock, 0, s>>>(w.key[cur], w.val[cur], w.key[cur ^ 1], w.val[cur ^ 1], P, shift,
+    k_radix_hist<<<sgrid, kBlock, 0, s>>>(w.key[cur], P, shift, w.hist);
+    k_scan_inplace<<<1, 1024, 0, s>>>(w.hist, int64_t(256) * sgrid, nullptr);
+    k_radix_scatter<<<sgrid, kBlock, 0, s>>>(w.key[cur], w.val[cur], w.key[cur ^ 1], w.val[cur ^ 1], P, shift,
                                                  w.hist);
     cur ^= 1;
   }
@@ -698,7 +706,8 @@ static int run_train(const ngl_model& md, const float* x, const float* target, c
   }
   // 3. decoder gradients
   DecArgs B{x, P, sidx, w.zrows, w.gs, w.dec_part, w.dec_b2};
-  k_dec_grad<M, XYZ><<<dim3(kDecGrid, Lm), kBlock, 0, s>>>(md, B);
+  const int dgrid = dec_grid(P);
+  k_dec_grad<M, XYZ><<<dim3(dgrid, Lm), kBlock, 0, s>>>(md, B);
   DecOut O{};
   for (int l = 0; l < Lm; ++l) {
     O.dW1[l] = dW1[l];
@@ -709,7 +718,7 @@ static int run_train(const ngl_model& md, const float* x, const float* target, c
   const int din = M + (XYZ ? 3 : 0);
   const int H = md.hidden;
   k_dec_reduce<<<dim3(unsigned((H * (din + 2) + kBlock - 1) / kBlock), Lm), kBlock, 0, s>>>(
-      w.dec_part, w.dec_b2, H, din, kBlock / H, O);
+      w.dec_part, w.dec_b2, H, din, kBlock / H, dgrid, O);
   // 4. feature gradients, level by level
   for (int l = 1; l <= Lm; ++l) {
     const int64_t nc = md.ncorner[l - 1];

@@ -110,11 +110,12 @@ class Fitter:
         grads = [self.grad_of[id(t)] for t in tensors]
         ms = [self.m[id(t)] for t in tensors]
         vs = [self.v[id(t)] for t in tensors]
+        adam = ngl.AdamGroup(tensors, grads, ms, vs)
         B = self.batch
         for b in range(self.N // B):
             ngl.train_fwd_bwd_lods(self.model, self.x[b], self.target[b * B:(b + 1) * B], wts, grads=self.grads,
                                    ws=self.ws, loss=self.losses[b:b + 1])
             self.step += 1
-            ngl.adam_step(tensors, grads, ms, vs, self.step, **self.hp)
+            adam.step(self.step, **self.hp)
         self.epoch += 1
         return float(self.losses.mean().item())

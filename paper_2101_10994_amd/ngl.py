@@ -717,16 +717,26 @@ def training_points(shape: DeviceShape, surface: torch.Tensor, n_surface: int, u
     return x, target
 
 
+class AdamGroup:
+    """Pointer tables of one set of tensors for ngl_adam_step, built once."""
+
+    def __init__(self, params, grads, m, v):
+        self.n = len(params)
+        arr = lambda lst: (P * max(self.n, 1))(*[_ptr(t) for t in lst])
+        self.numel = (i64 * max(self.n, 1))(*[t.numel() for t in params])
+        self.arrays = [arr(params), arr(grads), arr(m), arr(v)]
+        self.addr = [C.addressof(a) for a in self.arrays]
+        self.prm = ngl_adam_params()
+
+    def step(self, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        p = self.prm
+        p.lr, p.beta1, p.beta2, p.eps, p.step = float(lr), float(beta1), float(beta2), float(eps), int(step)
+        _check(lib().ngl_adam_step(C.addressof(p), self.n, *self.addr, C.addressof(self.numel), _stream()))
+
+
 def adam_step(params, grads, m, v, step: int, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     """Fused Adam over lists of FP32 device tensors (in place)."""
-    n = len(params)
-    prm = ngl_adam_params()
-    prm.lr, prm.beta1, prm.beta2, prm.eps, prm.step = float(lr), float(beta1), float(beta2), float(eps), int(step)
-    arr = lambda lst: (P * max(n, 1))(*[_ptr(t) for t in lst])
-    numel = (i64 * max(n, 1))(*[t.numel() for t in params])
-    a = [arr(params), arr(grads), arr(m), arr(v)]
-    _check(lib().ngl_adam_step(C.addressof(prm), n, C.addressof(a[0]), C.addressof(a[1]), C.addressof(a[2]),
-                               C.addressof(a[3]), C.addressof(numel), _stream()))
+    AdamGroup(params, grads, m, v).step(step, lr, beta1, beta2, eps)
 
 
 def train_fwd_bwd_lods(model: Model, x: torch.Tensor, target: torch.Tensor, lod_weight, grads: Grads = None,
