@@ -371,6 +371,7 @@ def main():
         comp["decoder_bf16"] = run_decoder(S, dev, args.steps, args.warmup)
         comp["frame_lod_select"] = run_lod_select(model, cfg, o, d, buf, args.steps, args.warmup)
         comp["fit"] = run_fit(S, dev)
+        comp["octree_build"] = run_octree_build(dev, args.steps)
         if do_h:
             hq = comp["bf16_form"]["queries_per_s"] * DEC_MFMA_FLOPS / 1e12
             comp["bf16_form"]["fused_decoder_mfma_frac"] = hq / BF16_PEAK_TFLOPS
@@ -484,6 +485,28 @@ def run_fit(S, dev):
                                    "loss_epoch1": first, "loss_epoch2": last,
                                    "surface_samples": int(f.sampler["count"].item())}
     return out
+
+
+def run_octree_build(dev, steps):
+    """Device octree build (the initialisation pass) from the 7-LOD
+    occupancy of the 32-sphere/4-torus union (res 256), against the host
+    build of the same cells."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    from paper_2101_10994_amd import workloads as W
+    ijk = W.occupancy_ijk(W.prec_shape(0), 256)
+    t0 = time.perf_counter()
+    ngl.Octree(ijk, 7, device=None)
+    host_ms = (time.perf_counter() - t0) * 1e3
+    dt = ngl.DeviceOctree(torch.from_numpy(ijk.astype(np.int32)).to(dev), 7)
+    tm = Timer()
+    for _ in range(steps):
+        with tm:
+            dt.rebuild()
+    torch.cuda.synchronize()
+    ms = float(np.median(tm.values()))
+    return {"cells": int(len(ijk)), "lods": 7, "voxels": int(dt.nvox.sum()), "corners": int(dt.ncorner.sum()),
+            "device_ms": ms, "host_ms": host_ms, "cells_per_s": len(ijk) / (ms * 1e-3)}
 
 
 def run_batch(dev, steps, warmup):

@@ -124,6 +124,35 @@ typedef struct {
 /* Fill the canonical layout (same inputs as ngl_octree_plan). */
 int ngl_octree_fill(const int32_t* ijk, int64_t n, int32_t num_lods, const ngl_octree_host* out);
 
+/* The same build on the device, bit for bit the arrays of ngl_octree_fill,
+ * without host synchronisation: ijk is device int32 [n][3]; the arrays are
+ * device buffers allocated to upper bounds (depth d: min(n, 8^d) voxels,
+ * at least 1; level l: 8 * (voxels of depth l+1) corner slots, corners and
+ * adjacency entries, corner_adj_off one more); the actual sizes are written
+ * to nvox (device [num_lods+2]) and ncorner (device [num_lods]), and the
+ * number of cells outside [0, 2^(num_lods+1))^3 (which are skipped) to
+ * *bad (device).  cell/parent are required at every depth, child_mask and
+ * first_child at depths 0..num_lods (optional at num_lods+1: mask 0, first
+ * child -1), corners at every level; corner_cell and the adjacency pair are
+ * optional.  n < 2^28.  ws: device bytes from
+ * ngl_octree_build_device_workspace(n, num_lods). */
+typedef struct {
+  uint32_t* cell[NGL_MAX_DEPTH];
+  uint8_t* child_mask[NGL_MAX_DEPTH];
+  int32_t* first_child[NGL_MAX_DEPTH];
+  int32_t* parent[NGL_MAX_DEPTH];
+  int32_t* corners[NGL_MAX_LODS];
+  int32_t* corner_cell[NGL_MAX_LODS];
+  int32_t* corner_adj_off[NGL_MAX_LODS];
+  int32_t* corner_adj[NGL_MAX_LODS];
+  int64_t* nvox;    /* device [num_lods + 2] */
+  int64_t* ncorner; /* device [num_lods] */
+  int64_t* bad;     /* device [1] */
+} ngl_octree_device;
+int ngl_octree_build_device_workspace(int64_t n, int32_t num_lods, size_t* bytes);
+int ngl_octree_build_device(const int32_t* ijk, int64_t n, int32_t num_lods, const ngl_octree_device* out,
+                            void* ws, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------ */
 /* Device view of a model: octree + corner features + per-LOD decoders.  */
 /* ------------------------------------------------------------------ */

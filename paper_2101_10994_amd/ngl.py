@@ -84,6 +84,8 @@ EXPORTS = {
     "ngl_get_option": (C.c_int, [C.c_int, P]),
     "ngl_octree_plan": (C.c_int, [P, i64, i32, P, P]),
     "ngl_octree_fill": (C.c_int, [P, i64, i32, P]),
+    "ngl_octree_build_device_workspace": (C.c_int, [i64, i32, P]),
+    "ngl_octree_build_device": (C.c_int, [P, i64, i32, P, P, C.c_size_t, P]),
     "ngl_query_sdf": (C.c_int, [P, P, i64, i32, C.c_float, P, P, P, P, P]),
     "ngl_query_sdf_all_lods": (C.c_int, [P, P, i64, P, P]),
     "ngl_decode_sdf": (C.c_int, [P, i32, P, P, i32, i64, P, P]),
@@ -232,6 +234,79 @@ class Octree:
 
     def corner_positions(self) -> List[np.ndarray]:
         return [-1.0 + self.corner_cell[lv].astype(np.float64) * (2.0 / 2 ** (lv + 2))
+                for lv in range(self.num_lods)]
+
+
+class ngl_octree_device(C.Structure):
+    _fields_ = [("cell", P * MAX_DEPTH), ("child_mask", P * MAX_DEPTH), ("first_child", P * MAX_DEPTH),
+                ("parent", P * MAX_DEPTH), ("corners", P * MAX_LODS), ("corner_cell", P * MAX_LODS),
+                ("corner_adj_off", P * MAX_LODS), ("corner_adj", P * MAX_LODS), ("nvox", P), ("ncorner", P),
+                ("bad", P)]
+
+
+class DeviceOctree:
+    """The canonical octree built on the device (ngl_octree_build_device),
+    with the attributes a Model reads; device arrays are trimmed views of
+    upper-bound allocations (one synchronisation reads the sizes)."""
+
+    def __init__(self, ijk: torch.Tensor, num_lods: int):
+        if ijk.dtype != torch.int32 or not ijk.is_cuda:
+            raise NGLError("ijk must be an int32 device tensor [n][3]")
+        ijk = ijk.reshape(-1, 3).contiguous()
+        n = ijk.shape[0]
+        dev = ijk.device
+        self.num_lods = L = int(num_lods)
+        self.depth = D = L + 1
+        nb = C.c_size_t()
+        _check(lib().ngl_octree_build_device_workspace(n, L, C.addressof(nb)))
+        ws = torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=dev)
+        cap = [max(1, min(n, 8 ** d)) for d in range(D + 1)]
+        e32 = lambda k: torch.empty(k, dtype=torch.int32, device=dev)
+        self.d_cell = [e32(cap[d]) for d in range(D + 1)]
+        self.d_child_mask = [torch.empty(cap[d], dtype=torch.uint8, device=dev) for d in range(D + 1)]
+        self.d_first_child = [e32(cap[d]) for d in range(D + 1)]
+        self.d_parent = [e32(cap[d]) for d in range(D + 1)]
+        self.d_corners = [e32(8 * cap[lv + 1]) for lv in range(1, D)]
+        self.d_corner_cell = [e32(3 * 8 * cap[lv + 1]) for lv in range(1, D)]
+        self.d_corner_adj_off = [e32(8 * cap[lv + 1] + 1) for lv in range(1, D)]
+        self.d_corner_adj = [e32(8 * cap[lv + 1]) for lv in range(1, D)]
+        counts = torch.zeros(MAX_DEPTH + MAX_LODS + 1, dtype=torch.int64, device=dev)
+        o = ngl_octree_device()
+        for d in range(D + 1):
+            o.cell[d], o.child_mask[d] = _ptr(self.d_cell[d]), _ptr(self.d_child_mask[d])
+            o.first_child[d], o.parent[d] = _ptr(self.d_first_child[d]), _ptr(self.d_parent[d])
+        for lv in range(L):
+            o.corners[lv], o.corner_cell[lv] = _ptr(self.d_corners[lv]), _ptr(self.d_corner_cell[lv])
+            o.corner_adj_off[lv], o.corner_adj[lv] = _ptr(self.d_corner_adj_off[lv]), _ptr(self.d_corner_adj[lv])
+        base = counts.data_ptr()
+        o.nvox, o.ncorner, o.bad = base, base + 8 * MAX_DEPTH, base + 8 * (MAX_DEPTH + MAX_LODS)
+        self._keep = (ijk, ws, counts, o)
+        self.rebuild()
+        c = counts.cpu().numpy()
+        if c[MAX_DEPTH + MAX_LODS] > 0:
+            raise NGLError("%d cells outside [0, %d)^3" % (int(c[MAX_DEPTH + MAX_LODS]), 1 << D))
+        self.nvox = c[: D + 1].copy()
+        self.ncorner = c[MAX_DEPTH: MAX_DEPTH + L].copy()
+        nv, nc = self.nvox, self.ncorner
+        self.d_cell = [t[: int(nv[d])] for d, t in enumerate(self.d_cell)]
+        self.d_child_mask = [t[: int(nv[d])] for d, t in enumerate(self.d_child_mask)]
+        self.d_first_child = [t[: int(nv[d])] for d, t in enumerate(self.d_first_child)]
+        self.d_parent = [t[: int(nv[d])] for d, t in enumerate(self.d_parent)]
+        self.d_corners = [t[: 8 * int(nv[lv + 2])].view(-1, 8) for lv, t in enumerate(self.d_corners)]
+        self.d_corner_cell = [t[: 3 * int(nc[lv])].view(-1, 3) for lv, t in enumerate(self.d_corner_cell)]
+        self.d_corner_adj_off = [t[: int(nc[lv]) + 1] for lv, t in enumerate(self.d_corner_adj_off)]
+        self.d_corner_adj = [t[: 8 * int(nv[lv + 2])] for lv, t in enumerate(self.d_corner_adj)]
+        self.device = dev
+
+    def rebuild(self):
+        """Enqueue the build again into the same buffers (no allocation, no
+        synchronisation): for timing."""
+        ijk, ws, counts, o = self._keep
+        _check(lib().ngl_octree_build_device(_ptr(ijk), ijk.shape[0], self.num_lods, C.addressof(o), _ptr(ws),
+                                             ws.numel(), _stream()))
+
+    def corner_positions(self) -> List[np.ndarray]:
+        return [-1.0 + self.d_corner_cell[lv].cpu().numpy().astype(np.float64) * (2.0 / 2 ** (lv + 2))
                 for lv in range(self.num_lods)]
 
 

@@ -1,0 +1,75 @@
+"""The octree built on the device (Sec. 3.2; App. A.1) equals the host
+build array for array, bit for bit (the host build is itself checked
+against the oracle's independent build), for the tiny, paper-scale and
+7-LOD occupancies, shuffled input with duplicates, a single cell and no
+cells; out-of-range cells are reported."""
+import numpy as np
+import pytest
+
+from paper_2101_10994_amd import workloads as W
+
+from cases import tiny_case
+
+pytestmark = pytest.mark.gpu
+
+
+def compare(ijk, L):
+    import torch
+    from paper_2101_10994_amd import ngl
+    host = ngl.Octree(ijk, L, device=None)
+    dev = ngl.DeviceOctree(torch.from_numpy(np.ascontiguousarray(ijk, dtype=np.int32)).cuda(), L)
+    np.testing.assert_array_equal(dev.nvox, host.nvox)
+    np.testing.assert_array_equal(dev.ncorner, host.ncorner)
+    D = L + 1
+    for d in range(D + 1):
+        np.testing.assert_array_equal(dev.d_cell[d].cpu().numpy().view(np.uint32), host.cell[d])
+        np.testing.assert_array_equal(dev.d_parent[d].cpu().numpy(), host.parent[d])
+        np.testing.assert_array_equal(dev.d_child_mask[d].cpu().numpy(), host.child_mask[d])
+        np.testing.assert_array_equal(dev.d_first_child[d].cpu().numpy(), host.first_child[d])
+    for lv in range(L):
+        np.testing.assert_array_equal(dev.d_corners[lv].cpu().numpy(), host.corners[lv])
+        np.testing.assert_array_equal(dev.d_corner_cell[lv].cpu().numpy(), host.corner_cell[lv])
+        np.testing.assert_array_equal(dev.d_corner_adj_off[lv].cpu().numpy(), host.corner_adj_off[lv])
+        np.testing.assert_array_equal(dev.d_corner_adj[lv].cpu().numpy(), host.corner_adj[lv])
+    return host, dev
+
+
+@pytest.mark.parametrize("which", ["tiny", "paper", "prec"])
+def test_shapes(which):
+    shape, res, L = {"tiny": (W.tiny_shape(), 16, 3), "paper": (W.paper_shape(0), 64, 5),
+                     "prec": (W.prec_shape(0), 256, 7)}[which]
+    compare(W.occupancy_ijk(shape, res), L)
+
+
+def test_shuffled_duplicates_single_and_empty():
+    rng = np.random.default_rng(0)
+    ijk = W.occupancy_ijk(W.paper_shape(1), 32)
+    dup = np.concatenate([ijk, ijk[rng.integers(0, len(ijk), 5000)]])
+    compare(dup[rng.permutation(len(dup))], 4)
+    compare(np.array([[5, 0, 31]], np.int32), 4)
+    compare(np.array([[0, 0, 0], [31, 31, 31]], np.int32), 4)
+    compare(np.zeros((0, 3), np.int32), 3)
+
+
+def test_out_of_range_is_reported():
+    import torch
+    from paper_2101_10994_amd import ngl
+    bad = torch.tensor([[0, 0, 0], [16, 0, 0]], dtype=torch.int32, device="cuda")
+    with pytest.raises(ngl.NGLError):
+        ngl.DeviceOctree(bad, 3)
+    neg = torch.tensor([[0, -1, 0]], dtype=torch.int32, device="cuda")
+    with pytest.raises(ngl.NGLError):
+        ngl.DeviceOctree(neg, 3)
+
+
+def test_model_on_device_octree_queries_bitwise():
+    import torch
+    from paper_2101_10994_amd import ngl
+    case = tiny_case(sigma=0.1)
+    gm = case.gpu_model()
+    dt = ngl.DeviceOctree(torch.from_numpy(case.ijk.astype(np.int32)).cuda(), case.L)
+    gm2 = ngl.Model(dt, gm.feats, gm.W1, gm.b1, gm.w2, gm.b2, with_xyz=case.with_xyz)
+    x = torch.from_numpy(W.soa(W.points_in_cells(np.random.default_rng(1), case.ijk, 16, 5000))).cuda()
+    a = ngl.query_sdf(gm, x, 3, want_vox=True)
+    b = ngl.query_sdf(gm2, x, 3, want_vox=True)
+    assert torch.equal(a["sdf"], b["sdf"]) and torch.equal(a["vox"], b["vox"])
