@@ -188,7 +188,7 @@ __global__ __launch_bounds__(64 * NW) void k_decode_lds(ngl_model md, DecodeArgs
     if constexpr (MFMA) {
       DEC::stage(S.stage, x, z);
       wave_lds_sync();
-      out = DEC::decode(S.frag0, S.w2s0, b2, S.stage, H);
+      out = DEC::decode(S.frag0, S.w2s0, b2, S.stage, H, __ballot(in));
       wave_lds_sync();
     } else {
       out = decode_f32<M, XYZ>(md, A.lod, x, z);

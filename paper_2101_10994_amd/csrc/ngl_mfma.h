@@ -150,14 +150,18 @@ __device__ inline void stage_row(uint16_t* stage, const float x[3], const float*
 
 // First layer on the matrix cores, second layer and reduction in FP32: the
 // decoder output for this lane's staged point (all 64 lanes must call it).
+// `live` (wave-uniform) marks the lanes whose output is used: a 16-lane
+// point tile without any is skipped (its lanes get b2).
 template <int M, bool XYZ>
-__device__ inline float wave_decode(const uint4* frag, const float* w2s, float b2, const uint16_t* stage, int H) {
+__device__ inline float wave_decode(const uint4* frag, const float* w2s, float b2, const uint16_t* stage, int H,
+                                    uint64_t live) {
   using S = MfmaShape<M, XYZ>;
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, j = lane & 15;
   float mine = 0.0f;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
+    if (((live >> (16 * t)) & 0xffffull) == 0) continue;
     bf16x8 b[S::KS];
 #pragma unroll
     for (int s = 0; s < S::KS; ++s)
@@ -233,13 +237,15 @@ __device__ inline void stage_row32(float* stage, const float x[3], const float* 
 }
 
 template <int M, bool XYZ>
-__device__ inline float wave_decode32(const float* frag, const float* w2s, float b2, const float* stage, int H) {
+__device__ inline float wave_decode32(const float* frag, const float* w2s, float b2, const float* stage, int H,
+                                      uint64_t live) {
   using S = MfmaShape32<M, XYZ>;
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, j = lane & 15;
   float mine = 0.0f;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
+    if (((live >> (16 * t)) & 0xffffull) == 0) continue;
     float b[S::KS];
 #pragma unroll
     for (int s = 0; s < S::KS; ++s) b[s] = stage[(16 * t + j) * S::ROW + 4 * s + g];
@@ -273,8 +279,9 @@ struct DecBF16 {
   static constexpr int frag_bytes(int H) { return MfmaShape<M, XYZ>::frag_bytes(H); }
   __device__ static void load(const ngl_model& md, int L, Frag* f, float* w2s) { load_frags<M, XYZ>(md, L, f, w2s); }
   __device__ static void stage(Stage* st, const float x[3], const float* z) { stage_row<M, XYZ>(st, x, z); }
-  __device__ static float decode(const Frag* f, const float* w2s, float b2, const Stage* st, int H) {
-    return wave_decode<M, XYZ>(f, w2s, b2, st, H);
+  __device__ static float decode(const Frag* f, const float* w2s, float b2, const Stage* st, int H,
+                                 uint64_t live = ~0ull) {
+    return wave_decode<M, XYZ>(f, w2s, b2, st, H, live);
   }
 };
 
@@ -288,8 +295,9 @@ struct DecF32 {
   static constexpr int frag_bytes(int H) { return MfmaShape32<M, XYZ>::frag_bytes(H); }
   __device__ static void load(const ngl_model& md, int L, Frag* f, float* w2s) { load_frags32<M, XYZ>(md, L, f, w2s); }
   __device__ static void stage(Stage* st, const float x[3], const float* z) { stage_row32<M, XYZ>(st, x, z); }
-  __device__ static float decode(const Frag* f, const float* w2s, float b2, const Stage* st, int H) {
-    return wave_decode32<M, XYZ>(f, w2s, b2, st, H);
+  __device__ static float decode(const Frag* f, const float* w2s, float b2, const Stage* st, int H,
+                                 uint64_t live = ~0ull) {
+    return wave_decode32<M, XYZ>(f, w2s, b2, st, H, live);
   }
 };
 

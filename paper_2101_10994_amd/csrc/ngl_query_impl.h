@@ -138,14 +138,14 @@ __global__ __launch_bounds__(64 * NW) void k_query_mfma(ngl_model md, const floa
         interp_level<M, FT>(md, l, vox[l - 1], cx >> (Lp - l), cy >> (Lp - l), cz >> (Lp - l), x, z);
     DEC::stage(S.stage, x, z);
     wave_lds_sync();
-    float out = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H);
+    float out = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H, __ballot(act));
     if (blend) {
       if (vn >= 0) interp_level<M, FT>(md, lod + 1, vn, cx, cy, cz, x, z);
       wave_lds_sync();
       DEC::stage(S.stage, x, z);
       wave_lds_sync();
       const float a = act ? (alpha_pp ? alpha_pp[p] : alpha) : 0.0f;
-      out = (1.0f - a) * out + a * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H);
+      out = (1.0f - a) * out + a * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H, __ballot(act));
     }
     wave_lds_sync();
     if (act) {
@@ -262,12 +262,12 @@ __global__ __launch_bounds__(64 * NW) void k_normals(ngl_model md, NormalArgs A)
       if constexpr (MFMA) {
         DEC::stage(S.stage, x, z);
         wave_lds_sync();
-        f = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H);
+        f = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H, __ballot(act));
         if (blend) {
           wave_lds_sync();
           DEC::stage(S.stage, x, zn);
           wave_lds_sync();
-          f = (1.0f - A.alpha) * f + A.alpha * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H);
+          f = (1.0f - A.alpha) * f + A.alpha * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H, __ballot(act));
         }
         wave_lds_sync();
       } else {

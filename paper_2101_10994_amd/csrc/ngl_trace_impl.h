@@ -219,14 +219,17 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
         if constexpr (MFMA) {
           DEC::stage(S.stage, x, z);
           wave_lds_sync();
-          dist = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H);
+          // point tiles without an evaluating lane are skipped (the tail of
+          // the queue runs waves with few live rays)
+          dist = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H, __ballot(ok));
           const bool mix = ok && al > 0.0f;  // Eq. 3 blend with the level lod+1 voxel
-          if (blend && __ballot(mix)) {
+          const uint64_t mixing = __ballot(mix);
+          if (blend && mixing) {
             if (mix) interp_level<M, FT>(md, lod + 1, vox[lod], cell_x(cell[lod]), cell_y(cell[lod]), cell_z(cell[lod]), x, z);
             wave_lds_sync();
             DEC::stage(S.stage, x, z);
             wave_lds_sync();
-            const float d1 = DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H);
+            const float d1 = DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H, mixing);
             if (mix) dist = (1.0f - al) * dist + al * d1;
           }
           wave_lds_sync();
