@@ -10,8 +10,8 @@
 
 namespace ngl {
 
-static int trace_by_width(const ngl_model& m, const TraceArgs& A, hipStream_t s) {
-  NGL_BY_WIDTH(m.feat_dim, trace_run, m, A, s)
+static int buckets_by_width(const ngl_model& m, const BucketArgs& B, hipStream_t s) {
+  NGL_BY_WIDTH(m.feat_dim, bucket_run, m, B, s)
 }
 
 // Workspace of the per-ray LOD trace: [3][NGL_MAX_LODS] counters (group
@@ -165,18 +165,17 @@ int ngl_sphere_trace_lod(const ngl_model* m, const float* o, const float* d, int
   NGL_LAUNCHED();
   const int first = std::max(1, int(std::floor(lmin)));
   const int last = std::min(L, int(std::floor(lmax)));
-  for (int lod = first; lod <= last; ++lod) {
-    TraceArgs A{o, d, R, 0, R, lod, 0.0f, pair_vox, t_in, t_out, ray_off, *params, t_hit, status, steps, hit_vox,
-                W.counts + 2 * NGL_MAX_LODS + (lod - 1), nullptr, nullptr};
-    A.pair_depth = pair_depth;
-    A.ray_ids = W.ids;
-    A.bucket_counts = W.counts;
-    A.bucket = lod - 1;
-    A.alpha_pp = lod < L ? W.alpha : nullptr;
-    rc = trace_by_width(*m, A, s);
-    if (rc) return rc;
-  }
-  return NGL_OK;
+  BucketArgs B{};
+  B.base = TraceArgs{o, d, R, 0, R, first, 0.0f, pair_vox, t_in, t_out, ray_off, *params, t_hit, status, steps,
+                     hit_vox, nullptr, nullptr, nullptr};
+  B.base.pair_depth = pair_depth;
+  B.base.ray_ids = W.ids;
+  B.base.bucket_counts = W.counts;
+  B.base.alpha_pp = W.alpha;
+  B.first = first;
+  B.n = last - first + 1;
+  B.heads = W.counts + 2 * NGL_MAX_LODS;  // zeroed by k_lod_init
+  return buckets_by_width(*m, B, s);
 }
 
 int ngl_model_table_bytes(int32_t n, size_t* bytes) {

@@ -373,6 +373,53 @@ __global__ __launch_bounds__(64 * NW) void k_trace_batch(BatchArgs B) {
   }
 }
 
+// Per-pixel LOD groups in one launch: group b holds the rays of integer
+// LOD first + b (ids grouped on the device, sizes in counts[first - 1 + b]).
+// Each block visits the groups once, in rotation from its own start,
+// stages that LOD's two decoders and serves the group's queue, so the
+// groups' tails overlap instead of running one launch after another.
+struct BucketArgs {
+  TraceArgs base;  // rays, hit lists, outputs, pair depth, ids, counts, alpha_pp
+  int first;       // LOD of group 0
+  int n;           // groups
+  unsigned int* heads;  // [NGL_MAX_LODS] queue heads (zeroed)
+};
+
+template <int M, typename FT, bool XYZ, bool MFMA, int NW, class DEC>
+__global__ __launch_bounds__(64 * NW) void k_trace_buckets(ngl_model md, BucketArgs B) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int s_has;
+  const int H = md.hidden;
+  for (int step = 0; step < B.n; ++step) {
+    const int b = (int(blockIdx.x) + step) % B.n;
+    const int lod = B.first + b;
+    if (threadIdx.x == 0)
+      s_has = __atomic_load_n(&B.heads[lod - 1], __ATOMIC_RELAXED) < B.base.bucket_counts[lod - 1];
+    __syncthreads();
+    if (!s_has) {
+      __syncthreads();
+      continue;
+    }
+    TraceArgs A = B.base;
+    A.lod = lod;
+    A.bucket = lod - 1;
+    A.counter = B.heads + (lod - 1);
+    if (lod >= md.num_lods) A.alpha_pp = nullptr;  // the finest LOD does not blend
+    const bool blend = trace_blend(A);
+    DecLds<DEC> S(smem, H, blend && MFMA);
+    float b2a = 0.0f, b2b = 0.0f;
+    if constexpr (MFMA) {
+      DEC::load(md, lod, S.frag0, S.w2s0);
+      if (blend) DEC::load(md, lod + 1, S.frag1, S.w2s1);
+      __syncthreads();
+      b2a = md.b2[lod - 1];
+      b2b = blend ? md.b2[lod] : 0.0f;
+    }
+    serve_queue<M, FT, XYZ, false, MFMA, DEC>(md, A, S, b2a, b2b);
+    __syncthreads();  // every wavefront is done with this group's LDS
+  }
+}
+
 static __global__ void k_zero_counter(unsigned int* c) {
   if (threadIdx.x == 0) *c = 0u;
 }
@@ -481,6 +528,43 @@ static __global__ void k_batch_init(unsigned int* counters, unsigned int* live, 
   if (i == 0 && clock) clock[0] = wall_clock64();
 }
 
+template <int M, typename FT, bool XYZ, bool MFMA, int NW, class DEC>
+static int launch_buckets_nw(const ngl_model& md, const BucketArgs& B, hipStream_t s, size_t lds) {
+  static int per = 0, cus = 0;
+  if (!per) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    const void* kern = reinterpret_cast<const void*>(&k_trace_buckets<M, FT, XYZ, MFMA, NW, DEC>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
+  }
+  k_trace_buckets<M, FT, XYZ, MFMA, NW, DEC><<<cus * per, 64 * NW, lds, s>>>(md, B);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+// Wavefronts per block from the LDS the two staged decoders leave.
+template <int M, typename FT, bool XYZ, bool MFMA, class DEC>
+static int launch_buckets(const ngl_model& md, const BucketArgs& B, hipStream_t s) {
+  if constexpr (!MFMA) return launch_buckets_nw<M, FT, XYZ, false, 4, DEC>(md, B, s, 0);
+  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, true);
+  if (fixed + 4 * DEC::STAGE_BYTES <= 65536)
+    return launch_buckets_nw<M, FT, XYZ, MFMA, 4, DEC>(md, B, s, fixed + 4 * DEC::STAGE_BYTES);
+  if (fixed + 2 * DEC::STAGE_BYTES <= 65536)
+    return launch_buckets_nw<M, FT, XYZ, MFMA, 2, DEC>(md, B, s, fixed + 2 * DEC::STAGE_BYTES);
+  return launch_buckets_nw<M, FT, XYZ, MFMA, 1, DEC>(md, B, s, fixed + DEC::STAGE_BYTES);
+}
+
+template <int M, typename FT, bool XYZ>
+struct BucketOp {
+  static int run(const ngl_model& md, const BucketArgs& B, hipStream_t s) {
+    if (md.w_dtype == NGL_BF16) return launch_buckets<M, FT, XYZ, true, DecBF16<M, XYZ>>(md, B, s);
+    if (option(NGL_OPT_F32_DECODER) == 1) return launch_buckets<M, FT, XYZ, true, DecF32<M, XYZ>>(md, B, s);
+    return launch_buckets<M, FT, XYZ, false, DecF32<M, XYZ>>(md, B, s);
+  }
+};
+
 template <int M, typename FT, bool XYZ>
 struct TraceOp {
   static int run(const ngl_model& md, const TraceArgs& A, hipStream_t s) { return launch_trace<M, FT, XYZ, false>(md, A, s); }
@@ -489,7 +573,8 @@ struct TraceOp {
 // Per-width runners, defined in ngl_trace_m<width>.hip.
 #define NGL_TRACE_DECLARE(M_)                                                            \
   int trace_run_m##M_(const ngl_model& md, const TraceArgs& A, hipStream_t s);           \
-  int batch_run_m##M_(const ngl_model& md, const BatchArgs& B, bool any_blend, hipStream_t s);
+  int batch_run_m##M_(const ngl_model& md, const BatchArgs& B, bool any_blend, hipStream_t s); \
+  int bucket_run_m##M_(const ngl_model& md, const BucketArgs& B, hipStream_t s);
 NGL_TRACE_DECLARE(8)
 NGL_TRACE_DECLARE(16)
 NGL_TRACE_DECLARE(32)
@@ -503,6 +588,9 @@ int trace_run_analytic(const ngl_model& md, const TraceArgs& A, hipStream_t s);
   }                                                                                                 \
   int batch_run_m##M_(const ngl_model& md, const BatchArgs& B, bool any_blend, hipStream_t s) {     \
     return dispatch_ft<BatchOp, M_>(md, B, any_blend, s);                                           \
+  }                                                                                                 \
+  int bucket_run_m##M_(const ngl_model& md, const BucketArgs& B, hipStream_t s) {                   \
+    return dispatch_ft<BucketOp, M_>(md, B, s);                                                     \
   }
 
 }  // namespace ngl
