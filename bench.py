@@ -51,14 +51,14 @@ TRAVERSAL_BYTES = 16
 # WRITE_SIZE 262,144 KiB).  Valid only while the kernel's sources hash to
 # the recorded value; otherwise traffic is reported as null.
 COUNTERS = {
-    "k_sphere_trace": {"sources": ["ngl_trace.hip", "ngl_device.h", "ngl_mfma.h"],
-                       "sha256": "6f0aed9ffa81e08fb77a9f7c4567bd2b4535dff30590bc36ed21e1a87555a8ea",
-                       "fetch_kib": 643103.9, "write_kib": 40544.5},
-    "k_query": {"sources": ["ngl_query.hip", "ngl_device.h", "ngl_mfma.h"],
-                "sha256": "df9f1c2b5be0f28378f97e732e9dcc0176f1f6b1666d84b627e719d4e083baa8",
-                "fetch_kib": 114441.0, "write_kib": 4096.0},
+    "k_sphere_trace": {"sources": ["ngl_trace_impl.h", "ngl_device.h", "ngl_mfma.h"],
+                       "sha256": "469521fca17ca6aec025420e4d9b87bb54a976f809605de3f94a2d0fbe991d69",
+                       "fetch_kib": 642903.8, "write_kib": 40498.4},
+    "k_query": {"sources": ["ngl_query_impl.h", "ngl_device.h", "ngl_mfma.h"],
+                "sha256": "c9b3cf5d23a0efc536a8a7e77f3ec05c5cad52739657c2573f4d5c85a4dc3a14",
+                "fetch_kib": 114554.2, "write_kib": 4096.0},
 }
-FETCH_SCALE = (256 << 10) / 131088.125
+FETCH_SCALE = (256 << 10) / 131087.8125
 WRITE_SCALE = (256 << 10) / 262144.0
 
 
@@ -150,6 +150,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="approximate CPU-baseline budget")
     ap.add_argument("--no-batch", action="store_true", help="skip the 16-shape batched render")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the decoder-alone, LOD-selection, fitting and octree-build components")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, run one plain 256 MiB device copy (counter calibration)")
     ap.add_argument("--only", choices=["query", "frame", "train", "half"], default=None,
@@ -367,7 +369,7 @@ def main():
         del src, dst
     if args.only is None and not args.no_batch:
         comp["batch"] = run_batch(dev, args.steps, args.warmup)
-    if args.only is None:
+    if args.only is None and not args.no_extras:
         comp["decoder_bf16"] = run_decoder(S, dev, args.steps, args.warmup)
         comp["frame_lod_select"] = run_lod_select(model, cfg, o, d, buf, args.steps, args.warmup)
         comp["fit"] = run_fit(S, dev)
