@@ -154,7 +154,7 @@ def main():
                     help="skip the decoder-alone, LOD-selection, fitting and octree-build components")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, run one plain 256 MiB device copy (counter calibration)")
-    ap.add_argument("--only", choices=["query", "frame", "train", "half"], default=None,
+    ap.add_argument("--only", choices=["query", "frame", "train", "half", "decoder"], default=None,
                     help="run a single component (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -369,8 +369,9 @@ def main():
         del src, dst
     if args.only is None and not args.no_batch:
         comp["batch"] = run_batch(dev, args.steps, args.warmup)
-    if args.only is None and not args.no_extras:
+    if args.only == "decoder" or (args.only is None and not args.no_extras):
         comp["decoder_bf16"] = run_decoder(S, dev, args.steps, args.warmup)
+    if args.only is None and not args.no_extras:
         comp["frame_lod_select"] = run_lod_select(model, cfg, o, d, buf, args.steps, args.warmup)
         comp["fit"] = run_fit(S, dev)
         comp["octree_build"] = run_octree_build(dev, args.steps)
