@@ -267,16 +267,18 @@ int ngl_octree_build_device(const int32_t* ijk, int64_t n, int32_t num_lods, con
     k_oct_cells<<<g1, kBlock, 0, s>>>(w.code[d], out->nvox + d, n, d < D ? out->first_child[d] : nullptr,
                                       d < D ? w.code[d + 1] : nullptr, d < D ? out->nvox + d + 1 : nullptr,
                                       out->cell[d], out->child_mask[d], d < D ? nullptr : out->first_child[d]);
-  // 3. corners per level
-  const unsigned g8 = unsigned((8 * nn + kBlock - 1) / kBlock);
+  // 3. corners per level; depth l+1 holds at most min(n, 8^(l+1)) voxels
   for (int l = 1; l <= L; ++l) {
-    // all 8 * nn entries are written (sentinels past the level's voxels)
-    k_oct_corner_keys<<<g8, kBlock, 0, s>>>(w.code[l + 1], out->nvox + l + 1, nn, w.key[0], w.val[0]);
+    const int64_t nl = (l + 1) * 3 < 62 ? std::min<int64_t>(nn, int64_t(1) << (3 * (l + 1))) : nn;
+    const int64_t m = 8 * nl;
+    const unsigned g8 = unsigned((m + kBlock - 1) / kBlock);
+    // all m entries are written (sentinels past the level's voxels)
+    k_oct_corner_keys<<<g8, kBlock, 0, s>>>(w.code[l + 1], out->nvox + l + 1, nl, w.key[0], w.val[0]);
     const int bits = 3 * (l + 2);
-    const int c = radix_sort_pairs(w.key, w.val, 8 * nn, bits <= 32 ? bits : 32, sort_grid_for(8 * nn), w.hist, s);
-    k_oct_flags<<<g8, kBlock, 0, s>>>(w.key[c], 8 * nn, nullptr, 0, 0xffffffffu, w.flag, w.pos);
-    k_scan_inplace<<<1, 1024, 0, s>>>(w.pos, 8 * nn, w.cnt32);
-    k_oct_corner_out<<<g8, kBlock, 0, s>>>(w.key[c], w.val[c], 8 * nn, out->nvox + l + 1, w.pos, w.flag, w.cnt32,
+    const int c = radix_sort_pairs(w.key, w.val, m, bits <= 32 ? bits : 32, sort_grid_for(m), w.hist, s);
+    k_oct_flags<<<g8, kBlock, 0, s>>>(w.key[c], m, nullptr, 0, 0xffffffffu, w.flag, w.pos);
+    k_scan_inplace<<<1, 1024, 0, s>>>(w.pos, m, w.cnt32);
+    k_oct_corner_out<<<g8, kBlock, 0, s>>>(w.key[c], w.val[c], m, out->nvox + l + 1, w.pos, w.flag, w.cnt32,
                                            out->corners[l - 1], out->corner_cell[l - 1], out->corner_adj_off[l - 1],
                                            out->corner_adj[l - 1], out->ncorner + l - 1);
   }
