@@ -81,12 +81,21 @@ int ngl_version(void);
  *    (1, 2 or 4; 0 = the most that fit in 64 KB of LDS, default).
  *  NGL_OPT_TRACE_BLOCKS_PER_CU: cap on resident tracer blocks per compute
  *    unit (0 = occupancy limit, default).
+ *  NGL_OPT_TRACE_PAUSE1, NGL_OPT_TRACE_PAUSE2: evaluation counts at which
+ *    a phased ngl_sphere_trace parks the rays still running (0..4096, 0 =
+ *    no such phase; a second count not above the first is ignored).
+ *  NGL_OPT_TRACE_WIDE: 1 (default) = the last phase of a phased trace
+ *    serves each ray with a group of lanes (matrix-core decoders only),
+ *    0 = one lane per ray throughout.
  * NGL_E_INVALID for an unknown option or value. */
 typedef enum {
   NGL_OPT_F32_DECODER = 0,
   NGL_OPT_TRACE_WAVES = 1,
   NGL_OPT_TRACE_BLOCKS_PER_CU = 2,
-  NGL_OPT_COUNT = 3
+  NGL_OPT_TRACE_PAUSE1 = 3,
+  NGL_OPT_TRACE_PAUSE2 = 4,
+  NGL_OPT_TRACE_WIDE = 5,
+  NGL_OPT_COUNT = 6
 } ngl_option;
 int ngl_set_option(int option, int value);
 int ngl_get_option(int option, int* value);
@@ -310,6 +319,14 @@ int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t
  * cleared by the call itself).  Calls that share a workspace must not run
  * concurrently. */
 int ngl_sphere_trace_workspace(size_t* bytes);
+/* Workspace that lets ngl_sphere_trace run in phases (about 24*R + 256
+ * bytes): rays still running after NGL_OPT_TRACE_PAUSE1 (then
+ * NGL_OPT_TRACE_PAUSE2) evaluations are parked with their state and served
+ * again by the next launch from a dense queue, so the long grazing rays do
+ * not keep near-empty wavefronts busy.  Results are the same bits as the
+ * single launch (every ray takes the same steps from the same state).  A
+ * workspace below this size runs the single launch. */
+int ngl_sphere_trace_workspace_rays(int64_t R, size_t* bytes);
 
 /* Per-pixel LOD selection (Sec. 3.4, LOD Selection): the continuous LOD of
  * a ray moves linearly from lod_near at distance d_near to lod_far at

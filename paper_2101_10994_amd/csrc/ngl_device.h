@@ -202,27 +202,98 @@ __device__ inline void box_of(uint32_t c, int depth, float lo[3], float hi[3]) {
 // ---------------------------------------------------------------------------
 // acc[k] += sum_j w_j(u) Z[corner(v, j)][k], u = local position of x in
 // the cell (clamped to [0,1]).
-template <int M, typename FT>
-__device__ inline void interp_level(const ngl_model& md, int lvl, int v, int cx, int cy, int cz, const float x[3],
-                                    float* acc) {
+// Local position of x in cell (cx, cy, cz) of level lvl, clamped to [0,1].
+__device__ inline void cell_local(int lvl, int cx, int cy, int cz, const float x[3], float u[3]) {
   const int r = 4 << (lvl - 1);
   const float step = 2.0f / float(r);
   const float half_r = 0.5f * float(r);
-  float u[3];
   const int ci[3] = {cx, cy, cz};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float lo = -1.0f + float(ci[a]) * step;
     u[a] = fminf(fmaxf((x[a] - lo) * half_r, 0.0f), 1.0f);
   }
+}
+
+// Trilinear weight of corner j (bit 0: +x, bit 1: +y, bit 2: +z).
+__device__ inline float corner_weight(const float u[3], int j) {
+  return ((j & 1) ? u[0] : 1.0f - u[0]) * ((j & 2) ? u[1] : 1.0f - u[1]) * ((j & 4) ? u[2] : 1.0f - u[2]);
+}
+
+template <int M, typename FT>
+__device__ inline void interp_level(const ngl_model& md, int lvl, int v, int cx, int cy, int cz, const float x[3],
+                                    float* acc) {
+  float u[3];
+  cell_local(lvl, cx, cy, cz, x, u);
   const int4* cp = reinterpret_cast<const int4*>(md.corners[lvl - 1] + size_t(v) * 8);
   const int4 c0 = cp[0], c1 = cp[1];
   const int cs[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const float w = ((j & 1) ? u[0] : 1.0f - u[0]) * ((j & 2) ? u[1] : 1.0f - u[1]) * ((j & 4) ? u[2] : 1.0f - u[2]);
-    axpy_row<M, FT>(md.feat[lvl - 1], cs[j], w, acc);
+  for (int j = 0; j < 8; ++j) axpy_row<M, FT>(md.feat[lvl - 1], cs[j], corner_weight(u, j), acc);
+}
+
+// acc[i] += w * row[off + i], i < D: a D-wide slice of row `c`.
+template <int M, typename FT, int D>
+__device__ inline void axpy_slice(const void* base, int c, int off, float w, float* acc) {
+  if constexpr (std::is_same<FT, F32>::value) {
+    const float* r = static_cast<const float*>(base) + size_t(c) * M + off;
+    float v[D];
+    if constexpr (D % 4 == 0) {
+#pragma unroll
+      for (int q = 0; q < D / 4; ++q) {
+        const float4 f = reinterpret_cast<const float4*>(r)[q];
+        v[4 * q] = f.x, v[4 * q + 1] = f.y, v[4 * q + 2] = f.z, v[4 * q + 3] = f.w;
+      }
+    } else if constexpr (D == 2) {
+      const float2 f = *reinterpret_cast<const float2*>(r);
+      v[0] = f.x, v[1] = f.y;
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i) v[i] = r[i];
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) acc[i] = fmaf(w, v[i], acc[i]);
+  } else {
+    const uint16_t* r = static_cast<const uint16_t*>(base) + size_t(c) * M + off;
+    uint16_t h[D];
+    if constexpr (D % 8 == 0) {
+#pragma unroll
+      for (int q = 0; q < D / 8; ++q) {
+        const uint4 f = reinterpret_cast<const uint4*>(r)[q];
+        const uint32_t wv[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) h[8 * q + 2 * e] = uint16_t(wv[e] & 0xffffu), h[8 * q + 2 * e + 1] = uint16_t(wv[e] >> 16);
+      }
+    } else if constexpr (D == 4) {
+      const uint2 f = *reinterpret_cast<const uint2*>(r);
+      h[0] = uint16_t(f.x & 0xffffu), h[1] = uint16_t(f.x >> 16), h[2] = uint16_t(f.y & 0xffffu), h[3] = uint16_t(f.y >> 16);
+    } else if constexpr (D == 2) {
+      const uint32_t f = *reinterpret_cast<const uint32_t*>(r);
+      h[0] = uint16_t(f & 0xffffu), h[1] = uint16_t(f >> 16);
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i) h[i] = r[i];
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const float f = std::is_same<FT, BF16>::value ? bf16_to_f32(h[i]) : f16_to_f32(h[i]);
+      acc[i] = fmaf(w, f, acc[i]);
+    }
   }
+}
+
+// The slice [off, off + D) of interp_level's accumulation, with the same
+// weights and the same order of operations for every feature element.
+template <int M, typename FT, int D>
+__device__ inline void interp_level_slice(const ngl_model& md, int lvl, int v, int cx, int cy, int cz,
+                                          const float x[3], int off, float* acc) {
+  float u[3];
+  cell_local(lvl, cx, cy, cz, x, u);
+  const int4* cp = reinterpret_cast<const int4*>(md.corners[lvl - 1] + size_t(v) * 8);
+  const int4 c0 = cp[0], c1 = cp[1];
+  const int cs[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+#pragma unroll
+  for (int j = 0; j < 8; ++j) axpy_slice<M, FT, D>(md.feat[lvl - 1], cs[j], off, corner_weight(u, j), acc);
 }
 
 // ---------------------------------------------------------------------------

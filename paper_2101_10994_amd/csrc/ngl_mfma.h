@@ -317,7 +317,7 @@ struct DecLds {
     w2s1 = w2s0 + H;
     stage = reinterpret_cast<typename DEC::Stage*>(w2s1 + H) + (threadIdx.x >> 6) * DEC::STAGE_ELEMS;
   }
-  static size_t fixed_bytes(int H, bool blend) {
+  __host__ __device__ static size_t fixed_bytes(int H, bool blend) {
     return size_t(DEC::frag_bytes(H)) * (blend ? 2 : 1) + 2 * sizeof(float) * size_t(H);
   }
 };

@@ -10,6 +10,38 @@
 
 namespace ngl {
 
+static int trace_by_width(const ngl_model& m, const TraceArgs& A, hipStream_t s) {
+  NGL_BY_WIDTH(m.feat_dim, trace_run, m, A, s)
+}
+
+// Workspace of the phased trace: counters ([0..1] parked per phase, [4..6]
+// queue heads), parked state per ray and two ping-pong id lists.
+struct PhaseWS {
+  unsigned* counts;
+  float* st_t;
+  int32_t* st_p;
+  int32_t* st_k;
+  float* st_prev;
+  int32_t* ids[2];
+  static size_t align(size_t b) { return (b + 255) & ~size_t(255); }
+  static size_t bytes(int64_t R) { return 256 + 6 * align(4 * size_t(R)); }
+  PhaseWS(void* ws, int64_t R) {
+    char* p = static_cast<char*>(ws);
+    const size_t a = align(4 * size_t(R));
+    counts = reinterpret_cast<unsigned*>(p);
+    st_t = reinterpret_cast<float*>(p + 256);
+    st_p = reinterpret_cast<int32_t*>(p + 256 + a);
+    st_k = reinterpret_cast<int32_t*>(p + 256 + 2 * a);
+    st_prev = reinterpret_cast<float*>(p + 256 + 3 * a);
+    ids[0] = reinterpret_cast<int32_t*>(p + 256 + 4 * a);
+    ids[1] = reinterpret_cast<int32_t*>(p + 256 + 5 * a);
+  }
+};
+
+__global__ void k_phase_init(unsigned* c) {
+  if (threadIdx.x < 8) c[threadIdx.x] = 0u;
+}
+
 static int buckets_by_width(const ngl_model& m, const BucketArgs& B, hipStream_t s) {
   NGL_BY_WIDTH(m.feat_dim, bucket_run, m, B, s)
 }
@@ -121,7 +153,48 @@ int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t
   TraceArgs A{o, d, R, 0, R, int(lod), alpha, pair_vox, t_in, t_out, ray_off, *params, t_hit, status, steps,
               hit_vox, static_cast<unsigned int*>(ws), nullptr, nullptr};
   if (analytic) return trace_run_analytic(*m, A, s);
-  NGL_BY_WIDTH(m->feat_dim, trace_run, *m, A, s)
+  if (ws_bytes < PhaseWS::bytes(R)) return trace_by_width(*m, A, s);
+  // Phased: rays still running at the first pause count (then the second)
+  // are parked and served again from a dense queue, so the long grazing
+  // rays finish in full wavefronts instead of a tail of near-empty ones.
+  int pause[2], np = 0;
+  const int p1 = option(NGL_OPT_TRACE_PAUSE1), p2 = option(NGL_OPT_TRACE_PAUSE2);
+  if (p1 > 0 && p1 < params->max_steps) pause[np++] = p1;
+  if (p2 > (np ? p1 : 0) && p2 < params->max_steps) pause[np++] = p2;
+  if (np == 0) return trace_by_width(*m, A, s);
+  const int phases = np + 1;
+  PhaseWS W(ws, R);
+  k_phase_init<<<1, 64, 0, s>>>(W.counts);
+  NGL_LAUNCHED();
+  for (int ph = 0; ph < phases; ++ph) {
+    TraceArgs B = A;
+    B.counter = W.counts + 4 + ph;
+    B.pause_at = ph + 1 < phases ? pause[ph] : 0;
+    B.st_t = W.st_t;
+    B.st_p = W.st_p;
+    B.st_k = W.st_k;
+    B.st_prev = W.st_prev;
+    if (ph + 1 < phases) {
+      B.parked = W.ids[ph & 1];
+      B.parked_n = W.counts + ph;
+    }
+    B.wide = ph > 0 && ph + 1 == phases && option(NGL_OPT_TRACE_WIDE) == 1;
+    if (ph > 0) {
+      B.resume = true;
+      B.ray_ids = W.ids[(ph - 1) & 1];
+      B.bucket_counts = W.counts + (ph - 1);
+      B.bucket = 0;
+    }
+    rc = trace_by_width(*m, B, s);
+    if (rc) return rc;
+  }
+  return NGL_OK;
+}
+
+int ngl_sphere_trace_workspace_rays(int64_t R, size_t* bytes) {
+  NGL_REQUIRE(bytes != nullptr && R >= 0, "bad arguments");
+  *bytes = ngl::PhaseWS::bytes(R);
+  return NGL_OK;
 }
 
 int ngl_sphere_trace_lod_workspace(int64_t R, size_t* bytes) {

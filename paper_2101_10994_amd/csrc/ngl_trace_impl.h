@@ -35,6 +35,19 @@ struct TraceArgs {
   const unsigned int* bucket_counts;  // nullable: ray_ids is split into buckets of these sizes ...
   int bucket;                         // ... and this launch serves bucket `bucket`
   const float* alpha_pp;              // nullable: blend weight per ray (replaces alpha)
+  // Phased tracing (all zero/null otherwise): a ray about to take evaluation
+  // number pause_at is parked (state saved, id appended to `parked`) so the
+  // next launch can serve the long rays from a dense queue; `resume` starts
+  // each queued ray from its parked state.
+  int pause_at;
+  bool resume;
+  float* st_t;
+  int32_t* st_p;
+  int32_t* st_k;
+  float* st_prev;
+  int32_t* parked;
+  unsigned int* parked_n;
+  bool wide;  // host side: serve the queue with the wide (lanes-per-ray) kernel
 };
 
 // The launch evaluates decoders lod and lod+1.
@@ -67,6 +80,26 @@ __device__ inline void lod_of_distance(const ngl_lod_select& s, int num_lods, fl
   *Lc = L;
   *Li = li;
   *alpha = a;
+}
+
+// Voxels and cells of levels 1..Lp on the ancestor chain of pair voxel v
+// (level Lpair; parents always exist).  With `known`, vox and cell hold the
+// chain of an earlier pair of the same ray, and the walk stops at the first
+// ancestor already held: everything above it is the same.
+__device__ __forceinline__ void ancestor_chain(const ngl_model& md, int v, int Lpair, int Lp, bool known, int* vox,
+                                               uint32_t* cell) {
+  int w = v;
+#pragma unroll
+  for (int l = NGL_MAX_LODS; l >= 1; --l) {
+    if (l <= Lpair) {
+      if (l <= Lp) {
+        if (known && vox[l - 1] == w) break;
+        vox[l - 1] = w;
+        cell[l - 1] = md.cell[l + 1][w];
+      }
+      w = md.parent[l + 1][w];
+    }
+  }
 }
 
 // One wavefront serves a view's ray queue.  Each lane keeps one ray; a lane
@@ -145,6 +178,12 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
               dd[a] = A.d[a * A.stride + ray];
             }
             t = p < e ? A.t_in[p] : 0.0f;
+            if (A.resume) {
+              t = A.st_t[ray];
+              p = A.st_p[ray];
+              k = A.st_k[ray];
+              prev = A.st_prev[ray];
+            }
             bool bad = false;
 #pragma unroll
             for (int a = 0; a < 3; ++a) bad = bad || !__builtin_isfinite(oo[a]) || !__builtin_isfinite(dd[a]);
@@ -161,7 +200,17 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
           if (t < ti) t = ti;  // outside the voxel: jump to its entry
           if (t > A.prm.t_far) NGL_FINISH(NGL_RAY_FAR, -1);
           else if (k == A.prm.max_steps) NGL_FINISH(NGL_RAY_MAX_STEPS, -1);
-          else ready = true;
+          else if (A.pause_at > 0 && k == A.pause_at) {
+            // park: the state reproduces this point exactly on resumption
+            A.st_t[ray] = t;
+            A.st_p[ray] = p;
+            A.st_k[ray] = k;
+            A.st_prev[ray] = prev;
+            A.parked[atomicAdd(A.parked_n, 1u)] = ray;
+            ray = -1;
+          } else {
+            ready = true;
+          }
         }
       }
       const bool waiting = (ray < 0 && !exhausted) || (ray >= 0 && !ready);
@@ -192,18 +241,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
             NGL_FINISH(NGL_RAY_INVALID, -1);  // hit list does not belong to this depth
           } else {
             if (p != cp) {
-              // ancestor chain of the pair's voxel (parents always exist)
-              int w = v;
-#pragma unroll
-              for (int l = NGL_MAX_LODS; l >= 1; --l) {
-                if (l <= Lpair) {
-                  if (l <= Lp) {
-                    vox[l - 1] = w;
-                    cell[l - 1] = md.cell[l + 1][w];
-                  }
-                  w = md.parent[l + 1][w];
-                }
-              }
+              ancestor_chain(md, v, Lpair, Lp, cp >= 0, vox, cell);
               cp = p;
             }
 #pragma unroll
@@ -288,6 +326,249 @@ __global__ __launch_bounds__(64 * NW) void k_sphere_trace(ngl_model md, TraceArg
     b2b = blend ? md.b2[A.lod] : 0.0f;
   }
   serve_queue<M, FT, XYZ, ANALYTIC, MFMA, DEC>(md, A, S, b2a, b2b);
+}
+
+// Lanes per ray of the wide tracer (a divisor of the feature width M).
+#ifndef NGL_TRACE_WIDE_LANES
+#define NGL_TRACE_WIDE_LANES 8
+#endif
+template <int M>
+constexpr int wide_lanes() {
+  return NGL_TRACE_WIDE_LANES < M ? NGL_TRACE_WIDE_LANES : M;
+}
+
+// Wide form of serve_queue for the long rays left after the first phase:
+// a group of G lanes serves one ray, lane g holding the feature slice
+// [g*D, g*D + D) of every level.  A step's loads are then two short
+// dependent rounds (corner ids, then row slices) spread over G lanes,
+// where one lane per ray issues every row load itself; a few long rays
+// finish in far less time.  Each feature element is accumulated over the
+// same corners and levels in the same order, the staged decoder row and
+// the step rule are those of serve_queue, so results are the same bits.
+template <int M, typename FT, bool XYZ, class DEC, int G>
+__device__ __forceinline__ void serve_queue_wide(const ngl_model& md, const TraceArgs& A, const DecLds<DEC>& S,
+                                                 float* zbuf, float b2a, float b2b) {
+  constexpr int D = M / G;    // feature elements per lane
+  constexpr int NS = 64 / G;  // rays per wavefront
+  constexpr int ZR = M + 1;   // zbuf row stride (odd: spreads LDS banks)
+  static_assert(M % G == 0 && 64 % G == 0 && NS <= 16, "wide tracer shape");
+  const int lane = threadIdx.x & 63;
+  const int slot = lane / G, g = lane % G, lead = slot * G;
+  const bool blend = trace_blend(A);
+  const int lod = A.lod;
+  const int Lp = blend ? lod + 1 : lod;
+  const int PD = A.pair_depth > 0 ? A.pair_depth : Lp + 1;
+  const int Lpair = PD - 1;
+  const int64_t nv_t = md.nvox[PD];
+  int64_t R = A.R;
+  const int32_t* ids = A.ray_ids;
+  if (A.bucket_counts) {
+    unsigned off = 0;
+    for (int b = 0; b < A.bucket; ++b) off += A.bucket_counts[b];
+    R = A.bucket_counts[A.bucket];
+    ids += off;
+  }
+  float al = A.alpha;
+  const int H = md.hidden;
+  // ray state, the same in every lane of a group
+  int ray = -1, p = 0, e = 0, k = 0, cp = -1;
+  bool ready = false;
+  float t = 0.0f, prev = __builtin_inff();
+  float oo[3] = {0.0f, 0.0f, 0.0f}, dd[3] = {0.0f, 0.0f, 0.0f};
+  int vox[NGL_MAX_LODS];
+  uint32_t cell[NGL_MAX_LODS];
+#pragma unroll
+  for (int l = 0; l < NGL_MAX_LODS; ++l) {
+    vox[l] = 0;
+    cell[l] = 0;
+  }
+  bool exhausted = false;  // wave-uniform
+  unsigned nfin = 0;
+#define NGL_FINISH_W(st_, hv_)          \
+  do {                                  \
+    if (g == 0) {                       \
+      const int64_t g_ = A.base + ray;  \
+      A.t_hit[g_] = t;                  \
+      A.status[g_] = (st_);             \
+      A.steps[g_] = k;                  \
+      A.hit_vox[g_] = (hv_);            \
+      ++nfin;                           \
+    }                                   \
+    ray = -1;                           \
+    ready = false;                      \
+  } while (0)
+  for (;;) {
+    // 1. refill idle groups (requests made by each group's first lane)
+    for (int round = 0; round < 8; ++round) {
+      const uint64_t need = __ballot(ray < 0 && g == 0);
+      if (need && !exhausted) {
+        const int n = __popcll(need);
+        const int first = __ffsll((unsigned long long)need) - 1;
+        unsigned int base = 0;
+        if (lane == first) base = atomicAdd(A.counter, unsigned(n));
+        base = __shfl(base, first, 64);
+        if (int64_t(base) + n >= R) exhausted = true;
+        const int64_t my = int64_t(base) + __popcll(need & ((1ull << lead) - 1ull));
+        if (ray < 0 && my < R) {
+          ray = ids ? ids[my] : int(my);
+          if (A.alpha_pp) al = A.alpha_pp[ray];
+          p = A.ray_off[ray];
+          e = A.ray_off[ray + 1];
+          k = 0;
+          cp = -1;
+          prev = __builtin_inff();
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            oo[a] = A.o[a * A.stride + ray];
+            dd[a] = A.d[a * A.stride + ray];
+          }
+          t = p < e ? A.t_in[p] : 0.0f;
+          if (A.resume) {
+            t = A.st_t[ray];
+            p = A.st_p[ray];
+            k = A.st_k[ray];
+            prev = A.st_prev[ray];
+          }
+          bool bad = false;
+#pragma unroll
+          for (int a = 0; a < 3; ++a) bad = bad || !__builtin_isfinite(oo[a]) || !__builtin_isfinite(dd[a]);
+          if (bad) NGL_FINISH_W(NGL_RAY_INVALID, -1);
+        }
+      }
+      if (ray >= 0 && !ready) {
+        while (p < e && t > A.t_out[p]) ++p;
+        if (p == e) {
+          NGL_FINISH_W(NGL_RAY_MISS, -1);
+        } else {
+          const float ti = A.t_in[p];
+          if (t < ti) t = ti;
+          if (t > A.prm.t_far) NGL_FINISH_W(NGL_RAY_FAR, -1);
+          else if (k == A.prm.max_steps) NGL_FINISH_W(NGL_RAY_MAX_STEPS, -1);
+          else if (A.pause_at > 0 && k == A.pause_at) {
+            if (g == 0) {
+              A.st_t[ray] = t;
+              A.st_p[ray] = p;
+              A.st_k[ray] = k;
+              A.st_prev[ray] = prev;
+              A.parked[atomicAdd(A.parked_n, 1u)] = ray;
+            }
+            ray = -1;
+          } else {
+            ready = true;
+          }
+        }
+      }
+      const bool waiting = (ray < 0 && !exhausted) || (ray >= 0 && !ready);
+      if (__ballot(waiting) == 0) break;
+    }
+    const bool act = ray >= 0 && ready;
+    const bool any_act = __ballot(act) != 0;
+    const bool done = !any_act && exhausted && __ballot(ray >= 0) == 0;
+    if (any_act) {
+      // 2. this lane's slice of the interpolated features
+      float x[3] = {0.0f, 0.0f, 0.0f};
+      float acc[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) acc[i] = 0.0f;
+      int32_t v = -1;
+      bool ok = false;
+      if (act) {
+        x[0] = fmaf(t, dd[0], oo[0]);
+        x[1] = fmaf(t, dd[1], oo[1]);
+        x[2] = fmaf(t, dd[2], oo[2]);
+        v = A.pair_vox[p];
+        if (v < 0 || int64_t(v) >= nv_t) {
+          NGL_FINISH_W(NGL_RAY_INVALID, -1);
+        } else {
+          if (p != cp) {
+            ancestor_chain(md, v, Lpair, Lp, cp >= 0, vox, cell);
+            cp = p;
+          }
+#pragma unroll
+          for (int l = 1; l <= NGL_MAX_LODS; ++l)
+            if (l <= lod)
+              interp_level_slice<M, FT, D>(md, l, vox[l - 1], cell_x(cell[l - 1]), cell_y(cell[l - 1]),
+                                           cell_z(cell[l - 1]), x, g * D, acc);
+          ok = true;
+        }
+      }
+      // 3. lane s < NS stages ray slot s's point as row s and decodes it
+      const int srow = lane < NS ? lane : 0;
+      const int src = srow * G;
+      float xs[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xs[a] = __shfl(x[a], src, 64);
+      const bool oks = (__shfl(int(ok), src, 64) != 0) && lane < NS;
+      const float als = __shfl(al, src, 64);
+      float zs[M];
+#pragma unroll
+      for (int i = 0; i < D; ++i) zbuf[slot * ZR + g * D + i] = acc[i];
+      wave_lds_sync();
+#pragma unroll
+      for (int i = 0; i < M; ++i) zs[i] = oks ? zbuf[srow * ZR + i] : 0.0f;
+      DEC::stage(S.stage, xs, zs);
+      wave_lds_sync();
+      float dist = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H, __ballot(oks));
+      const bool mixs = oks && als > 0.0f;  // Eq. 3 blend with the level lod+1 voxel
+      const uint64_t mixing = __ballot(mixs);
+      if (blend && mixing) {
+        if (ok && al > 0.0f)
+          interp_level_slice<M, FT, D>(md, lod + 1, vox[lod], cell_x(cell[lod]), cell_y(cell[lod]),
+                                       cell_z(cell[lod]), x, g * D, acc);
+#pragma unroll
+        for (int i = 0; i < D; ++i) zbuf[slot * ZR + g * D + i] = acc[i];
+        wave_lds_sync();
+#pragma unroll
+        for (int i = 0; i < M; ++i) zs[i] = mixs ? zbuf[srow * ZR + i] : 0.0f;
+        DEC::stage(S.stage, xs, zs);
+        wave_lds_sync();
+        const float d1 = DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H, mixing);
+        if (mixs) dist = (1.0f - als) * dist + als * d1;
+      }
+      wave_lds_sync();
+      dist = __shfl(dist, slot, 64);
+      // 4. step, in every lane of the group
+      if (act && ray >= 0) {
+        ++k;
+        if (dist < A.prm.delta) {
+          NGL_FINISH_W(NGL_RAY_HIT, v);
+        } else if (A.prm.osc_check && fabsf(dist - prev) < 6.0f * A.prm.delta) {
+          NGL_FINISH_W(NGL_RAY_STALLED, -1);
+        } else {
+          prev = dist;
+          t += dist;
+          ready = false;
+        }
+      }
+    }
+    if (A.live) {
+      unsigned tot = nfin;
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) tot += __shfl_xor(tot, off, 64);
+      nfin = 0;
+      if (lane == 0 && tot > 0) {
+        const unsigned old = atomicSub(A.live, tot);
+        if (old == tot && A.done_clock) *A.done_clock = wall_clock64();
+      }
+    }
+    if (done) break;
+  }
+#undef NGL_FINISH_W
+}
+
+template <int M, typename FT, bool XYZ, int NW, class DEC>
+__global__ __launch_bounds__(64 * NW) void k_sphere_trace_wide(ngl_model md, TraceArgs A) {
+  constexpr int G = wide_lanes<M>();
+  extern __shared__ __align__(16) char smem[];
+  const bool blend = trace_blend(A);
+  const int H = md.hidden;
+  DecLds<DEC> S(smem, H, blend);
+  float* zbuf = reinterpret_cast<float*>(smem + DecLds<DEC>::fixed_bytes(H, blend) + NW * DEC::STAGE_BYTES) +
+                (threadIdx.x >> 6) * (64 / G) * (M + 1);
+  DEC::load(md, A.lod, S.frag0, S.w2s0);
+  if (blend) DEC::load(md, A.lod + 1, S.frag1, S.w2s1);
+  __syncthreads();
+  serve_queue_wide<M, FT, XYZ, DEC, G>(md, A, S, zbuf, md.b2[A.lod - 1], blend ? md.b2[A.lod] : 0.0f);
 }
 
 // Batched form: views in one launch.  Each block walks the views once, in
@@ -457,8 +738,39 @@ static int launch_trace_nw(const ngl_model& md, const TraceArgs& A, hipStream_t 
   return NGL_OK;
 }
 
+template <int M, typename FT, bool XYZ, int NW, class DEC>
+static int launch_trace_wide_nw(const ngl_model& md, const TraceArgs& A, hipStream_t s, size_t lds) {
+  static int cached = 0;
+  if (!cached) {
+    int dev = 0, cus = 256, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    const void* kern = reinterpret_cast<const void*>(&k_sphere_trace_wide<M, FT, XYZ, NW, DEC>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
+    cached = cus * per;
+  }
+  k_zero_counter<<<1, 64, 0, s>>>(A.counter);
+  constexpr int NS = 64 / wide_lanes<M>();
+  int grid = cached;
+  const int64_t need = (A.R + NS * NW - 1) / (NS * NW);
+  if (need < grid) grid = int(need);
+  k_sphere_trace_wide<M, FT, XYZ, NW, DEC><<<grid, 64 * NW, lds, s>>>(md, A);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+template <int M, typename FT, bool XYZ, class DEC>
+static int launch_trace_wide(const ngl_model& md, const TraceArgs& A, hipStream_t s) {
+  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, trace_blend(A));
+  const size_t per_wave = DEC::STAGE_BYTES + size_t(64 / wide_lanes<M>()) * (M + 1) * 4;
+  if (fixed + 4 * per_wave <= 65536) return launch_trace_wide_nw<M, FT, XYZ, 4, DEC>(md, A, s, fixed + 4 * per_wave);
+  if (fixed + 2 * per_wave <= 65536) return launch_trace_wide_nw<M, FT, XYZ, 2, DEC>(md, A, s, fixed + 2 * per_wave);
+  return launch_trace_wide_nw<M, FT, XYZ, 1, DEC>(md, A, s, fixed + per_wave);
+}
+
 template <int M, typename FT, bool XYZ, class DEC>
 static int launch_trace_mfma(const ngl_model& md, const TraceArgs& A, hipStream_t s) {
+  if (A.wide) return launch_trace_wide<M, FT, XYZ, DEC>(md, A, s);
   const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, trace_blend(A));
   const int want = option(NGL_OPT_TRACE_WAVES);
   if ((want == 0 || want >= 4) && fixed + 4 * DEC::STAGE_BYTES <= 65536)

@@ -95,6 +95,7 @@ EXPORTS = {
     "ngl_trace_octree": (C.c_int, [P, P, P, i64, i32, i64, P, C.c_size_t, P, P, P, P, P, P, P]),
     "ngl_sphere_trace": (C.c_int, [P, P, P, i64, i32, C.c_float, P, P, P, P, P, P, P, P, P, P, C.c_size_t, P]),
     "ngl_sphere_trace_workspace": (C.c_int, [P]),
+    "ngl_sphere_trace_workspace_rays": (C.c_int, [C.c_int64, P]),
     "ngl_sphere_trace_lod_workspace": (C.c_int, [i64, P]),
     "ngl_sphere_trace_lod": (C.c_int, [P, P, P, i64, i32, P, P, P, P, P, P, P, P, P, P, P, P, C.c_size_t, P]),
     "ngl_model_table_bytes": (C.c_int, [i32, P]),
@@ -130,7 +131,8 @@ def lib():
     return _lib
 
 
-OPT_F32_DECODER, OPT_TRACE_WAVES, OPT_TRACE_BLOCKS_PER_CU = 0, 1, 2
+(OPT_F32_DECODER, OPT_TRACE_WAVES, OPT_TRACE_BLOCKS_PER_CU, OPT_TRACE_PAUSE1, OPT_TRACE_PAUSE2,
+ OPT_TRACE_WIDE) = 0, 1, 2, 3, 4, 5
 MAX_BATCH = 32
 
 
@@ -540,7 +542,9 @@ def trace_params(max_steps: int, delta: float, t_far: float = 5.0, osc_check: bo
 
 
 def sphere_trace(model: Model, o, d, lod: int, alpha: float, hits: dict, max_steps: int, delta: float,
-                 t_far: float = 5.0, osc_check: bool = False, analytic_sphere=None, out=None):
+                 t_far: float = 5.0, osc_check: bool = False, analytic_sphere=None, out=None, phased: bool = True):
+    """Sphere trace one view (ngl_sphere_trace).  `phased` sizes the
+    workspace for the phased form (same results, long rays compacted)."""
     R = o.shape[1]
     dev = o.device
     if out is None:
@@ -551,7 +555,10 @@ def sphere_trace(model: Model, o, d, lod: int, alpha: float, hits: dict, max_ste
     prm = trace_params(max_steps, delta, t_far, osc_check, analytic_sphere)
     if "ws" not in out:
         nb = C.c_size_t()
-        _check(lib().ngl_sphere_trace_workspace(C.addressof(nb)))
+        if phased:
+            _check(lib().ngl_sphere_trace_workspace_rays(R, C.addressof(nb)))
+        else:
+            _check(lib().ngl_sphere_trace_workspace(C.addressof(nb)))
         out["ws"] = torch.empty(int(nb.value), dtype=torch.uint8, device=dev)
     _check(lib().ngl_sphere_trace(model.ref, _ptr(o), _ptr(d), R, int(lod), float(alpha), _ptr(hits["vox"]),
                                   _ptr(hits["t_in"]), _ptr(hits["t_out"]), _ptr(hits["ray_off"]), C.addressof(prm),

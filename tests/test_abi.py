@@ -78,3 +78,10 @@ def test_options():
         ngl.set_option(ngl.OPT_F32_DECODER, 7)
     with pytest.raises(ngl.NGLError):
         ngl.set_option(99, 0)
+    for key in (ngl.OPT_TRACE_PAUSE1, ngl.OPT_TRACE_PAUSE2):
+        with pytest.raises(ngl.NGLError):
+            ngl.set_option(key, 5000)
+        with pytest.raises(ngl.NGLError):
+            ngl.set_option(key, -1)
+    with pytest.raises(ngl.NGLError):
+        ngl.set_option(ngl.OPT_TRACE_WIDE, 2)
