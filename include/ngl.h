@@ -87,6 +87,9 @@ int ngl_version(void);
  *  NGL_OPT_TRACE_WIDE: 1 (default) = the last phase of a phased trace
  *    serves each ray with a group of lanes (matrix-core decoders only),
  *    0 = one lane per ray throughout.
+ *  NGL_OPT_COOP_GATHER: 1 (default) = the matrix-core query kernel
+ *    gathers each feature row with M/8 lanes holding 8 elements each,
+ *    0 = one lane per point reads whole rows (same results).
  * NGL_E_INVALID for an unknown option or value. */
 typedef enum {
   NGL_OPT_F32_DECODER = 0,
@@ -95,7 +98,8 @@ typedef enum {
   NGL_OPT_TRACE_PAUSE1 = 3,
   NGL_OPT_TRACE_PAUSE2 = 4,
   NGL_OPT_TRACE_WIDE = 5,
-  NGL_OPT_COUNT = 6
+  NGL_OPT_COOP_GATHER = 6,
+  NGL_OPT_COUNT = 7
 } ngl_option;
 int ngl_set_option(int option, int value);
 int ngl_get_option(int option, int* value);

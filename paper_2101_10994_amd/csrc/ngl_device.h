@@ -232,6 +232,50 @@ __device__ inline void interp_level(const ngl_model& md, int lvl, int v, int cx,
   for (int j = 0; j < 8; ++j) axpy_row<M, FT>(md.feat[lvl - 1], cs[j], corner_weight(u, j), acc);
 }
 
+// v[i] = row[off + i] as float, i < D: a D-wide slice of row `c`.
+template <int M, typename FT, int D>
+__device__ inline void load_slice(const void* base, int c, int off, float* v) {
+  if constexpr (std::is_same<FT, F32>::value) {
+    const float* r = static_cast<const float*>(base) + size_t(c) * M + off;
+    if constexpr (D % 4 == 0) {
+#pragma unroll
+      for (int q = 0; q < D / 4; ++q) {
+        const float4 f = reinterpret_cast<const float4*>(r)[q];
+        v[4 * q] = f.x, v[4 * q + 1] = f.y, v[4 * q + 2] = f.z, v[4 * q + 3] = f.w;
+      }
+    } else if constexpr (D == 2) {
+      const float2 f = *reinterpret_cast<const float2*>(r);
+      v[0] = f.x, v[1] = f.y;
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i) v[i] = r[i];
+    }
+  } else {
+    const uint16_t* r = static_cast<const uint16_t*>(base) + size_t(c) * M + off;
+    uint32_t h[D];
+    if constexpr (D % 8 == 0) {
+#pragma unroll
+      for (int q = 0; q < D / 8; ++q) {
+        const uint4 f = reinterpret_cast<const uint4*>(r)[q];
+        const uint32_t wv[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) h[8 * q + 2 * e] = wv[e] & 0xffffu, h[8 * q + 2 * e + 1] = wv[e] >> 16;
+      }
+    } else if constexpr (D == 4) {
+      const uint2 f = *reinterpret_cast<const uint2*>(r);
+      h[0] = f.x & 0xffffu, h[1] = f.x >> 16, h[2] = f.y & 0xffffu, h[3] = f.y >> 16;
+    } else if constexpr (D == 2) {
+      const uint32_t f = *reinterpret_cast<const uint32_t*>(r);
+      h[0] = f & 0xffffu, h[1] = f >> 16;
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i) h[i] = r[i];
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[i] = std::is_same<FT, BF16>::value ? bf16_to_f32(h[i]) : f16_to_f32(h[i]);
+  }
+}
+
 // acc[i] += w * row[off + i], i < D: a D-wide slice of row `c`.
 template <int M, typename FT, int D>
 __device__ inline void axpy_slice(const void* base, int c, int off, float w, float* acc) {
@@ -282,6 +326,13 @@ __device__ inline void axpy_slice(const void* base, int c, int off, float w, flo
   }
 }
 
+// interp_level_slice for a voxel that may be absent (v < 0): the loads use
+// voxel 0 of the level (which exists) so that they need no branch, and an
+// absent voxel leaves acc unchanged, as skipping the level does.
+template <int M, typename FT, int D>
+__device__ inline void interp_level_slice_sel(const ngl_model& md, int lvl, int v, int cx, int cy, int cz,
+                                              const float x[3], int off, float* acc);
+
 // The slice [off, off + D) of interp_level's accumulation, with the same
 // weights and the same order of operations for every feature element.
 template <int M, typename FT, int D>
@@ -294,6 +345,17 @@ __device__ inline void interp_level_slice(const ngl_model& md, int lvl, int v, i
   const int cs[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
 #pragma unroll
   for (int j = 0; j < 8; ++j) axpy_slice<M, FT, D>(md.feat[lvl - 1], cs[j], off, corner_weight(u, j), acc);
+}
+
+template <int M, typename FT, int D>
+__device__ inline void interp_level_slice_sel(const ngl_model& md, int lvl, int v, int cx, int cy, int cz,
+                                              const float x[3], int off, float* acc) {
+  float t[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) t[i] = acc[i];
+  interp_level_slice<M, FT, D>(md, lvl, v >= 0 ? v : 0, cx, cy, cz, x, off, t);
+#pragma unroll
+  for (int i = 0; i < D; ++i) acc[i] = v >= 0 ? t[i] : acc[i];
 }
 
 // ---------------------------------------------------------------------------

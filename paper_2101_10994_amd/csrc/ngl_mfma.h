@@ -148,6 +148,36 @@ __device__ inline void stage_row(uint16_t* stage, const float x[3], const float*
   for (int q = 4; q < 16; ++q) tail[q] = 0u;
 }
 
+// stage_row in two parts, for rows whose features were gathered by other
+// lanes: the packed slice [off, off + 8) of row `row`'s features, and the
+// rest of this lane's own row (feature padding, position and bias words).
+template <int M, bool XYZ>
+__device__ inline void stage_slice8(uint16_t* stage, int row, int off, const float* v) {
+  using S = MfmaShape<M, XYZ>;
+  uint4* w = reinterpret_cast<uint4*>(stage + row * S::ROW + off);
+  *w = make_uint4(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7]));
+}
+
+template <int M, bool XYZ>
+__device__ inline void stage_rest(uint16_t* stage, const float x[3]) {
+  using S = MfmaShape<M, XYZ>;
+  const int lane = threadIdx.x & 63;
+  uint32_t* row = reinterpret_cast<uint32_t*>(stage + lane * S::ROW);
+#pragma unroll
+  for (int s = 0; s < S::KZ; ++s)
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (32 * s + 2 * q >= M) row[16 * s + q] = 0u;
+  const uint4 t = pos_bias_row<XYZ>(x);
+  uint32_t* tail = row + 16 * S::KZ;
+  tail[0] = t.x;
+  tail[1] = t.y;
+  tail[2] = t.z;
+  tail[3] = t.w;
+#pragma unroll
+  for (int q = 4; q < 16; ++q) tail[q] = 0u;
+}
+
 // First layer on the matrix cores, second layer and reduction in FP32: the
 // decoder output for this lane's staged point (all 64 lanes must call it).
 // `live` (wave-uniform) marks the lanes whose output is used: a 16-lane
@@ -237,6 +267,26 @@ __device__ inline void stage_row32(float* stage, const float x[3], const float* 
 }
 
 template <int M, bool XYZ>
+__device__ inline void stage_slice8_32(float* stage, int row, int off, const float* v) {
+  using S = MfmaShape32<M, XYZ>;
+  float* w = stage + row * S::ROW + S::OFF + off;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) w[i] = v[i];
+}
+
+template <int M, bool XYZ>
+__device__ inline void stage_rest32(float* stage, const float x[3]) {
+  using S = MfmaShape32<M, XYZ>;
+  float* row = stage + (threadIdx.x & 63) * S::ROW;
+#pragma unroll
+  for (int k = 0; k < S::KP; ++k) {
+    if (k < S::OFF) row[k] = x[k < 3 ? k : 0];
+    else if (k == S::OFF + M) row[k] = 1.0f;
+    else if (k > S::OFF + M) row[k] = 0.0f;
+  }
+}
+
+template <int M, bool XYZ>
 __device__ inline float wave_decode32(const float* frag, const float* w2s, float b2, const float* stage, int H,
                                       uint64_t live) {
   using S = MfmaShape32<M, XYZ>;
@@ -279,6 +329,10 @@ struct DecBF16 {
   static constexpr int frag_bytes(int H) { return MfmaShape<M, XYZ>::frag_bytes(H); }
   __device__ static void load(const ngl_model& md, int L, Frag* f, float* w2s) { load_frags<M, XYZ>(md, L, f, w2s); }
   __device__ static void stage(Stage* st, const float x[3], const float* z) { stage_row<M, XYZ>(st, x, z); }
+  __device__ static void stage_slice(Stage* st, int row, int off, const float* v) {
+    stage_slice8<M, XYZ>(st, row, off, v);
+  }
+  __device__ static void stage_rest(Stage* st, const float x[3]) { ngl::stage_rest<M, XYZ>(st, x); }
   __device__ static float decode(const Frag* f, const float* w2s, float b2, const Stage* st, int H,
                                  uint64_t live = ~0ull) {
     return wave_decode<M, XYZ>(f, w2s, b2, st, H, live);
@@ -295,6 +349,10 @@ struct DecF32 {
   static constexpr int frag_bytes(int H) { return MfmaShape32<M, XYZ>::frag_bytes(H); }
   __device__ static void load(const ngl_model& md, int L, Frag* f, float* w2s) { load_frags32<M, XYZ>(md, L, f, w2s); }
   __device__ static void stage(Stage* st, const float x[3], const float* z) { stage_row32<M, XYZ>(st, x, z); }
+  __device__ static void stage_slice(Stage* st, int row, int off, const float* v) {
+    stage_slice8_32<M, XYZ>(st, row, off, v);
+  }
+  __device__ static void stage_rest(Stage* st, const float x[3]) { stage_rest32<M, XYZ>(st, x); }
   __device__ static float decode(const Frag* f, const float* w2s, float b2, const Stage* st, int H,
                                  uint64_t live = ~0ull) {
     return wave_decode32<M, XYZ>(f, w2s, b2, st, H, live);
@@ -321,5 +379,92 @@ struct DecLds {
     return size_t(DEC::frag_bytes(H)) * (blend ? 2 : 1) + 2 * sizeof(float) * size_t(H);
   }
 };
+
+#ifndef NGL_COOP_BATCH
+#define NGL_COOP_BATCH 1
+#endif
+
+// One level of the cooperative gather for the wavefront's 64 points:
+// round s gives group r the point q = (64/G) s + r, whose voxel, cell and
+// position come from lane q (the cell is (cx, cy, cz) >> sh, or with
+// PACKED the packed cell word in cx).  The corner ids of all rounds are
+// loaded first, then the row slices a few rounds at a time, so most loads
+// of a level are in flight together.  Absent voxels (v < 0) load voxel 0's
+// rows and keep their accumulator; rounds whose points are all outside
+// `live` (wave-uniform lane mask) are skipped.
+template <int M, typename FT, int G, bool PACKED>
+__device__ __forceinline__ void coop_level(const ngl_model& md, int l, int sh, int v, const float x[3], int cx, int cy,
+                                           int cz, int r, int g, float (*acc)[M / G], uint64_t live = ~0ull) {
+  constexpr int D = M / G, NQ = 64 / G;
+  constexpr uint64_t QM = NQ == 64 ? ~0ull : ((1ull << NQ) - 1ull);
+  int vq[G];
+  int4 c0[G], c1[G];
+#pragma unroll
+  for (int s = 0; s < G; ++s) {
+    vq[s] = __shfl(v, NQ * s + r, 64);
+    if (((live >> (NQ * s)) & QM) == 0) continue;
+    const int4* cp = reinterpret_cast<const int4*>(md.corners[l - 1] + size_t(vq[s] >= 0 ? vq[s] : 0) * 8);
+    c0[s] = cp[0];
+    c1[s] = cp[1];
+  }
+  constexpr int B = NGL_COOP_BATCH < G ? NGL_COOP_BATCH : G;  // rounds whose row slices are in flight together
+#pragma unroll
+  for (int h = 0; h < G / B; ++h) {
+    float fv[B][8][D];
+#pragma unroll
+    for (int s2 = 0; s2 < B; ++s2) {
+      const int s = h * B + s2;
+      if (((live >> (NQ * s)) & QM) == 0) continue;
+      const int cs[8] = {c0[s].x, c0[s].y, c0[s].z, c0[s].w, c1[s].x, c1[s].y, c1[s].z, c1[s].w};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) load_slice<M, FT, D>(md.feat[l - 1], cs[j], g * D, fv[s2][j]);
+    }
+#pragma unroll
+    for (int s2 = 0; s2 < B; ++s2) {
+      const int s = h * B + s2;
+      if (((live >> (NQ * s)) & QM) == 0) continue;
+      const int q = NQ * s + r;
+      float xq[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) xq[a] = __shfl(x[a], q, 64);
+      int qx, qy, qz;
+      if constexpr (PACKED) {
+        const uint32_t c = uint32_t(__shfl(cx, q, 64));
+        qx = cell_x(c), qy = cell_y(c), qz = cell_z(c);
+      } else {
+        qx = __shfl(cx, q, 64) >> sh, qy = __shfl(cy, q, 64) >> sh, qz = __shfl(cz, q, 64) >> sh;
+      }
+      float u[3];
+      cell_local(l, qx, qy, qz, xq, u);
+      float t[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) t[i] = acc[s][i];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float w = corner_weight(u, j);
+#pragma unroll
+        for (int i = 0; i < D; ++i) t[i] = fmaf(w, fv[s2][j][i], t[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < D; ++i) acc[s][i] = vq[s] >= 0 ? t[i] : acc[s][i];
+    }
+  }
+}
+
+// Shape of the cooperative gather: G = M/8 lanes per point, each holding 8
+// feature elements (M is a multiple of 8).
+template <int M>
+struct CoopShape {
+  static constexpr int D = 8;      // feature elements per lane (16 or 32 bytes of a row)
+  static constexpr int G = M / D;  // lanes per point in a gather round
+};
+
+// Gathered slices into the staging rows: round s of group r is row
+// (64/G) s + r.
+template <class DEC, int G>
+__device__ __forceinline__ void stage_slices(typename DEC::Stage* st, int r, int g, const float (*acc)[8]) {
+#pragma unroll
+  for (int s = 0; s < G; ++s) DEC::stage_slice(st, (64 / G) * s + r, 8 * g, acc[s]);
+}
 
 }  // namespace ngl

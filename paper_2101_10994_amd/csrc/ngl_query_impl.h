@@ -160,6 +160,122 @@ __global__ __launch_bounds__(64 * NW) void k_query_mfma(ngl_model md, const floa
   }
 }
 
+// Cooperative gather: lanes locate their own points as above, then the
+// wavefront gathers the 64 points' features in G rounds of 64/G points, a
+// group of G = M/8 lanes per point with lane g loading the 8 elements
+// [8g, 8g + 8) of each corner row.  A row (32 to 256 bytes) is then read
+// by a few lanes together, where one lane per point reads whole rows alone
+// and the vector cache serves one line per lane and load.  Every element
+// is accumulated in the same order as interp_level, so the results are
+// those of k_query_mfma bit for bit: the slices are packed straight into the
+// staging rows, where each lane adds the rest of its own row.
+// One evaluation of the wavefront's located points with the cooperative
+// gather and the matrix-core decoder(s): features of levels 1..lod, the
+// decoder lod, and with `blend` the Eq. 3 mix (weight a) with decoder lod+1
+// on z + the level lod+1 voxel vn.  Every lane must call it.
+template <int M, typename FT, class DEC>
+__device__ __forceinline__ float coop_eval(const ngl_model& md, const DecLds<DEC>& S, const float x[3],
+                                           const int* vox, int cx, int cy, int cz, int vn, bool act, int lod, int Lp,
+                                           bool blend, float a, float b2a, float b2b) {
+  const uint64_t live = __ballot(act);  // rounds without an active point are skipped
+  constexpr int G = CoopShape<M>::G, D = CoopShape<M>::D;
+  const int lane = threadIdx.x & 63, r = lane / G, g = lane % G;
+  const int H = md.hidden;
+  float acc[G][D];
+#pragma unroll
+  for (int s = 0; s < G; ++s)
+#pragma unroll
+    for (int i = 0; i < D; ++i) acc[s][i] = 0.0f;
+#pragma unroll
+  for (int l = 1; l <= NGL_MAX_LODS; ++l)
+    if (l <= lod && md.nvox[l + 1] > 0)
+      coop_level<M, FT, G, false>(md, l, Lp - l, act ? vox[l - 1] : -1, x, cx, cy, cz, r, g, acc, live);
+  stage_slices<DEC, G>(S.stage, r, g, acc);
+  DEC::stage_rest(S.stage, x);
+  wave_lds_sync();
+  float out = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H, live);
+  if (blend) {
+    // z_{L+1} = z_L + psi_{L+1}
+    wave_lds_sync();
+    if (md.nvox[lod + 2] > 0) coop_level<M, FT, G, false>(md, lod + 1, 0, act ? vn : -1, x, cx, cy, cz, r, g, acc, live);
+    stage_slices<DEC, G>(S.stage, r, g, acc);
+    wave_lds_sync();
+    out = (1.0f - a) * out + a * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H, live);
+  }
+  wave_lds_sync();
+  return out;
+}
+
+template <int M, typename FT, bool XYZ, int NW, class DEC>
+__global__ __launch_bounds__(64 * NW) void k_query_coop(ngl_model md, const float* __restrict__ xs, int64_t P,
+                                                        int lod, float alpha, const float* __restrict__ alpha_pp,
+                                                        float* __restrict__ sdf, uint8_t* __restrict__ valid,
+                                                        int32_t* __restrict__ vox_out) {
+  extern __shared__ __align__(16) char smem[];
+  const int H = md.hidden;
+  const bool blend = alpha_pp != nullptr || alpha > 0.0f;
+  DecLds<DEC> S(smem, H, blend);
+  DEC::load(md, lod, S.frag0, S.w2s0);
+  if (blend) DEC::load(md, lod + 1, S.frag1, S.w2s1);
+  __syncthreads();
+  const float b2a = md.b2[lod - 1];
+  const float b2b = blend ? md.b2[lod] : 0.0f;
+  const int Lp = blend ? lod + 1 : lod;
+  for (int64_t base = int64_t(blockIdx.x) * (64 * NW); base < P; base += int64_t(gridDim.x) * (64 * NW)) {
+    const int64_t p = base + threadIdx.x;
+    const bool act = p < P;
+    float x[3] = {0.0f, 0.0f, 0.0f};
+    if (act) {
+      x[0] = xs[p];
+      x[1] = xs[P + p];
+      x[2] = xs[2 * P + p];
+    }
+    int vox[NGL_MAX_LODS];
+    int cx, cy, cz, vlast, vn;
+    locate<NGL_MAX_LODS>(md, x, Lp, vox, &cx, &cy, &cz, &vlast, lod + 1, &vn);
+    if (!act) {
+#pragma unroll
+      for (int l = 0; l < NGL_MAX_LODS; ++l) vox[l] = -1;
+      vlast = vn = -1;
+    }
+    const float a = act ? (alpha_pp ? alpha_pp[p] : alpha) : 0.0f;
+    const float out = coop_eval<M, FT, DEC>(md, S, x, vox, cx, cy, cz, vn, act, lod, Lp, blend, a, b2a, b2b);
+    if (act) {
+      sdf[p] = out;
+      if (valid) valid[p] = vlast >= 0 ? 1 : 0;
+      if (vox_out) {
+#pragma unroll
+        for (int l = 1; l <= NGL_MAX_LODS; ++l)
+          if (l <= Lp) vox_out[int64_t(l - 1) * P + p] = vox[l - 1];
+      }
+    }
+  }
+}
+
+template <int M, typename FT, bool XYZ, int NW, class DEC>
+static int launch_query_coop_nw(const ngl_model& md, const float* x, int64_t P, int lod, float alpha,
+                                const float* app, float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s,
+                                size_t lds) {
+  int64_t grid = (P + 64 * NW - 1) / (64 * NW);
+  if (grid > 4096) grid = 4096;
+  k_query_coop<M, FT, XYZ, NW, DEC><<<unsigned(grid), 64 * NW, lds, s>>>(md, x, P, lod, alpha, app, sdf, valid, vox);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+template <int M, typename FT, bool XYZ, class DEC>
+static int launch_query_coop(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app,
+                             float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s) {
+  const bool blend = app != nullptr || alpha > 0.0f;
+  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, blend);
+  constexpr size_t R = DEC::STAGE_BYTES;
+  if (fixed + 4 * R <= 65536)
+    return launch_query_coop_nw<M, FT, XYZ, 4, DEC>(md, x, P, lod, alpha, app, sdf, valid, vox, s, fixed + 4 * R);
+  if (fixed + 2 * R <= 65536)
+    return launch_query_coop_nw<M, FT, XYZ, 2, DEC>(md, x, P, lod, alpha, app, sdf, valid, vox, s, fixed + 2 * R);
+  return launch_query_coop_nw<M, FT, XYZ, 1, DEC>(md, x, P, lod, alpha, app, sdf, valid, vox, s, fixed + R);
+}
+
 template <int M, typename FT, bool XYZ, int NW, class DEC>
 static int launch_query_mfma_nw(const ngl_model& md, const float* x, int64_t P, int lod, float alpha,
                                 const float* app, float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s,
@@ -174,6 +290,8 @@ static int launch_query_mfma_nw(const ngl_model& md, const float* x, int64_t P, 
 template <int M, typename FT, bool XYZ, class DEC>
 static int launch_query_mfma(const ngl_model& md, const float* x, int64_t P, int lod, float alpha, const float* app,
                              float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s) {
+  if (option(NGL_OPT_COOP_GATHER) == 1)
+    return launch_query_coop<M, FT, XYZ, DEC>(md, x, P, lod, alpha, app, sdf, valid, vox, s);
   const bool blend = app != nullptr || alpha > 0.0f;
   const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, blend);
   if (fixed + 4 * DEC::STAGE_BYTES <= 65536)
@@ -256,9 +374,14 @@ __global__ __launch_bounds__(64 * NW) void k_normals(ngl_model md, NormalArgs A)
       const float sgn = (e & 1) ? -1.0f : 1.0f;
       float x[3] = {x0[0], x0[1], x0[2]};
       x[a] = x0[a] + sgn * A.h;
-      float z[M], zn[M];
-      query_z<M, FT, XYZ>(md, x, A.lod, blend, z, zn);
       float f;
+      float z[M], zn[M];
+      if (act) {
+        query_z<M, FT, XYZ>(md, x, A.lod, blend, z, zn);
+      } else {
+#pragma unroll
+        for (int k = 0; k < M; ++k) z[k] = zn[k] = 0.0f;
+      }
       if constexpr (MFMA) {
         DEC::stage(S.stage, x, z);
         wave_lds_sync();
@@ -271,8 +394,11 @@ __global__ __launch_bounds__(64 * NW) void k_normals(ngl_model md, NormalArgs A)
         }
         wave_lds_sync();
       } else {
-        f = decode_f32<M, XYZ>(md, A.lod, x, z);
-        if (blend) f = (1.0f - A.alpha) * f + A.alpha * decode_f32<M, XYZ>(md, A.lod + 1, x, zn);
+        f = 0.0f;
+        if (act) {
+          f = decode_f32<M, XYZ>(md, A.lod, x, z);
+          if (blend) f = (1.0f - A.alpha) * f + A.alpha * decode_f32<M, XYZ>(md, A.lod + 1, x, zn);
+        }
       }
       g[a] += sgn * f;
     }

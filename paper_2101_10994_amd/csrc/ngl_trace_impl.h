@@ -102,6 +102,10 @@ __device__ __forceinline__ void ancestor_chain(const ngl_model& md, int v, int L
   }
 }
 
+#ifndef NGL_TRACE_COOP
+#define NGL_TRACE_COOP 1
+#endif
+
 // One wavefront serves a view's ray queue.  Each lane keeps one ray; a lane
 // whose ray terminates takes the next ray from the queue, so every step is
 // evaluated on a compacted set of active rays.  Every ray ends after at most
@@ -127,6 +131,9 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
   }
   float al = A.alpha;  // this lane's blend weight
   const int H = md.hidden;
+  // matrix-core tracers over FP32 features gather rows cooperatively (see
+  // coop_level); with 16-bit features one lane per ray measured faster
+  constexpr bool COOP = MFMA && !ANALYTIC && NGL_TRACE_COOP && std::is_same<FT, F32>::value;
   int ray = -1, p = 0, e = 0, k = 0, cp = -1;
   bool ready = false;
   float t = 0.0f, prev = __builtin_inff();
@@ -244,17 +251,51 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
               ancestor_chain(md, v, Lpair, Lp, cp >= 0, vox, cell);
               cp = p;
             }
+            if constexpr (!COOP) {
 #pragma unroll
-            for (int l = 1; l <= NGL_MAX_LODS; ++l)
-              if (l <= lod)
-                interp_level<M, FT>(md, l, vox[l - 1], cell_x(cell[l - 1]), cell_y(cell[l - 1]), cell_z(cell[l - 1]),
-                                    x, z);
+              for (int l = 1; l <= NGL_MAX_LODS; ++l)
+                if (l <= lod)
+                  interp_level<M, FT>(md, l, vox[l - 1], cell_x(cell[l - 1]), cell_y(cell[l - 1]),
+                                      cell_z(cell[l - 1]), x, z);
+            }
             ok = true;
           }
         }
       }
       if constexpr (!ANALYTIC) {
         if constexpr (MFMA) {
+          if constexpr (COOP) {
+            // cooperative gather of the evaluating lanes' features (rounds
+            // without one are skipped), packed straight into the staging rows
+            constexpr int G = CoopShape<M>::G, D = CoopShape<M>::D;
+            const int r = lane / G, g = lane % G;
+            const uint64_t okm = __ballot(ok);
+            float acc[G][D];
+#pragma unroll
+            for (int s = 0; s < G; ++s)
+#pragma unroll
+              for (int i = 0; i < D; ++i) acc[s][i] = 0.0f;
+#pragma unroll
+            for (int l = 1; l <= NGL_MAX_LODS; ++l)
+              if (l <= lod)
+                coop_level<M, FT, G, true>(md, l, 0, ok ? vox[l - 1] : -1, x, int(cell[l - 1]), 0, 0, r, g, acc, okm);
+            stage_slices<DEC, G>(S.stage, r, g, acc);
+            DEC::stage_rest(S.stage, x);
+            wave_lds_sync();
+            dist = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H, okm);
+            const bool mix = ok && al > 0.0f;
+            const uint64_t mixing = __ballot(mix);
+            if (blend && mixing) {
+              wave_lds_sync();
+              coop_level<M, FT, G, true>(md, lod + 1, 0, mix ? vox[lod] : -1, x, int(cell[lod]), 0, 0, r, g, acc,
+                                         mixing);
+              stage_slices<DEC, G>(S.stage, r, g, acc);
+              wave_lds_sync();
+              const float d1 = DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H, mixing);
+              if (mix) dist = (1.0f - al) * dist + al * d1;
+            }
+            wave_lds_sync();
+          } else {
           DEC::stage(S.stage, x, z);
           wave_lds_sync();
           // point tiles without an evaluating lane are skipped (the tail of
@@ -271,6 +312,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
             if (mix) dist = (1.0f - al) * dist + al * d1;
           }
           wave_lds_sync();
+          }
         } else if (ok) {
           dist = decode_f32<M, XYZ>(md, lod, x, z);
           if (blend && al > 0.0f) {

@@ -121,3 +121,4 @@ def test_empty_and_argument_errors():
             ngl.sdf_normals(gm, x=x, **kw)
     n = ngl.sdf_normals(gm, 2, x=x)
     assert torch.isfinite(n).all()
+

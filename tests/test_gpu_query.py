@@ -187,3 +187,41 @@ def test_precision_config_sampled():
         print("precision config LOD %d: max |err|/s1 %.2e, median %.2e, max |err| %.2e, max |err|/s %.2e"
               % (lod, rel.max(), np.median(rel), np.abs(gl - ol["sdf"]).max(),
                  (np.abs(gl - ol["sdf"]) / ol["scale"]).max()))
+
+
+COOP_CASES = {
+    "m32-f32": lambda: make_case(W.paper_shape(0), 64, 5, 32, 128),
+    "m32-f16-bf16": lambda: make_case(W.paper_shape(0), 64, 5, 32, 128, feat_dtype="f16", w_dtype="bf16"),
+    "m8": lambda: tiny_case(sigma=0.1),
+    "m16-bf16": lambda: make_case(W.tiny_shape(), 16, 3, 16, 32, feat_dtype="bf16", w_dtype="bf16", sigma=0.1),
+    "m64-noxyz": lambda: make_case(W.tiny_shape(), 16, 3, 64, 64, with_xyz=False, sigma=0.1),
+}
+
+
+@pytest.mark.parametrize("name", list(COOP_CASES))
+def test_coop_gather_is_bitwise_the_lane_gather(name, f32_decoder):
+    """The cooperative gather (8 lanes per feature row) accumulates every
+    element in the same order as the one-lane-per-point gather: sdf, valid
+    and voxel outputs are the same bits, ragged sizes and blends included."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    case = COOP_CASES[name]()
+    gm = case.gpu_model()
+    L = gm.num_lods
+    rng = np.random.default_rng(11)
+    old = ngl.get_option(ngl.OPT_COOP_GATHER)
+    try:
+        for P in (1, 63, 64 * 37 + 5, 100_003):
+            x = np.concatenate([edge_points(case.ijk, 2 ** (L + 1), L, rng), rng.uniform(-1.2, 1.2, (3, P))], axis=1)
+            x = np.ascontiguousarray(x[:, :P].astype(np.float32))
+            xd = torch.from_numpy(x).cuda()
+            app = torch.from_numpy(rng.uniform(0, 1, P).astype(np.float32)).cuda()
+            for lod, alpha, pp in ((L, 0.0, None), (1, 0.0, None), (L - 1, 0.3, None), (L - 1, 0.0, app)):
+                outs = []
+                for coop in (0, 1):
+                    ngl.set_option(ngl.OPT_COOP_GATHER, coop)
+                    outs.append(ngl.query_sdf(gm, xd, lod, alpha=alpha, alpha_pp=pp, want_valid=True, want_vox=True))
+                for k in ("sdf", "valid", "vox"):
+                    assert torch.equal(outs[0][k], outs[1][k]), (P, lod, alpha, pp is not None, k)
+    finally:
+        ngl.set_option(ngl.OPT_COOP_GATHER, old)
