@@ -356,7 +356,11 @@ typedef struct {
  * ngl_sphere_trace (hit_vox is a voxel at pair_depth), plus lod_out
  * (nullable, device [R]): each ray's continuous LOD L.  ws: device bytes
  * from ngl_sphere_trace_lod_workspace(R); calls sharing it must not
- * overlap. */
+ * overlap.  With matrix-core decoders and that workspace the groups are
+ * traced in two phases as in ngl_sphere_trace (rays still running after
+ * NGL_OPT_TRACE_PAUSE1 evaluations are parked per group and finished with
+ * a group of lanes per ray; same results bit for bit); a workspace of
+ * 256 + 9 R bytes (rounded up per array) runs one phase. */
 int ngl_sphere_trace_lod_workspace(int64_t R, size_t* bytes);
 int ngl_sphere_trace_lod(const ngl_model* m, const float* o, const float* d, int64_t R, int32_t pair_depth,
                          const ngl_lod_select* sel, const int32_t* pair_vox, const float* t_in, const float* t_out,

@@ -55,8 +55,15 @@ struct LodWS {
   float* alpha;
   uint8_t* lint;
   static size_t align(size_t b) { return (b + 255) & ~size_t(255); }
+  // phased form: parked state and ids per ray
+  float* st_t = nullptr;
+  int32_t* st_p = nullptr;
+  int32_t* st_k = nullptr;
+  float* st_prev = nullptr;
+  int32_t* pids = nullptr;
   static size_t bytes(int64_t R) { return 256 + align(4 * size_t(R)) + align(4 * size_t(R)) + align(size_t(R)); }
-  LodWS(void* ws, int64_t R) {
+  static size_t bytes_phased(int64_t R) { return bytes(R) + 5 * align(4 * size_t(R)); }
+  LodWS(void* ws, int64_t R, bool phased) {
     char* p = static_cast<char*>(ws);
     counts = reinterpret_cast<unsigned*>(p);
     p += 256;
@@ -65,11 +72,22 @@ struct LodWS {
     alpha = reinterpret_cast<float*>(p);
     p += align(4 * size_t(R));
     lint = reinterpret_cast<uint8_t*>(p);
+    p += align(size_t(R));
+    if (phased) {
+      st_t = reinterpret_cast<float*>(p);
+      st_p = reinterpret_cast<int32_t*>(p + align(4 * size_t(R)));
+      st_k = reinterpret_cast<int32_t*>(p + 2 * align(4 * size_t(R)));
+      st_prev = reinterpret_cast<float*>(p + 3 * align(4 * size_t(R)));
+      pids = reinterpret_cast<int32_t*>(p + 4 * align(4 * size_t(R)));
+    }
   }
 };
 
+// counts: [0, MAX) group sizes, [MAX, 2 MAX) scatter offsets, [2 MAX, 3 MAX)
+// queue heads, [3 MAX, 4 MAX) parked per group, [4 MAX, 5 MAX) heads of the
+// parked queues.
 __global__ void k_lod_init(unsigned* c) {
-  if (threadIdx.x < 3 * NGL_MAX_LODS) c[threadIdx.x] = 0u;
+  if (threadIdx.x < 5 * NGL_MAX_LODS) c[threadIdx.x] = 0u;
 }
 
 // L* and alpha per ray; group sizes counted per block in LDS, then one
@@ -199,7 +217,7 @@ int ngl_sphere_trace_workspace_rays(int64_t R, size_t* bytes) {
 
 int ngl_sphere_trace_lod_workspace(int64_t R, size_t* bytes) {
   NGL_REQUIRE(bytes != nullptr && R >= 0, "bad arguments");
-  *bytes = ngl::LodWS::bytes(R);
+  *bytes = ngl::LodWS::bytes_phased(R);
   return NGL_OK;
 }
 
@@ -228,7 +246,14 @@ int ngl_sphere_trace_lod(const ngl_model* m, const float* o, const float* d, int
   NGL_REQUIRE(ws != nullptr && ws_bytes >= LodWS::bytes(R), "workspace too small: %zu < %zu bytes", ws_bytes,
               LodWS::bytes(R));
   hipStream_t s = (hipStream_t)stream;
-  LodWS W(ws, R);
+  // Phased (matrix-core decoders, workspace large enough, a pause count
+  // below max_steps and the wide phase enabled): rays still running at
+  // the pause are parked per group and finished eight lanes per ray.
+  const int pause = option(NGL_OPT_TRACE_PAUSE1);
+  const bool phased = ws_bytes >= LodWS::bytes_phased(R) && pause > 0 && pause < params->max_steps &&
+                      option(NGL_OPT_TRACE_WIDE) == 1 &&
+                      (m->w_dtype == NGL_BF16 || option(NGL_OPT_F32_DECODER) == 1);
+  LodWS W(ws, R, phased);
   k_lod_init<<<1, 64, 0, s>>>(W.counts);
   NGL_LAUNCHED();
   const unsigned g = unsigned((R + 255) / 256);
@@ -248,7 +273,27 @@ int ngl_sphere_trace_lod(const ngl_model* m, const float* o, const float* d, int
   B.first = first;
   B.n = last - first + 1;
   B.heads = W.counts + 2 * NGL_MAX_LODS;  // zeroed by k_lod_init
-  return buckets_by_width(*m, B, s);
+  if (!phased) return buckets_by_width(*m, B, s);
+  B.base.pause_at = pause;
+  B.base.st_t = W.st_t;
+  B.base.st_p = W.st_p;
+  B.base.st_k = W.st_k;
+  B.base.st_prev = W.st_prev;
+  B.base.parked = W.pids;
+  B.base.parked_n = W.counts + 3 * NGL_MAX_LODS;
+  rc = buckets_by_width(*m, B, s);
+  if (rc) return rc;
+  BucketArgs C = B;
+  C.base.pause_at = 0;
+  C.base.parked = nullptr;
+  C.base.parked_n = nullptr;
+  C.base.resume = true;
+  C.base.wide = true;
+  C.base.ray_ids = W.pids;
+  C.base.bucket_counts = W.counts + 3 * NGL_MAX_LODS;
+  C.base.bucket_sizes = W.counts;
+  C.heads = W.counts + 4 * NGL_MAX_LODS;
+  return buckets_by_width(*m, C, s);
 }
 
 int ngl_model_table_bytes(int32_t n, size_t* bytes) {

@@ -35,6 +35,8 @@ struct TraceArgs {
   const unsigned int* bucket_counts;  // nullable: ray_ids is split into buckets of these sizes ...
   int bucket;                         // ... and this launch serves bucket `bucket`
   const float* alpha_pp;              // nullable: blend weight per ray (replaces alpha)
+  const unsigned int* bucket_sizes;   // nullable: bucket b starts at the sum of these sizes below b
+                                      // (bucket_counts then give each bucket's live entries)
   // Phased tracing (all zero/null otherwise): a ray about to take evaluation
   // number pause_at is parked (state saved, id appended to `parked`) so the
   // next launch can serve the long rays from a dense queue; `resume` starts
@@ -125,7 +127,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
   const int32_t* ids = A.ray_ids;
   if (A.bucket_counts) {
     unsigned off = 0;
-    for (int b = 0; b < A.bucket; ++b) off += A.bucket_counts[b];
+    for (int b = 0; b < A.bucket; ++b) off += A.bucket_sizes ? A.bucket_sizes[b] : A.bucket_counts[b];
     R = A.bucket_counts[A.bucket];
     ids += off;
   }
@@ -406,7 +408,7 @@ __device__ __forceinline__ void serve_queue_wide(const ngl_model& md, const Trac
   const int32_t* ids = A.ray_ids;
   if (A.bucket_counts) {
     unsigned off = 0;
-    for (int b = 0; b < A.bucket; ++b) off += A.bucket_counts[b];
+    for (int b = 0; b < A.bucket; ++b) off += A.bucket_sizes ? A.bucket_sizes[b] : A.bucket_counts[b];
     R = A.bucket_counts[A.bucket];
     ids += off;
   }
@@ -728,6 +730,13 @@ __global__ __launch_bounds__(64 * NW) void k_trace_buckets(ngl_model md, BucketA
     A.bucket = lod - 1;
     A.counter = B.heads + (lod - 1);
     if (lod >= md.num_lods) A.alpha_pp = nullptr;  // the finest LOD does not blend
+    if (A.pause_at > 0) {
+      // parked rays of group b go to the group's own range of the id list
+      unsigned off = 0;
+      for (int q = 0; q < lod - 1; ++q) off += A.bucket_counts[q];
+      A.parked = B.base.parked + off;
+      A.parked_n = B.base.parked_n + (lod - 1);
+    }
     const bool blend = trace_blend(A);
     DecLds<DEC> S(smem, H, blend && MFMA);
     float b2a = 0.0f, b2b = 0.0f;
@@ -740,6 +749,45 @@ __global__ __launch_bounds__(64 * NW) void k_trace_buckets(ngl_model md, BucketA
     }
     serve_queue<M, FT, XYZ, false, MFMA, DEC>(md, A, S, b2a, b2b);
     __syncthreads();  // every wavefront is done with this group's LDS
+  }
+}
+
+// Parked rays of the LOD groups, eight lanes per ray (serve_queue_wide):
+// group b's parked ids sit at its original offset, base.bucket_counts
+// holds how many were parked, base.bucket_sizes the original sizes.
+template <int M, typename FT, bool XYZ, int NW, class DEC>
+__global__ __launch_bounds__(64 * NW) void k_trace_buckets_wide(ngl_model md, BucketArgs B) {
+  constexpr int G = wide_lanes<M>();
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int s_has;
+  const int H = md.hidden;
+  for (int step = 0; step < B.n; ++step) {
+    const int b = (int(blockIdx.x) + step) % B.n;
+    const int lod = B.first + b;
+    if (threadIdx.x == 0)
+      s_has = __atomic_load_n(&B.heads[lod - 1], __ATOMIC_RELAXED) < B.base.bucket_counts[lod - 1];
+    __syncthreads();
+    if (!s_has) {
+      __syncthreads();
+      continue;
+    }
+    TraceArgs A = B.base;
+    A.lod = lod;
+    A.bucket = lod - 1;
+    A.counter = B.heads + (lod - 1);
+    if (lod >= md.num_lods) A.alpha_pp = nullptr;
+    const bool blend = trace_blend(A);
+    DecLds<DEC> S(smem, H, blend);
+    // the slice buffers follow the staging areas of the blending layout (the largest)
+    float* zbuf = reinterpret_cast<float*>(smem + DecLds<DEC>::fixed_bytes(H, true) + NW * DEC::STAGE_BYTES) +
+                  (threadIdx.x >> 6) * (64 / G) * (M + 1);
+    S.stage = reinterpret_cast<typename DEC::Stage*>(smem + DecLds<DEC>::fixed_bytes(H, true)) +
+              (threadIdx.x >> 6) * DEC::STAGE_ELEMS;
+    DEC::load(md, lod, S.frag0, S.w2s0);
+    if (blend) DEC::load(md, lod + 1, S.frag1, S.w2s1);
+    __syncthreads();
+    serve_queue_wide<M, FT, XYZ, DEC, G>(md, A, S, zbuf, md.b2[lod - 1], blend ? md.b2[lod] : 0.0f);
+    __syncthreads();
   }
 }
 
@@ -910,9 +958,38 @@ static int launch_buckets(const ngl_model& md, const BucketArgs& B, hipStream_t 
   return launch_buckets_nw<M, FT, XYZ, MFMA, 1, DEC>(md, B, s, fixed + DEC::STAGE_BYTES);
 }
 
+template <int M, typename FT, bool XYZ, int NW, class DEC>
+static int launch_buckets_wide_nw(const ngl_model& md, const BucketArgs& B, hipStream_t s, size_t lds) {
+  static int per = 0, cus = 0;
+  if (!per) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    const void* kern = reinterpret_cast<const void*>(&k_trace_buckets_wide<M, FT, XYZ, NW, DEC>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
+  }
+  k_trace_buckets_wide<M, FT, XYZ, NW, DEC><<<cus * per, 64 * NW, lds, s>>>(md, B);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+template <int M, typename FT, bool XYZ, class DEC>
+static int launch_buckets_wide(const ngl_model& md, const BucketArgs& B, hipStream_t s) {
+  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, true);
+  const size_t per_wave = DEC::STAGE_BYTES + size_t(64 / wide_lanes<M>()) * (M + 1) * 4;
+  if (fixed + 4 * per_wave <= 65536) return launch_buckets_wide_nw<M, FT, XYZ, 4, DEC>(md, B, s, fixed + 4 * per_wave);
+  if (fixed + 2 * per_wave <= 65536) return launch_buckets_wide_nw<M, FT, XYZ, 2, DEC>(md, B, s, fixed + 2 * per_wave);
+  return launch_buckets_wide_nw<M, FT, XYZ, 1, DEC>(md, B, s, fixed + per_wave);
+}
+
 template <int M, typename FT, bool XYZ>
 struct BucketOp {
   static int run(const ngl_model& md, const BucketArgs& B, hipStream_t s) {
+    if (B.base.wide) {
+      if (md.w_dtype == NGL_BF16) return launch_buckets_wide<M, FT, XYZ, DecBF16<M, XYZ>>(md, B, s);
+      return launch_buckets_wide<M, FT, XYZ, DecF32<M, XYZ>>(md, B, s);
+    }
     if (md.w_dtype == NGL_BF16) return launch_buckets<M, FT, XYZ, true, DecBF16<M, XYZ>>(md, B, s);
     if (option(NGL_OPT_F32_DECODER) == 1) return launch_buckets<M, FT, XYZ, true, DecF32<M, XYZ>>(md, B, s);
     return launch_buckets<M, FT, XYZ, false, DecF32<M, XYZ>>(md, B, s);

@@ -124,3 +124,33 @@ def test_arguments():
     e = ngl.trace_octree(gm, z, z, 3)
     out = ngl.sphere_trace_lod(gm, z, z, 3, ngl.lod_select(1.0, 2.0, 2.0, 1.0), e, 10, 3e-4)
     assert out["t"].numel() == 0
+
+
+@pytest.mark.parametrize("dtypes", [("f32", "f32"), ("f16", "bf16")])
+def test_phased_lod_trace_is_bitwise_the_single_launch(dtypes):
+    """Per-pixel LOD groups traced in two phases (rays parked per group at
+    the pause count, finished eight lanes per ray) give the single launch's
+    outputs bit for bit."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    fd, wd = dtypes
+    case = make_case(W.paper_shape(0), 64, 5, 32, 128, embedded=True, feat_dtype=fd, w_dtype=wd)
+    gm = case.gpu_model()
+    o, d = ngl.camera_rays(W.PAPER.eye, (0, 0, 0), (0, 1, 0), 45.0, 320, 256)
+    hits = ngl.trace_octree(gm, o, d, 6)
+    sel = ngl.lod_select(1.6, 3.2, 5.0, 2.0)
+    keys = (ngl.OPT_TRACE_PAUSE1, ngl.OPT_TRACE_WIDE)
+    old = [ngl.get_option(k) for k in keys]
+    try:
+        ngl.set_option(ngl.OPT_TRACE_PAUSE1, 0)
+        ref = ngl.sphere_trace_lod(gm, o, d, 6, sel, hits, 100, 1e-4)
+        assert (ref["steps"].cpu().numpy() > 8).sum() > 100
+        ngl.set_option(ngl.OPT_TRACE_WIDE, 1)
+        for pause in (24, 8, 1, 99):
+            ngl.set_option(ngl.OPT_TRACE_PAUSE1, pause)
+            g = ngl.sphere_trace_lod(gm, o, d, 6, sel, hits, 100, 1e-4)
+            for key in ("t", "status", "steps", "hit_vox", "lod"):
+                assert torch.equal(g[key], ref[key]), (pause, key)
+    finally:
+        for k, v in zip(keys, old):
+            ngl.set_option(k, v)
