@@ -53,14 +53,14 @@ TRAVERSAL_BYTES = 16
 COUNTERS = {
     # both launches of the phased FP32 trace (first 24 evaluations, then the wide kernel)
     "k_sphere_trace": {"sources": ["ngl_trace_impl.h", "ngl_device.h", "ngl_mfma.h"],
-                       "sha256": "2f76f2212f173e4ae2b961278dd3f4e39514e0a3be0e5a9144490129104963a8",
-                       "fetch_kib": 584672.2 + 22290.9, "write_kib": 37844.4 + 4040.4},
+                       "sha256": "2b82478c21b49ee2c901a7b94dd38c58c05f20b5a44935f2817bf10d25234233",
+                       "fetch_kib": 585161.8 + 22342.9, "write_kib": 37967.3 + 4029.0},
     # k_query_coop, FP32 features and matrix-core decoder
     "k_query": {"sources": ["ngl_query_impl.h", "ngl_device.h", "ngl_mfma.h"],
                 "sha256": "2ae9a27a1469622257884d09aa4626e40a2f823f3232cd8f4e80f5f08f41f947",
-                "fetch_kib": 122302.1, "write_kib": 4096.0},
+                "fetch_kib": 122348.4, "write_kib": 4096.0},
 }
-FETCH_SCALE = (256 << 10) / 131088.0625
+FETCH_SCALE = (256 << 10) / 131087.625
 WRITE_SCALE = (256 << 10) / 262144.0
 
 
