@@ -42,6 +42,10 @@ __global__ void k_phase_init(unsigned* c) {
   if (threadIdx.x < 8) c[threadIdx.x] = 0u;
 }
 
+static int batch_by_width(const ngl_model& m, const BatchArgs& B, bool any_blend, hipStream_t s) {
+  NGL_BY_WIDTH(m.feat_dim, batch_run, m, B, any_blend, s)
+}
+
 static int buckets_by_width(const ngl_model& m, const BucketArgs& B, hipStream_t s) {
   NGL_BY_WIDTH(m.feat_dim, bucket_run, m, B, s)
 }
@@ -323,6 +327,13 @@ struct BatchLayout {
   int32_t* ray_off = nullptr;
   unsigned int* counters = nullptr;
   unsigned int* live = nullptr;
+  unsigned int* pcount = nullptr;
+  unsigned int* heads2 = nullptr;
+  float* st_t = nullptr;
+  int32_t* st_p = nullptr;
+  int32_t* st_k = nullptr;
+  float* st_prev = nullptr;
+  int32_t* pids = nullptr;
   char* trav_ws = nullptr;
   size_t trav_bytes = 0;
   size_t bytes = 0;
@@ -354,6 +365,13 @@ BatchLayout batch_layout(const ngl_view* views, int n, int64_t cap, void* ws) {
   L.ray_off = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * size_t(L.R_total + n)));
   L.counters = reinterpret_cast<unsigned int*>(take(sizeof(unsigned int) * NGL_MAX_BATCH));
   L.live = reinterpret_cast<unsigned int*>(take(sizeof(unsigned int) * NGL_MAX_BATCH));
+  L.pcount = reinterpret_cast<unsigned int*>(take(sizeof(unsigned int) * NGL_MAX_BATCH));
+  L.heads2 = reinterpret_cast<unsigned int*>(take(sizeof(unsigned int) * NGL_MAX_BATCH));
+  L.st_t = reinterpret_cast<float*>(take(sizeof(float) * size_t(L.R_total)));
+  L.st_p = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * size_t(L.R_total)));
+  L.st_k = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * size_t(L.R_total)));
+  L.st_prev = reinterpret_cast<float*>(take(sizeof(float) * size_t(L.R_total)));
+  L.pids = reinterpret_cast<int32_t*>(take(sizeof(int32_t) * size_t(L.R_total)));
   size_t tb = 0;
   ngl_trace_octree_workspace(L.R_max, cap, &tb);
   L.trav_bytes = tb;
@@ -404,7 +422,7 @@ int ngl_render_batch(const ngl_model* models, const void* table, const ngl_view*
   BatchInit I{};
   I.n = n;
   for (int i = 0; i < n; ++i) I.R[i] = int64_t(views[i].width) * views[i].height;
-  k_batch_init<<<1, 64, 0, s>>>(L.counters, L.live, I, frame_clock);
+  k_batch_init<<<1, 64, 0, s>>>(L.counters, L.live, I, frame_clock, L.pcount, L.heads2);
   NGL_LAUNCHED();
   // rays and hit lists, view by view (the traversal workspace is reused)
   for (int i = 0; i < n; ++i) {
@@ -440,7 +458,26 @@ int ngl_render_batch(const ngl_model* models, const void* table, const ngl_view*
   B.counters = L.counters;
   B.live = L.live;
   B.clock = frame_clock;
-  NGL_BY_WIDTH(m0.feat_dim, batch_run, m0, B, any_blend, s)
+  // Phased as ngl_sphere_trace: rays still running at the pause count are
+  // parked per view and finished by the lanes-per-ray kernel.
+  const int pause = option(NGL_OPT_TRACE_PAUSE1);
+  if (!(pause > 0 && pause < params->max_steps && option(NGL_OPT_TRACE_WIDE) == 1))
+    return batch_by_width(m0, B, any_blend, s);
+  B.pause_at = pause;
+  B.st_t = L.st_t;
+  B.st_p = L.st_p;
+  B.st_k = L.st_k;
+  B.st_prev = L.st_prev;
+  B.pids = L.pids;
+  B.pcount = L.pcount;
+  B.heads2 = L.heads2;
+  const int rc1 = batch_by_width(m0, B, any_blend, s);
+  if (rc1) return rc1;
+  BatchArgs C = B;
+  C.pause_at = 0;
+  C.resume = true;
+  C.wide = true;
+  return batch_by_width(m0, C, any_blend, s);
 }
 
 }  // extern "C"

@@ -646,7 +646,70 @@ struct BatchArgs {
   unsigned int* counters;   // [n] queue heads
   unsigned int* live;       // [n] unfinished rays
   uint64_t* clock;          // nullable [n+1]
+  // Phased (all zero/null otherwise): the first launch parks rays at
+  // evaluation pause_at into view v's range [base_v, base_v + R_v) of pids
+  // (count in pcount[v]); with `resume` the launch serves those instead,
+  // from queue heads heads2[v].  State arrays are indexed by base_v + ray.
+  int pause_at;
+  bool resume;
+  bool wide;  // host side: the wide (lanes-per-ray) kernel
+  float* st_t;
+  int32_t* st_p;
+  int32_t* st_k;
+  float* st_prev;
+  int32_t* pids;
+  unsigned int* pcount;     // [n]
+  unsigned int* heads2;     // [n]
 };
+
+// View v's queue of a batched launch (phase fields included).
+__device__ inline TraceArgs batch_view_args(const BatchArgs& B, int v) {
+  TraceArgs A{};
+  const int64_t base = B.view[v].base;
+  A.o = B.o + 3 * base;  // each view's rays are one SoA block
+  A.d = B.d + 3 * base;
+  A.stride = B.view[v].R;
+  A.base = base;
+  A.R = B.view[v].R;
+  A.lod = B.view[v].lod;
+  A.alpha = B.view[v].alpha;
+  A.pair_vox = B.pair_vox + int64_t(v) * B.cap;
+  A.t_in = B.t_in + int64_t(v) * B.cap;
+  A.t_out = B.t_out + int64_t(v) * B.cap;
+  A.ray_off = B.ray_off + base + v;
+  A.prm = B.prm;
+  A.t_hit = B.t_hit;
+  A.status = B.status;
+  A.steps = B.steps;
+  A.hit_vox = B.hit_vox;
+  A.counter = (B.resume ? B.heads2 : B.counters) + v;
+  A.live = B.live + v;
+  A.done_clock = B.clock ? B.clock + 1 + v : nullptr;
+  if (B.pause_at > 0 || B.resume) {
+    A.st_t = B.st_t + base;
+    A.st_p = B.st_p + base;
+    A.st_k = B.st_k + base;
+    A.st_prev = B.st_prev + base;
+  }
+  if (B.pause_at > 0) {
+    A.pause_at = B.pause_at;
+    A.parked = B.pids + base;
+    A.parked_n = B.pcount + v;
+  }
+  if (B.resume) {
+    A.resume = true;
+    A.ray_ids = B.pids + base;
+    A.bucket_counts = B.pcount + v;
+    A.bucket = 0;
+  }
+  return A;
+}
+
+// Rays still queued for view v in this launch.
+__device__ inline bool batch_view_has(const BatchArgs& B, int v) {
+  if (B.resume) return __atomic_load_n(&B.heads2[v], __ATOMIC_RELAXED) < __atomic_load_n(&B.pcount[v], __ATOMIC_RELAXED);
+  return int64_t(__atomic_load_n(&B.counters[v], __ATOMIC_RELAXED)) < B.view[v].R;
+}
 
 template <int M, typename FT, bool XYZ, int NW, class DEC>
 __global__ __launch_bounds__(64 * NW) void k_trace_batch(BatchArgs B) {
@@ -656,7 +719,7 @@ __global__ __launch_bounds__(64 * NW) void k_trace_batch(BatchArgs B) {
   const int H = B.table[0].hidden;
   for (int step = 0; step < B.n; ++step) {
     const int v = (int(blockIdx.x) + step) % B.n;
-    if (threadIdx.x == 0) s_has = int64_t(__atomic_load_n(&B.counters[v], __ATOMIC_RELAXED)) < B.view[v].R;
+    if (threadIdx.x == 0) s_has = batch_view_has(B, v);
     __syncthreads();
     if (!s_has) {
       __syncthreads();
@@ -668,26 +731,7 @@ __global__ __launch_bounds__(64 * NW) void k_trace_batch(BatchArgs B) {
       for (int w = threadIdx.x; w < int(sizeof(ngl_model) / 4); w += blockDim.x) dst[w] = src[w];
     }
     __syncthreads();
-    TraceArgs A{};
-    A.o = B.o + 3 * B.view[v].base;  // each view's rays are one SoA block
-    A.d = B.d + 3 * B.view[v].base;
-    A.stride = B.view[v].R;
-    A.base = B.view[v].base;
-    A.R = B.view[v].R;
-    A.lod = B.view[v].lod;
-    A.alpha = B.view[v].alpha;
-    A.pair_vox = B.pair_vox + int64_t(v) * B.cap;
-    A.t_in = B.t_in + int64_t(v) * B.cap;
-    A.t_out = B.t_out + int64_t(v) * B.cap;
-    A.ray_off = B.ray_off + B.view[v].base + v;
-    A.prm = B.prm;
-    A.t_hit = B.t_hit;
-    A.status = B.status;
-    A.steps = B.steps;
-    A.hit_vox = B.hit_vox;
-    A.counter = B.counters + v;
-    A.live = B.live + v;
-    A.done_clock = B.clock ? B.clock + 1 + v : nullptr;
+    const TraceArgs A = batch_view_args(B, v);
     const bool blend = A.alpha > 0.0f;
     DecLds<DEC> S(smem, H, blend);
     DEC::load(smd, A.lod, S.frag0, S.w2s0);
@@ -695,6 +739,43 @@ __global__ __launch_bounds__(64 * NW) void k_trace_batch(BatchArgs B) {
     __syncthreads();
     serve_queue<M, FT, XYZ, false, true, DEC>(smd, A, S, smd.b2[A.lod - 1], blend ? smd.b2[A.lod] : 0.0f);
     __syncthreads();  // every wavefront is done with this view's LDS
+  }
+}
+
+// Parked rays of a phased batch, eight lanes per ray (serve_queue_wide).
+template <int M, typename FT, bool XYZ, int NW, class DEC>
+__global__ __launch_bounds__(64 * NW) void k_trace_batch_wide(BatchArgs B) {
+  constexpr int G = wide_lanes<M>();
+  extern __shared__ __align__(16) char smem[];
+  __shared__ ngl_model smd;
+  __shared__ int s_has;
+  const int H = B.table[0].hidden;
+  for (int step = 0; step < B.n; ++step) {
+    const int v = (int(blockIdx.x) + step) % B.n;
+    if (threadIdx.x == 0) s_has = batch_view_has(B, v);
+    __syncthreads();
+    if (!s_has) {
+      __syncthreads();
+      continue;
+    }
+    {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(B.table + v);
+      uint32_t* dst = reinterpret_cast<uint32_t*>(&smd);
+      for (int w = threadIdx.x; w < int(sizeof(ngl_model) / 4); w += blockDim.x) dst[w] = src[w];
+    }
+    __syncthreads();
+    const TraceArgs A = batch_view_args(B, v);
+    const bool blend = A.alpha > 0.0f;
+    DecLds<DEC> S(smem, H, blend);
+    S.stage = reinterpret_cast<typename DEC::Stage*>(smem + DecLds<DEC>::fixed_bytes(H, true)) +
+              (threadIdx.x >> 6) * DEC::STAGE_ELEMS;
+    float* zbuf = reinterpret_cast<float*>(smem + DecLds<DEC>::fixed_bytes(H, true) + NW * DEC::STAGE_BYTES) +
+                  (threadIdx.x >> 6) * (64 / G) * (M + 1);
+    DEC::load(smd, A.lod, S.frag0, S.w2s0);
+    if (blend) DEC::load(smd, A.lod + 1, S.frag1, S.w2s1);
+    __syncthreads();
+    serve_queue_wide<M, FT, XYZ, DEC, G>(smd, A, S, zbuf, smd.b2[A.lod - 1], blend ? smd.b2[A.lod] : 0.0f);
+    __syncthreads();
   }
 }
 
@@ -908,9 +989,38 @@ static int launch_batch(const BatchArgs& B, bool any_blend, int H, hipStream_t s
   return launch_batch_nw<M, FT, XYZ, 1, DEC>(B, s, fixed + DEC::STAGE_BYTES);
 }
 
+template <int M, typename FT, bool XYZ, int NW, class DEC>
+static int launch_batch_wide_nw(const BatchArgs& B, hipStream_t s, size_t lds) {
+  static int per = 0;
+  static int cus = 0;
+  if (!per) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    const void* kern = reinterpret_cast<const void*>(&k_trace_batch_wide<M, FT, XYZ, NW, DEC>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
+  }
+  k_trace_batch_wide<M, FT, XYZ, NW, DEC><<<cus * per, 64 * NW, lds, s>>>(B);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
+template <int M, typename FT, bool XYZ, class DEC>
+static int launch_batch_wide(const BatchArgs& B, int H, hipStream_t s) {
+  const size_t fixed = DecLds<DEC>::fixed_bytes(H, true);
+  const size_t per_wave = DEC::STAGE_BYTES + size_t(64 / wide_lanes<M>()) * (M + 1) * 4;
+  if (fixed + 4 * per_wave <= 65536) return launch_batch_wide_nw<M, FT, XYZ, 4, DEC>(B, s, fixed + 4 * per_wave);
+  if (fixed + 2 * per_wave <= 65536) return launch_batch_wide_nw<M, FT, XYZ, 2, DEC>(B, s, fixed + 2 * per_wave);
+  return launch_batch_wide_nw<M, FT, XYZ, 1, DEC>(B, s, fixed + per_wave);
+}
+
 template <int M, typename FT, bool XYZ>
 struct BatchOp {
   static int run(const ngl_model& md, const BatchArgs& B, bool any_blend, hipStream_t s) {
+    if (B.wide) {
+      if (md.w_dtype == NGL_BF16) return launch_batch_wide<M, FT, XYZ, DecBF16<M, XYZ>>(B, md.hidden, s);
+      return launch_batch_wide<M, FT, XYZ, DecF32<M, XYZ>>(B, md.hidden, s);
+    }
     if (md.w_dtype == NGL_BF16) return launch_batch<M, FT, XYZ, DecBF16<M, XYZ>>(B, any_blend, md.hidden, s);
     return launch_batch<M, FT, XYZ, DecF32<M, XYZ>>(B, any_blend, md.hidden, s);
   }
@@ -921,11 +1031,14 @@ struct BatchInit {
   int64_t R[NGL_MAX_BATCH];
 };
 
-static __global__ void k_batch_init(unsigned int* counters, unsigned int* live, BatchInit I, uint64_t* clock) {
+static __global__ void k_batch_init(unsigned int* counters, unsigned int* live, BatchInit I, uint64_t* clock,
+                                    unsigned int* pcount, unsigned int* heads2) {
   const int i = threadIdx.x;
   if (i < I.n) {
     counters[i] = 0u;
     live[i] = unsigned(I.R[i]);
+    pcount[i] = 0u;
+    heads2[i] = 0u;
   }
   if (i == 0 && clock) clock[0] = wall_clock64();
 }

@@ -121,3 +121,43 @@ def test_autotuner_applies_a_valid_config(tmp_path):
         torch.cuda.synchronize()
     finally:
         autotune.apply(saved)
+
+
+def phased_batch_run():
+    import torch
+    from paper_2101_10994_amd import ngl
+    cases = batch_cases()
+    models = [c.gpu_model() for c in cases]
+    rng = np.random.default_rng(5)
+    views = []
+    for i, c in enumerate(cases):
+        cam = W.camera_on_sphere(rng, 2.6, 128, 96)
+        views.append(ngl.make_view(cam.eye, cam.width, cam.height, c.L - 1, 0.5 if i % 2 else 0.0))
+    br = ngl.BatchRenderer(models, views, pair_capacity=1 << 20)
+    br.render(100, 1e-4)
+    torch.cuda.synchronize()
+    assert not br.overflowed()
+    assert int((br.steps > 4).sum()) > 100
+    return {"t": br.t.clone(), "status": br.status.clone(), "steps": br.steps.clone(), "hit_vox": br.hit_vox.clone()}
+
+
+def test_phased_batch_is_bitwise_the_single_launch():
+    """The batched render parks rays at the pause count per view and
+    finishes them eight lanes per ray: outputs equal the one-phase launch
+    bit for bit."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    keys = (ngl.OPT_TRACE_PAUSE1, ngl.OPT_TRACE_WIDE)
+    old = [ngl.get_option(k) for k in keys]
+    try:
+        ngl.set_option(ngl.OPT_TRACE_PAUSE1, 0)
+        ref = phased_batch_run()
+        ngl.set_option(ngl.OPT_TRACE_WIDE, 1)
+        for pause in (24, 4):
+            ngl.set_option(ngl.OPT_TRACE_PAUSE1, pause)
+            got = phased_batch_run()
+            for key in ("t", "status", "steps", "hit_vox"):
+                assert torch.equal(got[key], ref[key]), (pause, key)
+    finally:
+        for k, v in zip(keys, old):
+            ngl.set_option(k, v)
