@@ -137,6 +137,9 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
   // coop_level); with 16-bit features one lane per ray measured faster
   constexpr bool COOP = MFMA && !ANALYTIC && NGL_TRACE_COOP && std::is_same<FT, F32>::value;
   int ray = -1, p = 0, e = 0, k = 0, cp = -1;
+  // the current pair's t_in, t_out and voxel, loaded together when p moves
+  int pc = -1, v_c = -1;
+  float tin_c = 0.0f, tout_c = 0.0f;
   bool ready = false;
   float t = 0.0f, prev = __builtin_inff();
   float oo[3] = {0.0f, 0.0f, 0.0f}, dd[3] = {0.0f, 0.0f, 0.0f};
@@ -180,6 +183,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
             e = A.ray_off[ray + 1];
             k = 0;
             cp = -1;
+            pc = -1;
             prev = __builtin_inff();
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -201,11 +205,20 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
         }
       }
       if (ray >= 0 && !ready) {
-        while (p < e && t > A.t_out[p]) ++p;  // empty space: next voxel
+        while (p < e) {  // empty space: next voxel
+          if (p != pc) {
+            tin_c = A.t_in[p];
+            tout_c = A.t_out[p];
+            v_c = A.pair_vox[p];
+            pc = p;
+          }
+          if (t > tout_c) ++p;
+          else break;
+        }
         if (p == e) {
           NGL_FINISH(NGL_RAY_MISS, -1);
         } else {
-          const float ti = A.t_in[p];
+          const float ti = tin_c;
           if (t < ti) t = ti;  // outside the voxel: jump to its entry
           if (t > A.prm.t_far) NGL_FINISH(NGL_RAY_FAR, -1);
           else if (k == A.prm.max_steps) NGL_FINISH(NGL_RAY_MAX_STEPS, -1);
@@ -241,7 +254,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
         x[0] = fmaf(t, dd[0], oo[0]);
         x[1] = fmaf(t, dd[1], oo[1]);
         x[2] = fmaf(t, dd[2], oo[2]);
-        v = A.pair_vox[p];
+        v = v_c;
         if constexpr (ANALYTIC) {
           const float q0 = x[0] - A.prm.sphere[0], q1 = x[1] - A.prm.sphere[1], q2 = x[2] - A.prm.sphere[2];
           dist = sqrtf(q0 * q0 + q1 * q1 + q2 * q2) - A.prm.sphere[3];
@@ -416,6 +429,9 @@ __device__ __forceinline__ void serve_queue_wide(const ngl_model& md, const Trac
   const int H = md.hidden;
   // ray state, the same in every lane of a group
   int ray = -1, p = 0, e = 0, k = 0, cp = -1;
+  // the current pair's t_in, t_out and voxel, loaded together when p moves
+  int pc = -1, v_c = -1;
+  float tin_c = 0.0f, tout_c = 0.0f;
   bool ready = false;
   float t = 0.0f, prev = __builtin_inff();
   float oo[3] = {0.0f, 0.0f, 0.0f}, dd[3] = {0.0f, 0.0f, 0.0f};
@@ -460,6 +476,7 @@ __device__ __forceinline__ void serve_queue_wide(const ngl_model& md, const Trac
           e = A.ray_off[ray + 1];
           k = 0;
           cp = -1;
+          pc = -1;
           prev = __builtin_inff();
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
@@ -480,11 +497,20 @@ __device__ __forceinline__ void serve_queue_wide(const ngl_model& md, const Trac
         }
       }
       if (ray >= 0 && !ready) {
-        while (p < e && t > A.t_out[p]) ++p;
+        while (p < e) {  // empty space: next voxel
+          if (p != pc) {
+            tin_c = A.t_in[p];
+            tout_c = A.t_out[p];
+            v_c = A.pair_vox[p];
+            pc = p;
+          }
+          if (t > tout_c) ++p;
+          else break;
+        }
         if (p == e) {
           NGL_FINISH_W(NGL_RAY_MISS, -1);
         } else {
-          const float ti = A.t_in[p];
+          const float ti = tin_c;
           if (t < ti) t = ti;
           if (t > A.prm.t_far) NGL_FINISH_W(NGL_RAY_FAR, -1);
           else if (k == A.prm.max_steps) NGL_FINISH_W(NGL_RAY_MAX_STEPS, -1);
@@ -520,7 +546,7 @@ __device__ __forceinline__ void serve_queue_wide(const ngl_model& md, const Trac
         x[0] = fmaf(t, dd[0], oo[0]);
         x[1] = fmaf(t, dd[1], oo[1]);
         x[2] = fmaf(t, dd[2], oo[2]);
-        v = A.pair_vox[p];
+        v = v_c;
         if (v < 0 || int64_t(v) >= nv_t) {
           NGL_FINISH_W(NGL_RAY_INVALID, -1);
         } else {
