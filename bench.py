@@ -53,14 +53,14 @@ TRAVERSAL_BYTES = 16
 COUNTERS = {
     # both launches of the phased FP32 trace (first 24 evaluations, then the wide kernel)
     "k_sphere_trace": {"sources": ["ngl_trace_impl.h", "ngl_device.h", "ngl_mfma.h"],
-                       "sha256": "2b82478c21b49ee2c901a7b94dd38c58c05f20b5a44935f2817bf10d25234233",
-                       "fetch_kib": 585161.8 + 22342.9, "write_kib": 37967.3 + 4029.0},
+                       "sha256": "b3e62dcbe54c211863b933e63da94edeb50220b31f1ab3b049a8f2eae5645e4b",
+                       "fetch_kib": 220508.6 + 24205.4, "write_kib": 39021.9 + 3657.4},
     # k_query_coop, FP32 features and matrix-core decoder
     "k_query": {"sources": ["ngl_query_impl.h", "ngl_device.h", "ngl_mfma.h"],
                 "sha256": "2ae9a27a1469622257884d09aa4626e40a2f823f3232cd8f4e80f5f08f41f947",
-                "fetch_kib": 122348.4, "write_kib": 4096.0},
+                "fetch_kib": 122333.3, "write_kib": 4096.0},
 }
-FETCH_SCALE = (256 << 10) / 131087.625
+FETCH_SCALE = (256 << 10) / 131088.0625
 WRITE_SCALE = (256 << 10) / 262144.0
 
 
