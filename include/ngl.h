@@ -90,6 +90,9 @@ int ngl_version(void);
  *  NGL_OPT_COOP_GATHER: 1 (default) = the matrix-core query kernel
  *    gathers each feature row with M/8 lanes holding 8 elements each,
  *    0 = one lane per point reads whole rows (same results).
+ *  NGL_OPT_QUERY_BLOCKS_PER_CU: blocks per compute unit of the
+ *    cooperative query kernel, whose blocks loop over the points (0..64;
+ *    0 = as many as are resident at once, default).
  * NGL_E_INVALID for an unknown option or value. */
 typedef enum {
   NGL_OPT_F32_DECODER = 0,
@@ -99,7 +102,8 @@ typedef enum {
   NGL_OPT_TRACE_PAUSE2 = 4,
   NGL_OPT_TRACE_WIDE = 5,
   NGL_OPT_COOP_GATHER = 6,
-  NGL_OPT_COUNT = 7
+  NGL_OPT_QUERY_BLOCKS_PER_CU = 7,
+  NGL_OPT_COUNT = 8
 } ngl_option;
 int ngl_set_option(int option, int value);
 int ngl_get_option(int option, int* value);

@@ -8,7 +8,7 @@ namespace ngl {
 static thread_local std::string g_last_error;
 
 // Library options; defaults are the fastest measured choices.
-static std::atomic<int> g_options[NGL_OPT_COUNT] = {{1}, {0}, {0}, {24}, {0}, {1}, {1}};
+static std::atomic<int> g_options[NGL_OPT_COUNT] = {{1}, {0}, {0}, {24}, {0}, {1}, {1}, {0}};
 
 int option(int key) { return (key >= 0 && key < NGL_OPT_COUNT) ? g_options[key].load() : 0; }
 
@@ -83,6 +83,8 @@ int ngl_set_option(int key, int value) {
     NGL_REQUIRE(value >= 0 && value <= 4096, "NGL_OPT_TRACE_PAUSE1/2 take 0..4096");
   if (key == NGL_OPT_TRACE_WIDE) NGL_REQUIRE(value == 0 || value == 1, "NGL_OPT_TRACE_WIDE takes 0 or 1");
   if (key == NGL_OPT_COOP_GATHER) NGL_REQUIRE(value == 0 || value == 1, "NGL_OPT_COOP_GATHER takes 0 or 1");
+  if (key == NGL_OPT_QUERY_BLOCKS_PER_CU)
+    NGL_REQUIRE(value >= 0 && value <= 64, "NGL_OPT_QUERY_BLOCKS_PER_CU takes 0..64");
   ngl::g_options[key].store(value);
   return NGL_OK;
 }

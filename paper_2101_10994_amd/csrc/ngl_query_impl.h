@@ -256,8 +256,20 @@ template <int M, typename FT, bool XYZ, int NW, class DEC>
 static int launch_query_coop_nw(const ngl_model& md, const float* x, int64_t P, int lod, float alpha,
                                 const float* app, float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s,
                                 size_t lds) {
+  // Grid-stride over the points with one round of resident blocks (each
+  // stages the decoder once), or at most NGL_OPT_QUERY_BLOCKS_PER_CU per CU.
+  static int cus = 0, per = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    const void* kern = reinterpret_cast<const void*>(&k_query_coop<M, FT, XYZ, NW, DEC>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
+  }
+  const int bpc = option(NGL_OPT_QUERY_BLOCKS_PER_CU);
   int64_t grid = (P + 64 * NW - 1) / (64 * NW);
-  if (grid > 4096) grid = 4096;
+  const int64_t cap = int64_t(cus) * (bpc > 0 ? bpc : per);
+  if (grid > cap) grid = cap;
   k_query_coop<M, FT, XYZ, NW, DEC><<<unsigned(grid), 64 * NW, lds, s>>>(md, x, P, lod, alpha, app, sdf, valid, vox);
   NGL_LAUNCHED();
   return NGL_OK;

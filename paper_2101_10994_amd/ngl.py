@@ -132,7 +132,7 @@ def lib():
 
 
 (OPT_F32_DECODER, OPT_TRACE_WAVES, OPT_TRACE_BLOCKS_PER_CU, OPT_TRACE_PAUSE1, OPT_TRACE_PAUSE2,
- OPT_TRACE_WIDE, OPT_COOP_GATHER) = 0, 1, 2, 3, 4, 5, 6
+ OPT_TRACE_WIDE, OPT_COOP_GATHER, OPT_QUERY_BLOCKS_PER_CU) = 0, 1, 2, 3, 4, 5, 6, 7
 MAX_BATCH = 32
 
 
