@@ -432,15 +432,33 @@ __global__ __launch_bounds__(64 * NW) void k_normals(ngl_model md, NormalArgs A)
   }
 }
 
+template <int M, typename FT, bool XYZ, class DEC, bool MFMA, int NW>
+static int launch_normals_nw(const ngl_model& md, const NormalArgs& A, hipStream_t s, size_t lds) {
+  // one round of resident blocks looping over the points (each stages the
+  // decoders once)
+  static int cus = 0, per = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      cus = 256;
+    const void* kern = reinterpret_cast<const void*>(&k_normals<M, FT, XYZ, NW, DEC, MFMA>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
+  }
+  int64_t grid = (A.P + 64 * NW - 1) / (64 * NW);
+  if (grid > int64_t(cus) * per) grid = int64_t(cus) * per;
+  k_normals<M, FT, XYZ, NW, DEC, MFMA><<<unsigned(grid), 64 * NW, lds, s>>>(md, A);
+  NGL_LAUNCHED();
+  return NGL_OK;
+}
+
 template <int M, typename FT, bool XYZ, class DEC, bool MFMA>
 static int launch_normals(const ngl_model& md, const NormalArgs& A, hipStream_t s) {
   const bool blend = A.alpha > 0.0f;
-  const size_t lds = MFMA ? DecLds<DEC>::fixed_bytes(md.hidden, blend) + 2 * DEC::STAGE_BYTES : 0;
-  int64_t grid = (A.P + 127) / 128;
-  if (grid > 4096) grid = 4096;
-  k_normals<M, FT, XYZ, 2, DEC, MFMA><<<unsigned(grid), 128, lds, s>>>(md, A);
-  NGL_LAUNCHED();
-  return NGL_OK;
+  if constexpr (!MFMA) return launch_normals_nw<M, FT, XYZ, DEC, false, 2>(md, A, s, 0);
+  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, blend);
+  if (fixed + 4 * DEC::STAGE_BYTES <= 65536)
+    return launch_normals_nw<M, FT, XYZ, DEC, MFMA, 4>(md, A, s, fixed + 4 * DEC::STAGE_BYTES);
+  return launch_normals_nw<M, FT, XYZ, DEC, MFMA, 2>(md, A, s, fixed + 2 * DEC::STAGE_BYTES);
 }
 
 template <int M, typename FT, bool XYZ>
