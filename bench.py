@@ -54,13 +54,13 @@ COUNTERS = {
     # both launches of the phased FP32 trace (first 24 evaluations, then the wide kernel)
     "k_sphere_trace": {"sources": ["ngl_trace_impl.h", "ngl_device.h", "ngl_mfma.h"],
                        "sha256": "b3e62dcbe54c211863b933e63da94edeb50220b31f1ab3b049a8f2eae5645e4b",
-                       "fetch_kib": 220508.6 + 24205.4, "write_kib": 39021.9 + 3657.4},
+                       "fetch_kib": 220675.5 + 24850.8, "write_kib": 38948.4 + 3662.1},
     # k_query_coop, FP32 features and matrix-core decoder
     "k_query": {"sources": ["ngl_query_impl.h", "ngl_device.h", "ngl_mfma.h"],
-                "sha256": "2ae9a27a1469622257884d09aa4626e40a2f823f3232cd8f4e80f5f08f41f947",
-                "fetch_kib": 122333.3, "write_kib": 4096.0},
+                "sha256": "ea9654b73c633fa82bb86ffd497b9c19bb034b838e22a5e4b87897d383b47cc2",
+                "fetch_kib": 113972.5, "write_kib": 4096.0},
 }
-FETCH_SCALE = (256 << 10) / 131088.0625
+FETCH_SCALE = (256 << 10) / 131088.0
 WRITE_SCALE = (256 << 10) / 262144.0
 
 
