@@ -85,3 +85,21 @@ def test_options():
             ngl.set_option(key, -1)
     with pytest.raises(ngl.NGLError):
         ngl.set_option(ngl.OPT_TRACE_WIDE, 2)
+
+
+def test_phased_trace_workspace_sizes():
+    """Workspace queries of the phased tracers: 256 B of counters plus one
+    256-byte-aligned array per parked-state field and id list (host only)."""
+    import ctypes as C
+    from paper_2101_10994_amd import ngl
+    lib = ngl.lib()
+    al = lambda b: (b + 255) // 256 * 256
+    for R in (0, 1, 1000, 1 << 20):
+        nb = C.c_size_t()
+        assert lib.ngl_sphere_trace_workspace_rays(R, C.addressof(nb)) == 0
+        assert nb.value == 256 + 6 * al(4 * R)
+        assert lib.ngl_sphere_trace_lod_workspace(R, C.addressof(nb)) == 0
+        assert nb.value == 256 + 2 * al(4 * R) + al(R) + 5 * al(4 * R)
+    nb = C.c_size_t()
+    assert lib.ngl_sphere_trace_workspace_rays(-1, C.addressof(nb)) == 1
+    assert lib.ngl_sphere_trace_lod_workspace(-1, C.addressof(nb)) == 1
