@@ -161,7 +161,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the hot path is single-GPU (one process per GPU would replicate the "
-              "octree and shard rays/points; no multi-GPU run is part of this build). Use --gpus 1.",
+              "octree and shard rays/points; that form is not implemented). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

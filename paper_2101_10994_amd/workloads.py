@@ -8,8 +8,7 @@ construction, no traversal, no interpolation, no decoder), so it can feed
 both the GPU library and the CPU oracle without coupling them.
 
 Shapes stand in for the paper's meshes (ShapeNet / Thingi / TurboSquid,
-Section 4.1), which are not available; the recipes follow the workload
-descriptions in the repository's DESIGN notes:
+Section 4.1), which are not available; the recipes:
 
 * occupancy: a finest voxel is occupied iff |SDF(centre)| is strictly below
   the voxel diagonal (a voxel exists only where there is surface, Sec. 3.2);
