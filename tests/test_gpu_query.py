@@ -225,3 +225,26 @@ def test_coop_gather_is_bitwise_the_lane_gather(name, f32_decoder):
                     assert torch.equal(outs[0][k], outs[1][k]), (P, lod, alpha, pp is not None, k)
     finally:
         ngl.set_option(ngl.OPT_COOP_GATHER, old)
+
+
+def test_query_grid_shapes_give_the_same_bits():
+    """The cooperative query loops its resident blocks over the points: any
+    number of blocks per CU gives the same outputs (ragged sizes too)."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    case = make_case(W.paper_shape(0), 64, 5, 32, 128)
+    gm = case.gpu_model()
+    rng = np.random.default_rng(12)
+    old = ngl.get_option(ngl.OPT_QUERY_BLOCKS_PER_CU)
+    try:
+        for P in (1, 1000, 300_001):
+            x = torch.from_numpy(rng.uniform(-1.1, 1.1, (3, P)).astype(np.float32)).cuda()
+            outs = []
+            for bpc in (0, 1, 3, 64):
+                ngl.set_option(ngl.OPT_QUERY_BLOCKS_PER_CU, bpc)
+                outs.append(ngl.query_sdf(gm, x, 5, alpha=0.0, want_valid=True, want_vox=True))
+            for o in outs[1:]:
+                for k in ("sdf", "valid", "vox"):
+                    assert torch.equal(o[k], outs[0][k]), (P, k)
+    finally:
+        ngl.set_option(ngl.OPT_QUERY_BLOCKS_PER_CU, old)
