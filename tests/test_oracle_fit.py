@@ -98,6 +98,55 @@ def test_training_points_structure_and_statistics():
     assert 0.5 * sigma < np.median(np.abs(tg[(c == 2) | (c == 3)])) < 1.5 * sigma
 
 
+def test_near_offsets_are_isotropic_standard_normal():
+    """The near-surface offsets (training appendix, Sampling: surface points
+    moved by isotropic Gaussian noise) are sigma times a standard normal
+    vector in R^3: independent N(0,1) components.  Each check below is one
+    the two-value Box-Muller pairing can get wrong while every per-axis
+    mean and variance stays right (a reused angle correlates two axes, a
+    reused radius couples the squared components of all three)."""
+    from scipy import stats
+    shape = W.paper_shape(0)
+    rng = np.random.default_rng(5)
+    u = rng.uniform(0, 1, (5, 40000)).astype(np.float32)
+    s = oracle.sample_surface(shape.spheres, shape.tori, u, 200, 1e-6)
+    S = s["points"][:, s["hit"]]
+    N = 100000
+    uni = rng.uniform(0, 1, (4, N)).astype(np.float32)
+    sigma = 0.25  # large against FP32 rounding of the stored points
+    xs, _ = oracle.training_points(shape.spheres, shape.tori, S, uni, sigma)
+    c = np.arange(N) % 5
+    q = np.arange(N) // 5
+    near = (c == 2) | (c == 3)
+    k = (2 * q + (c - 2))[near] % S.shape[1]
+    g = (xs[:, near].astype(np.float64) - S[:, k]) / sigma
+    n = g.shape[1]
+    # FP32 storage of x moves g by at most 2^-24 |x| / sigma < 1e-6
+    se = 1.0 / np.sqrt(n)
+    # covariance = identity (a shared angle gives correlation +-1)
+    cov = g @ g.T / n
+    np.testing.assert_allclose(np.diag(cov), 1.0, atol=8 * np.sqrt(2) * se)
+    off = cov[~np.eye(3, dtype=bool)]
+    assert np.all(np.abs(off) < 6 * se), off
+    # squared components uncorrelated: cov(g_a^2, g_b^2) = 0 for independent
+    # normals (a shared radius gives E r^4 / 4 - 1 = 1); each estimate has
+    # standard error sqrt(8 / n)
+    g2 = g * g
+    c2 = np.cov(g2)
+    assert np.all(np.abs(c2[~np.eye(3, dtype=bool)]) < 6 * np.sqrt(8.0) * se), c2
+    # |g|^2 follows chi-square with 3 degrees of freedom: mean 3, variance 6
+    r2 = g2.sum(0)
+    assert abs(r2.mean() - 3.0) < 6 * np.sqrt(6.0) * se
+    assert abs(r2.var() - 6.0) < 0.3
+    assert stats.kstest(r2, stats.chi2(3).cdf).pvalue > 1e-4
+    # the direction g/|g| is uniform on the sphere: E[n n^T] = I/3
+    nd = g / np.sqrt(r2)
+    np.testing.assert_allclose(nd @ nd.T / n, np.eye(3) / 3, atol=6 * se)
+    # offsets do not depend on which surface sample they perturb
+    for a in range(3):
+        assert abs(np.corrcoef(g[a], k)[0, 1]) < 6 * se
+
+
 def test_lod_weights_are_linear():
     ijk = W.occupancy_ijk(W.tiny_shape(), 16)
     t = oracle.Octree(ijk, 3)
