@@ -80,7 +80,9 @@ int ngl_version(void);
  *  NGL_OPT_TRACE_WAVES: wavefronts per block of the matrix-core tracers
  *    (1, 2 or 4; 0 = the most that fit in 64 KB of LDS, default).
  *  NGL_OPT_TRACE_BLOCKS_PER_CU: cap on resident tracer blocks per compute
- *    unit (0 = occupancy limit, default).
+ *    unit (0 = occupancy limit, default), applied to every persistent
+ *    tracer launch (one-lane and lanes-per-ray phases, batched views, LOD
+ *    groups).
  *  NGL_OPT_TRACE_PAUSE1, NGL_OPT_TRACE_PAUSE2: evaluation counts at which
  *    a phased ngl_sphere_trace parks the rays still running (0..4096, 0 =
  *    no such phase; a second count not above the first is ignored).
@@ -194,7 +196,31 @@ typedef struct {
   const float* b2;                           /* device, [L] */
   const int32_t* corner_adj_off[NGL_MAX_LODS]; /* device, training only: CSR of corner -> 8*v+j */
   const int32_t* corner_adj[NGL_MAX_LODS];
+  /* device, nullable: decoder l's first layer [W1 | b1] pre-packed by
+   * ngl_pack_decoders in the fragment order of the matrix-core decoder; when
+   * set, kernels copy it instead of rebuilding the fragments from W1 and b1
+   * in every block.  Must be re-packed whenever W1 or b1 change. */
+  const void* W1_packed[NGL_MAX_LODS];
 } ngl_model;
+
+/* Decoder weights in matrix-core fragment order (Eq. 2's first layer,
+ * Sec. 4.1's 35 -> h -> 1 decoder).  For BF16 weights (w_dtype NGL_BF16) the
+ * fragments of v_mfma_f32_16x16x32_bf16: per hidden tile of 16 rows, one
+ * 32-column feature step per 32 features, then one step holding
+ * [W1_x, W1_x, b1_hi, b1_lo] (the position weights twice, for the high and
+ * low parts of x, and b1 split into two BF16 values); for FP32 weights the
+ * fragments of v_mfma_f32_16x16x4f32 over [W1 | b1].  Each lane's part of a
+ * fragment is stored contiguously (16 bytes for BF16, 4 for FP32), 64 lanes
+ * per fragment.
+ * ngl_packed_decoder_bytes: bytes for all num_lods decoders (a multiple of
+ * 256 per LOD).  ngl_pack_decoders writes them into `packed` (device,
+ * 256-byte aligned, at least that many bytes, caller-owned) and sets
+ * m->W1_packed[l] to decoder l+1's part.  The packed form does not depend on
+ * NGL_OPT_F32_DECODER (the per-lane FP32 form ignores it).
+ * Errors: NGL_E_INVALID for a bad model, null or misaligned buffer, or too
+ * few bytes. */
+int ngl_packed_decoder_bytes(const ngl_model* m, size_t* bytes);
+int ngl_pack_decoders(ngl_model* m, void* packed, size_t bytes, void* stream);
 
 /* ------------------------------------------------------------------ */
 /* 2. SDF query (Sec. 3.2, Eq. 2; continuous LOD, Eq. 3)                  */
@@ -212,7 +238,9 @@ typedef struct {
  * Outputs (device): sdf[P]; valid[P] (nullable): 1 iff the level-L' voxel
  * exists; vox_out[L'][P] (nullable): voxel index per level, -1 if absent.
  * The decoder's first layer runs in FP32 when w_dtype is F32 and on the
- * BF16 matrix cores with FP32 accumulation when w_dtype is BF16.
+ * BF16 matrix cores with FP32 accumulation when w_dtype is BF16: the BF16
+ * weights are used as stored and every FP32 input (z, x, b1) enters as the
+ * sum of two BF16 values (relative representation error 2^-16).
  * Errors: NGL_E_INVALID for lod outside 1..num_lods, alpha outside [0,1),
  * blending at lod == num_lods, or null required pointers. */
 int ngl_query_sdf(const ngl_model* m, const float* x, int64_t P, int32_t lod, float alpha,
@@ -224,7 +252,8 @@ int ngl_query_sdf(const ngl_model* m, const float* x, int64_t P, int32_t lod, fl
  * (required iff with_xyz, else ignored); z: device [P][feat_dim] rows,
  * z_dtype NGL_F32 or NGL_BF16, 16-byte aligned; sdf: device [P] FP32.  The
  * decoder form follows the model's weights as in ngl_query_sdf (BF16
- * weights: matrix cores with BF16 inputs; FP32: NGL_OPT_F32_DECODER).
+ * weights: matrix cores, BF16 rows used as stored, FP32 rows split into two
+ * BF16 parts; FP32: NGL_OPT_F32_DECODER).
  * Errors: NGL_E_INVALID for bad arguments, NGL_E_UNSUPPORTED for an
  * uncompiled feat_dim. */
 int ngl_decode_sdf(const ngl_model* m, int32_t lod, const float* x, const void* z, int32_t z_dtype, int64_t P,
@@ -504,6 +533,30 @@ int ngl_train_fwd_bwd_lods(const ngl_model* m, const float* x, const float* targ
                            const float* lod_weight, float* loss, float* sdf_all, float* const* dfeat,
                            float* const* dW1, float* const* db1, float* const* dw2, float* db2, void* ws,
                            size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ */
+/* 6. Workspace sizes in one call                                        */
+/* ------------------------------------------------------------------ */
+typedef enum {
+  NGL_OP_TRACE_OCTREE = 0,        /* n = rays, aux = pair capacity per depth */
+  NGL_OP_SPHERE_TRACE = 1,        /* n = rays: the phased trace's workspace */
+  NGL_OP_SPHERE_TRACE_LOD = 2,    /* n = rays */
+  NGL_OP_TRAIN = 3,               /* n = points; needs the model */
+  NGL_OP_SAMPLE_SURFACE = 4,      /* n = candidate rays */
+  NGL_OP_OCTREE_BUILD_DEVICE = 5, /* n = occupied cells, aux = num_lods */
+  NGL_OP_PACK_DECODERS = 6        /* bytes of ngl_pack_decoders; needs the model */
+} ngl_op;
+
+/* Device bytes the call `op` needs for n items: the same value as that
+ * call's own size query (ngl_trace_octree_workspace,
+ * ngl_sphere_trace_workspace_rays, ngl_sphere_trace_lod_workspace,
+ * ngl_train_workspace, ngl_sample_surface_workspace,
+ * ngl_octree_build_device_workspace, ngl_packed_decoder_bytes), so a caller
+ * can size every buffer through one entry point.  m may be NULL except for
+ * NGL_OP_TRAIN and NGL_OP_PACK_DECODERS.  The batched render's workspace
+ * depends on its views and has its own query (ngl_render_batch_workspace).
+ * NGL_E_INVALID for an unknown op, negative sizes or a missing model. */
+int ngl_workspace_bytes(int op, const ngl_model* m, int64_t n, int64_t aux, size_t* bytes);
 
 #ifdef __cplusplus
 }

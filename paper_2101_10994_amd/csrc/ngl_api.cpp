@@ -2,6 +2,9 @@
 #include "ngl_common.h"
 
 #include <atomic>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace ngl {
 
@@ -11,6 +14,31 @@ static thread_local std::string g_last_error;
 static std::atomic<int> g_options[NGL_OPT_COUNT] = {{1}, {0}, {0}, {24}, {0}, {1}, {1}, {0}};
 
 int option(int key) { return (key >= 0 && key < NGL_OPT_COUNT) ? g_options[key].load() : 0; }
+
+int resident_grid(const void* kern, int threads, size_t lds, int cap) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, const void*, int, size_t>, std::pair<int, int>> cache;  // -> (CUs, per CU)
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  const auto key = std::make_tuple(dev, kern, threads, lds);
+  std::pair<int, int> v;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      v = it->second;
+    } else {
+      int cus = 0, per = 0;
+      if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, threads, lds) != hipSuccess || per < 1) per = 1;
+      v = std::make_pair(cus, per);
+      cache.emplace(key, v);
+    }
+  }
+  const int per = (cap > 0 && cap < v.second) ? cap : v.second;
+  return v.first * per;
+}
 
 void set_error(const char* fmt, ...) {
   char buf[1024];
@@ -87,6 +115,27 @@ int ngl_set_option(int key, int value) {
     NGL_REQUIRE(value >= 0 && value <= 64, "NGL_OPT_QUERY_BLOCKS_PER_CU takes 0..64");
   ngl::g_options[key].store(value);
   return NGL_OK;
+}
+
+int ngl_workspace_bytes(int op, const ngl_model* m, int64_t n, int64_t aux, size_t* bytes) {
+  NGL_REQUIRE(bytes != nullptr, "bytes is null");
+  NGL_REQUIRE(n >= 0 && aux >= 0, "negative size");
+  switch (op) {
+    case NGL_OP_TRACE_OCTREE: return ngl_trace_octree_workspace(n, aux, bytes);
+    case NGL_OP_SPHERE_TRACE: return ngl_sphere_trace_workspace_rays(n, bytes);
+    case NGL_OP_SPHERE_TRACE_LOD: return ngl_sphere_trace_lod_workspace(n, bytes);
+    case NGL_OP_TRAIN:
+      NGL_REQUIRE(m != nullptr, "NGL_OP_TRAIN needs the model");
+      return ngl_train_workspace(m, n, bytes);
+    case NGL_OP_SAMPLE_SURFACE: return ngl_sample_surface_workspace(n, bytes);
+    case NGL_OP_OCTREE_BUILD_DEVICE:
+      NGL_REQUIRE(aux >= 1 && aux <= NGL_MAX_LODS, "aux (num_lods) %lld outside 1..%d", (long long)aux, NGL_MAX_LODS);
+      return ngl_octree_build_device_workspace(n, int32_t(aux), bytes);
+    case NGL_OP_PACK_DECODERS:
+      NGL_REQUIRE(m != nullptr, "NGL_OP_PACK_DECODERS needs the model");
+      return ngl_packed_decoder_bytes(m, bytes);
+    default: NGL_FAIL(NGL_E_INVALID, "unknown op %d", op);
+  }
 }
 
 int ngl_get_option(int key, int* value) {

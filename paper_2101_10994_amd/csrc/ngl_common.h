@@ -43,6 +43,13 @@ void set_error(const char* fmt, ...);
 // Current value of a library option (ngl_set_option).
 int option(int key);
 
+// Grid of a persistent launch: the blocks of `kern` that can be resident at
+// once with `threads` threads and `lds` bytes of dynamic LDS per block, on
+// every CU of the current device; with cap > 0 at most `cap` blocks per CU.
+// Cached per (device, kernel, threads, lds), so launches with different
+// LDS sizes (one or two staged decoders) each get their own occupancy.
+int resident_grid(const void* kern, int threads, size_t lds, int cap);
+
 // Checks the structural fields of a model view used by every device call.
 int check_model(const ngl_model* m, bool need_features);
 

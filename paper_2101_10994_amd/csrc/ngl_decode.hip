@@ -21,15 +21,16 @@ struct DecodeArgs {
   float* sdf;      // [P]
 };
 
-// Eight consecutive features f0..f0+7 of row p as BF16 bits (RNE from FP32).
+// Eight consecutive features f0..f0+7 of row p as BF16 bits: BF16 rows as
+// stored (lo = 0); FP32 rows split into high parts and residuals.
 template <int M, typename ZT>
-__device__ inline uint4 load_z8(const void* z, int64_t p, int f0) {
+__device__ inline void load_z8(const void* z, int64_t p, int f0, uint4& hi, uint4& lo) {
   if constexpr (std::is_same<ZT, BF16>::value) {
-    return *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(z) + p * M + f0);
+    hi = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(z) + p * M + f0);
+    lo = make_uint4(0u, 0u, 0u, 0u);
   } else {
     const float4* r = reinterpret_cast<const float4*>(static_cast<const float*>(z) + p * M + f0);
-    const float4 a = r[0], b = r[1];
-    return make_uint4(pack_bf16(a.x, a.y), pack_bf16(a.z, a.w), pack_bf16(b.x, b.y), pack_bf16(b.z, b.w));
+    split_bf16x8(r[0], r[1], hi, lo);
   }
 }
 
@@ -65,15 +66,19 @@ __device__ inline void load_row(const void* z, int64_t p, float* out) {
 // tiles at a time; lane (g = lane/16, j = lane%16) loads features
 // 32s + 8g..+7 of point j of a tile for every K-step s, which is exactly its
 // B fragment, and the lanes of g = 0 carry the tile's [x_hi, x_lo, 1, 1]
-// step.  All U tiles' inputs are loaded before the first decode.
-// NH = hidden/16.
+// step.  FP32 rows take a second pass per feature step with their BF16
+// residuals (BF16 rows are exact and skip it).  All U tiles' inputs are
+// loaded before the first decode.  NH = hidden/16.
 template <int M, bool XYZ, int NH, typename ZT, int U, bool FULL>
 __device__ inline void decode_tiles(const DecodeArgs& A, int64_t p0, const bf16x8 (&fr)[NH][MfmaShape<M, XYZ>::KS],
                                     const floatx4 (&w2v)[NH], float b2) {
   using S = MfmaShape<M, XYZ>;
+  constexpr bool SPLIT = !std::is_same<ZT, BF16>::value;
+  constexpr int NL = SPLIT ? S::KZ : 1;
   const int lane = threadIdx.x & 63, g = lane >> 4;
   const int64_t P = A.P;
   bf16x8 b[U][S::KS];
+  bf16x8 bl[U][NL];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int64_t p = p0 + 16 * u;
@@ -82,9 +87,10 @@ __device__ inline void decode_tiles(const DecodeArgs& A, int64_t p0, const bf16x
 #pragma unroll
     for (int s = 0; s < S::KZ; ++s) {
       const int f0 = 32 * s + 8 * g;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (f0 < M) v = load_z8<M, ZT>(A.z, pc, f0);
-      b[u][s] = __builtin_bit_cast(bf16x8, v);
+      uint4 hi = make_uint4(0u, 0u, 0u, 0u), lo = hi;
+      if (f0 < M) load_z8<M, ZT>(A.z, pc, f0, hi, lo);
+      b[u][s] = __builtin_bit_cast(bf16x8, hi);
+      if constexpr (SPLIT) bl[u][s] = __builtin_bit_cast(bf16x8, lo);
     }
     float x[3] = {0.0f, 0.0f, 0.0f};
     if constexpr (XYZ) {
@@ -103,8 +109,11 @@ __device__ inline void decode_tiles(const DecodeArgs& A, int64_t p0, const bf16x
     for (int h = 0; h < NH; ++h) {
       acc[h] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int s = 0; s < S::KS; ++s)
+      for (int s = 0; s < S::KZ; ++s) {
         acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[h][s], b[u][s], acc[h], 0, 0, 0);
+        if constexpr (SPLIT) acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[h][s], bl[u][s], acc[h], 0, 0, 0);
+      }
+      acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[h][S::KZ], b[u][S::KZ], acc[h], 0, 0, 0);
     }
     float part = 0.0f;
 #pragma unroll
@@ -130,7 +139,9 @@ __global__ __launch_bounds__(256) void k_decode_rf(ngl_model md, DecodeArgs A) {
 #pragma unroll
   for (int e0 = 0; e0 < NF; e0 += 256) {
     const int e = e0 + int(threadIdx.x);
-    if (e < NF) fl[e] = frag_bf16<M, XYZ>(md, A.lod, (e >> 6) / S::KS, (e >> 6) % S::KS, e & 63);
+    if (e < NF)
+      fl[e] = md.W1_packed[A.lod - 1] ? static_cast<const uint4*>(md.W1_packed[A.lod - 1])[e]
+                                      : frag_bf16<M, XYZ>(md, A.lod, (e >> 6) / S::KS, (e >> 6) % S::KS, e & 63);
   }
   if (threadIdx.x < 16 * NH) w2l[threadIdx.x] = md.w2[A.lod - 1][threadIdx.x];
   __syncthreads();
@@ -206,15 +217,7 @@ constexpr int kDecodeU = NGL_DECODE_TILES;  // 16-point tiles per wavefront iter
 // grid is sized to the occupancy and loops over the tiles).
 template <int M, bool XYZ, typename ZT, int NH>
 static int launch_rf(const ngl_model& md, const DecodeArgs& A, hipStream_t s) {
-  static int resident = 0;
-  if (!resident) {
-    int dev = 0, cus = 256, per = 1;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    const void* kern = reinterpret_cast<const void*>(&k_decode_rf<M, XYZ, NH, ZT, kDecodeU>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 256, 0) != hipSuccess || per < 1) per = 1;
-    resident = cus * per;
-  }
+  const int resident = resident_grid(reinterpret_cast<const void*>(&k_decode_rf<M, XYZ, NH, ZT, kDecodeU>), 256, 0, 0);
   const int64_t T = (A.P + 15) / 16;
   int64_t grid = (T + 3) / 4;
   if (grid > resident) grid = resident;
@@ -254,9 +257,94 @@ static int decode_m(const ngl_model& md, const DecodeArgs& A, int zt, hipStream_
   return zt == NGL_BF16 ? run_decode<M, false, BF16>(md, A, s) : run_decode<M, false, F32>(md, A, s);
 }
 
+// Decoder lod's fragments in the order load_frags / load_frags32 stage
+// them (ngl_pack_decoders).
+template <int M, bool XYZ>
+__global__ void k_pack_decoder(ngl_model md, int lod, void* out, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  if (md.w_dtype == NGL_BF16) {
+    using S = MfmaShape<M, XYZ>;
+    static_cast<uint4*>(out)[e] = frag_bf16<M, XYZ>(md, lod, (e >> 6) / S::KS, (e >> 6) % S::KS, e & 63);
+  } else {
+    static_cast<float*>(out)[e] = frag_f32<M, XYZ>(md, lod, e);
+  }
+}
+
+// Fragment elements and their size for one LOD of this model.
+static void packed_shape(const ngl_model& m, int64_t& elems, size_t& elem_bytes) {
+  const int off = m.with_xyz ? 3 : 0;
+  if (m.w_dtype == NGL_BF16) {
+    elems = int64_t(m.hidden / 16) * ((m.feat_dim + 31) / 32 + 1) * 64;
+    elem_bytes = 16;
+  } else {
+    elems = int64_t(m.hidden / 16) * ((m.feat_dim + off + 1 + 3) / 4) * 64;
+    elem_bytes = 4;
+  }
+}
+
+static size_t packed_lod_bytes(const ngl_model& m) {
+  int64_t n = 0;
+  size_t eb = 0;
+  packed_shape(m, n, eb);
+  return (size_t(n) * eb + 255) / 256 * 256;
+}
+
+template <int M, bool XYZ>
+static int pack_m(const ngl_model& m, char* out, hipStream_t s) {
+  int64_t n = 0;
+  size_t eb = 0;
+  packed_shape(m, n, eb);
+  const size_t per = packed_lod_bytes(m);
+  for (int l = 1; l <= m.num_lods; ++l) {
+    k_pack_decoder<M, XYZ><<<unsigned((n + 255) / 256), 256, 0, s>>>(m, l, out + size_t(l - 1) * per, int(n));
+    NGL_LAUNCHED();
+  }
+  return NGL_OK;
+}
+
+template <int M>
+static int pack_width(const ngl_model& m, char* out, hipStream_t s) {
+  return m.with_xyz ? pack_m<M, true>(m, out, s) : pack_m<M, false>(m, out, s);
+}
+
+size_t packed_decoder_bytes(const ngl_model& m) { return packed_lod_bytes(m) * size_t(m.num_lods); }
+
 }  // namespace ngl
 
 extern "C" {
+
+int ngl_packed_decoder_bytes(const ngl_model* m, size_t* bytes) {
+  int rc = ngl::check_model(m, true);
+  if (rc) return rc;
+  NGL_REQUIRE(bytes != nullptr, "bytes is null");
+  *bytes = ngl::packed_decoder_bytes(*m);
+  return NGL_OK;
+}
+
+int ngl_pack_decoders(ngl_model* m, void* packed, size_t bytes, void* stream) {
+  int rc = ngl::check_model(m, true);
+  if (rc) return rc;
+  NGL_REQUIRE(packed != nullptr, "packed is null");
+  NGL_REQUIRE(reinterpret_cast<uintptr_t>(packed) % 256 == 0, "packed must be 256-byte aligned");
+  const size_t need = ngl::packed_decoder_bytes(*m);
+  NGL_REQUIRE(bytes >= need, "packed holds %zu bytes, %zu needed", bytes, need);
+  ngl_model src = *m;
+  for (int l = 0; l < NGL_MAX_LODS; ++l) src.W1_packed[l] = nullptr;
+  char* out = static_cast<char*>(packed);
+  hipStream_t s = (hipStream_t)stream;
+  switch (m->feat_dim) {
+    case 8: rc = ngl::pack_width<8>(src, out, s); break;
+    case 16: rc = ngl::pack_width<16>(src, out, s); break;
+    case 32: rc = ngl::pack_width<32>(src, out, s); break;
+    case 64: rc = ngl::pack_width<64>(src, out, s); break;
+    default: NGL_FAIL(NGL_E_UNSUPPORTED, "feat_dim %d not compiled (8, 16, 32, 64)", m->feat_dim);
+  }
+  if (rc) return rc;
+  const size_t per = ngl::packed_decoder_bytes(*m) / size_t(m->num_lods);
+  for (int l = 0; l < NGL_MAX_LODS; ++l) m->W1_packed[l] = l < m->num_lods ? out + size_t(l) * per : nullptr;
+  return NGL_OK;
+}
 
 int ngl_decode_sdf(const ngl_model* m, int32_t lod, const float* x, const void* z, int32_t z_dtype, int64_t P,
                    float* sdf, void* stream) {

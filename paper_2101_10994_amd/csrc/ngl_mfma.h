@@ -11,11 +11,16 @@
 //   A[i][k]: lane l holds i = l%16, k = 8*(l/16) + 0..7
 //   B[k][j]: lane l holds j = l%16, k = 8*(l/16) + 0..7
 //   D[i][j]: lane l holds j = l%16, i = 4*(l/16) + r, r = 0..3
-// Layer-1 inputs: K-step s < KZ covers features 32s..32s+31 (BF16, zero
-// padded); the last K-step carries the position and the bias split into
-// high and low BF16 parts, x = x_hi + x_lo, b1 = b1_hi + b1_lo, so they keep
-// about 16 significant bits: columns [x_hi(3), x_lo(3), 1, 1, 0...] against
-// weights [W1_x(3), W1_x(3), b1_hi, b1_lo, 0...].
+// BF16 form: the weights are used as stored (BF16).  Every FP32 activation
+// a is carried as a_hi + a_lo, a_hi = bf16(a), a_lo = bf16(a - a_hi) (about
+// 16 significant bits), so the only rounding beyond FP32 accumulation is
+// that representation error (relative 2^-16):
+//   K-steps s < KZ: features 32s..32s+31 (zero padded), once with z_hi and
+//     once with z_lo against the same weight fragment;
+//   the last K-step: columns [x_hi(3), x_lo(3), 1, 1, 0...] against weights
+//     [W1_x(3), W1_x(3), b1_hi, b1_lo, 0...] (position and bias split alike).
+// The points' inputs are staged in LDS as FP32 rows and split while the B
+// fragments are formed.
 #pragma once
 
 #include "ngl_device.h"
@@ -40,6 +45,16 @@ __device__ inline uint32_t pack_bf16(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
 }
 
+// Eight FP32 values split into BF16 high parts and BF16 residuals:
+// v[i] = hi[i] + lo[i] up to the rounding of the residual (relative 2^-16).
+__device__ inline void split_bf16x8(const float4 a, const float4 b, uint4& hi, uint4& lo) {
+  hi = make_uint4(pack_bf16(a.x, a.y), pack_bf16(a.z, a.w), pack_bf16(b.x, b.y), pack_bf16(b.z, b.w));
+  lo = make_uint4(pack_bf16(a.x - __uint_as_float(hi.x << 16), a.y - __uint_as_float(hi.x & 0xffff0000u)),
+                  pack_bf16(a.z - __uint_as_float(hi.y << 16), a.w - __uint_as_float(hi.y & 0xffff0000u)),
+                  pack_bf16(b.x - __uint_as_float(hi.z << 16), b.y - __uint_as_float(hi.z & 0xffff0000u)),
+                  pack_bf16(b.z - __uint_as_float(hi.w << 16), b.w - __uint_as_float(hi.w & 0xffff0000u)));
+}
+
 // The last K-step's B row of a point: [x_hi(3), x_lo(3), 1, 1] as BF16
 // (x = x_hi + x_lo to about 16 bits), or [1, 1, 0...] without the position.
 template <bool XYZ>
@@ -58,14 +73,16 @@ template <int M, bool XYZ>
 struct MfmaShape {
   static constexpr int OFF = XYZ ? 3 : 0;
   static constexpr int KZ = (M + 31) / 32;   // K-steps over the features
-  static constexpr int KS = KZ + 1;          // + position/bias step
-  static constexpr int ROW = KS * 32 + 8;    // staged BF16 elements per point (16 B pad)
-  static constexpr int STAGE_BYTES = 64 * ROW * 2;
+  static constexpr int KS = KZ + 1;          // weight fragments per hidden tile (+ position/bias step)
+  static constexpr int ROW = M + 4;          // staged FP32 row: z (M), x (3), pad; 16-byte multiple
+  static constexpr int STAGE_BYTES = 64 * ROW * 4;
   static constexpr int frag_bytes(int H) { return (H / 16) * KS * 64 * 16; }
 };
 
 // One lane's A fragment (16 bytes) of decoder L for hidden tile h and K-step
-// s: row i = 16h + lane%16, columns 8*(lane/16) + 0..7 of that step.
+// s: row i = 16h + lane%16, columns 8*(lane/16) + 0..7 of that step.  W1 is
+// read from the model unless `packed` (the fragments in this order, from
+// ngl_pack_decoders) is given.
 template <int M, bool XYZ>
 __device__ inline uint4 frag_bf16(const ngl_model& md, int L, int h, int s, int lane) {
   using S = MfmaShape<M, XYZ>;
@@ -98,16 +115,22 @@ __device__ inline uint4 frag_bf16(const ngl_model& md, int L, int h, int s, int 
 }
 
 // Block-cooperative: A fragments of decoder L (BF16 weights) into LDS, and
-// its w2 (FP32).  frag: [H/16][KS][64] 16-byte fragments.
+// its w2 (FP32).  frag: [H/16][KS][64] 16-byte fragments, copied from the
+// pre-packed decoder when the model has one.
 template <int M, bool XYZ>
 __device__ inline void load_frags(const ngl_model& md, int L, uint4* frag, float* w2s) {
   using S = MfmaShape<M, XYZ>;
   const int H = md.hidden;
   const int n = (H / 16) * S::KS * 64;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int s = (e >> 6) % S::KS;
-    const int h = (e >> 6) / S::KS;
-    frag[e] = frag_bf16<M, XYZ>(md, L, h, s, e & 63);
+  const uint4* packed = static_cast<const uint4*>(md.W1_packed[L - 1]);
+  if (packed) {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) frag[e] = packed[e];
+  } else {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+      const int s = (e >> 6) % S::KS;
+      const int h = (e >> 6) / S::KS;
+      frag[e] = frag_bf16<M, XYZ>(md, L, h, s, e & 63);
+    }
   }
   for (int k = threadIdx.x; k < H; k += blockDim.x) w2s[k] = md.w2[L - 1][k];
 }
@@ -124,58 +147,60 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Stage this lane's decoder input row (BF16) into the wavefront's buffer.
+// Stage this lane's decoder input row (FP32: z, then x) into the
+// wavefront's buffer.
 template <int M, bool XYZ>
-__device__ inline void stage_row(uint16_t* stage, const float x[3], const float* z) {
+__device__ inline void stage_row(float* stage, const float x[3], const float* z) {
   using S = MfmaShape<M, XYZ>;
-  const int lane = threadIdx.x & 63;
-  uint32_t* row = reinterpret_cast<uint32_t*>(stage + lane * S::ROW);
+  float4* row = reinterpret_cast<float4*>(stage + (threadIdx.x & 63) * S::ROW);
 #pragma unroll
-  for (int s = 0; s < S::KZ; ++s) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int f0 = 32 * s + 2 * q;
-      row[16 * s + q] = f0 < M ? pack_bf16(z[f0 < M ? f0 : 0], z[f0 + 1 < M ? f0 + 1 : 0]) : 0u;
-    }
-  }
-  const uint4 t = pos_bias_row<XYZ>(x);
-  uint32_t* tail = row + 16 * S::KZ;
-  tail[0] = t.x;
-  tail[1] = t.y;
-  tail[2] = t.z;
-  tail[3] = t.w;
-#pragma unroll
-  for (int q = 4; q < 16; ++q) tail[q] = 0u;
+  for (int q = 0; q < M / 4; ++q) row[q] = make_float4(z[4 * q], z[4 * q + 1], z[4 * q + 2], z[4 * q + 3]);
+  row[M / 4] = XYZ ? make_float4(x[0], x[1], x[2], 0.0f) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // stage_row in two parts, for rows whose features were gathered by other
-// lanes: the packed slice [off, off + 8) of row `row`'s features, and the
-// rest of this lane's own row (feature padding, position and bias words).
+// lanes: the slice [off, off + 8) of row `row`'s features, and the rest of
+// this lane's own row (its position).
 template <int M, bool XYZ>
-__device__ inline void stage_slice8(uint16_t* stage, int row, int off, const float* v) {
+__device__ inline void stage_slice8(float* stage, int row, int off, const float* v) {
   using S = MfmaShape<M, XYZ>;
-  uint4* w = reinterpret_cast<uint4*>(stage + row * S::ROW + off);
-  *w = make_uint4(pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]), pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7]));
+  float4* w = reinterpret_cast<float4*>(stage + row * S::ROW + off);
+  w[0] = make_float4(v[0], v[1], v[2], v[3]);
+  w[1] = make_float4(v[4], v[5], v[6], v[7]);
 }
 
 template <int M, bool XYZ>
-__device__ inline void stage_rest(uint16_t* stage, const float x[3]) {
+__device__ inline void stage_rest(float* stage, const float x[3]) {
   using S = MfmaShape<M, XYZ>;
-  const int lane = threadIdx.x & 63;
-  uint32_t* row = reinterpret_cast<uint32_t*>(stage + lane * S::ROW);
+  float4* row = reinterpret_cast<float4*>(stage + (threadIdx.x & 63) * S::ROW);
+  row[M / 4] = XYZ ? make_float4(x[0], x[1], x[2], 0.0f) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// B fragments of one staged point for the BF16 form: for each feature
+// K-step the high and low parts of features 32s + 8g..+7 (zero past M), and
+// in lanes g = 0 the position/bias step.
+template <int M, bool XYZ>
+__device__ inline void bf16_b_frags(const float* row, int g, bf16x8 (&bh)[MfmaShape<M, XYZ>::KZ],
+                                    bf16x8 (&bl)[MfmaShape<M, XYZ>::KZ], bf16x8& bp) {
+  using S = MfmaShape<M, XYZ>;
 #pragma unroll
-  for (int s = 0; s < S::KZ; ++s)
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-      if (32 * s + 2 * q >= M) row[16 * s + q] = 0u;
-  const uint4 t = pos_bias_row<XYZ>(x);
-  uint32_t* tail = row + 16 * S::KZ;
-  tail[0] = t.x;
-  tail[1] = t.y;
-  tail[2] = t.z;
-  tail[3] = t.w;
-#pragma unroll
-  for (int q = 4; q < 16; ++q) tail[q] = 0u;
+  for (int s = 0; s < S::KZ; ++s) {
+    const int f0 = 32 * s + 8 * g;
+    uint4 hi = make_uint4(0u, 0u, 0u, 0u), lo = hi;
+    if (f0 < M) {
+      const float4* r = reinterpret_cast<const float4*>(row + f0);
+      split_bf16x8(r[0], r[1], hi, lo);
+    }
+    bh[s] = __builtin_bit_cast(bf16x8, hi);
+    bl[s] = __builtin_bit_cast(bf16x8, lo);
+  }
+  uint4 t = make_uint4(0u, 0u, 0u, 0u);
+  if (g == 0) {
+    const float4 xv = *reinterpret_cast<const float4*>(row + M);
+    const float x[3] = {xv.x, xv.y, xv.z};
+    t = pos_bias_row<XYZ>(x);
+  }
+  bp = __builtin_bit_cast(bf16x8, t);
 }
 
 // First layer on the matrix cores, second layer and reduction in FP32: the
@@ -183,7 +208,7 @@ __device__ inline void stage_rest(uint16_t* stage, const float x[3]) {
 // `live` (wave-uniform) marks the lanes whose output is used: a 16-lane
 // point tile without any is skipped (its lanes get b2).
 template <int M, bool XYZ>
-__device__ inline float wave_decode(const uint4* frag, const float* w2s, float b2, const uint16_t* stage, int H,
+__device__ inline float wave_decode(const uint4* frag, const float* w2s, float b2, const float* stage, int H,
                                     uint64_t live) {
   using S = MfmaShape<M, XYZ>;
   const int lane = threadIdx.x & 63;
@@ -192,17 +217,19 @@ __device__ inline float wave_decode(const uint4* frag, const float* w2s, float b
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     if (((live >> (16 * t)) & 0xffffull) == 0) continue;
-    bf16x8 b[S::KS];
-#pragma unroll
-    for (int s = 0; s < S::KS; ++s)
-      b[s] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(stage + (16 * t + j) * S::ROW + 32 * s + 8 * g));
+    bf16x8 bh[S::KZ], bl[S::KZ], bp;
+    bf16_b_frags<M, XYZ>(stage + (16 * t + j) * S::ROW, g, bh, bl, bp);
     float part = 0.0f;
     for (int h = 0; h < H / 16; ++h) {
       floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int s = 0; s < S::KS; ++s)
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, frag[(h * S::KS + s) * 64 + lane]),
-                                                      b[s], acc, 0, 0, 0);
+      for (int s = 0; s < S::KZ; ++s) {
+        const bf16x8 a = __builtin_bit_cast(bf16x8, frag[(h * S::KS + s) * 64 + lane]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh[s], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl[s], acc, 0, 0, 0);
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, frag[(h * S::KS + S::KZ) * 64 + lane]),
+                                                    bp, acc, 0, 0, 0);
       const float4 w = *reinterpret_cast<const float4*>(w2s + 16 * h + 4 * g);
       part = fmaf(w.x, relu_bits(acc[0]), part);
       part = fmaf(w.y, relu_bits(acc[1]), part);
@@ -233,21 +260,31 @@ struct MfmaShape32 {
   static constexpr int frag_bytes(int H) { return (H / 16) * KS * 64 * 4; }
 };
 
+// Element e of decoder L's FP32 fragments [H/16][KS][64]: hidden row
+// 16h + lane%16, input column 4s + lane/16 of [W1 | b1] (zero past it).
+template <int M, bool XYZ>
+__device__ inline float frag_f32(const ngl_model& md, int L, int e) {
+  using S = MfmaShape32<M, XYZ>;
+  const int din = M + S::OFF;
+  const float* W1 = static_cast<const float*>(md.W1[L - 1]);
+  const int lane = e & 63;
+  const int s = (e >> 6) % S::KS;
+  const int h = (e >> 6) / S::KS;
+  const int i = 16 * h + (lane & 15);
+  const int k = 4 * s + (lane >> 4);
+  return k < din ? W1[i * din + k] : (k == din ? md.b1[L - 1][i] : 0.0f);
+}
+
 template <int M, bool XYZ>
 __device__ inline void load_frags32(const ngl_model& md, int L, float* frag, float* w2s) {
   using S = MfmaShape32<M, XYZ>;
   const int H = md.hidden;
-  const int din = M + S::OFF;
-  const float* W1 = static_cast<const float*>(md.W1[L - 1]);
-  const float* b1 = md.b1[L - 1];
   const int n = (H / 16) * S::KS * 64;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int lane = e & 63;
-    const int s = (e >> 6) % S::KS;
-    const int h = (e >> 6) / S::KS;
-    const int i = 16 * h + (lane & 15);
-    const int k = 4 * s + (lane >> 4);
-    frag[e] = k < din ? W1[i * din + k] : (k == din ? b1[i] : 0.0f);
+  const float* packed = static_cast<const float*>(md.W1_packed[L - 1]);
+  if (packed) {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) frag[e] = packed[e];
+  } else {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) frag[e] = frag_f32<M, XYZ>(md, L, e);
   }
   for (int k = threadIdx.x; k < H; k += blockDim.x) w2s[k] = md.w2[L - 1][k];
 }
@@ -322,7 +359,7 @@ __device__ inline float wave_decode32(const float* frag, const float* w2s, float
 template <int M, bool XYZ>
 struct DecBF16 {
   using Frag = uint4;
-  using Stage = uint16_t;
+  using Stage = float;
   static constexpr int STAGE_BYTES = MfmaShape<M, XYZ>::STAGE_BYTES;
   static constexpr int STAGE_ELEMS = 64 * MfmaShape<M, XYZ>::ROW;
   static constexpr int frag_elems(int H) { return (H / 16) * MfmaShape<M, XYZ>::KS * 64; }

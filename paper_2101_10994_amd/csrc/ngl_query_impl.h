@@ -258,17 +258,13 @@ static int launch_query_coop_nw(const ngl_model& md, const float* x, int64_t P, 
                                 size_t lds) {
   // Grid-stride over the points with one round of resident blocks (each
   // stages the decoder once), or at most NGL_OPT_QUERY_BLOCKS_PER_CU per CU.
-  static int cus = 0, per = 0;
-  if (!cus) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    const void* kern = reinterpret_cast<const void*>(&k_query_coop<M, FT, XYZ, NW, DEC>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
-  }
+  const void* kern = reinterpret_cast<const void*>(&k_query_coop<M, FT, XYZ, NW, DEC>);
   const int bpc = option(NGL_OPT_QUERY_BLOCKS_PER_CU);
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    cus = 256;
   int64_t grid = (P + 64 * NW - 1) / (64 * NW);
-  const int64_t cap = int64_t(cus) * (bpc > 0 ? bpc : per);
+  const int64_t cap = bpc > 0 ? int64_t(cus) * bpc : resident_grid(kern, 64 * NW, lds, 0);
   if (grid > cap) grid = cap;
   k_query_coop<M, FT, XYZ, NW, DEC><<<unsigned(grid), 64 * NW, lds, s>>>(md, x, P, lod, alpha, app, sdf, valid, vox);
   NGL_LAUNCHED();
@@ -436,16 +432,10 @@ template <int M, typename FT, bool XYZ, class DEC, bool MFMA, int NW>
 static int launch_normals_nw(const ngl_model& md, const NormalArgs& A, hipStream_t s, size_t lds) {
   // one round of resident blocks looping over the points (each stages the
   // decoders once)
-  static int cus = 0, per = 0;
-  if (!cus) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    const void* kern = reinterpret_cast<const void*>(&k_normals<M, FT, XYZ, NW, DEC, MFMA>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
-  }
+  const void* kern = reinterpret_cast<const void*>(&k_normals<M, FT, XYZ, NW, DEC, MFMA>);
   int64_t grid = (A.P + 64 * NW - 1) / (64 * NW);
-  if (grid > int64_t(cus) * per) grid = int64_t(cus) * per;
+  const int64_t cap = resident_grid(kern, 64 * NW, lds, 0);
+  if (grid > cap) grid = cap;
   k_normals<M, FT, XYZ, NW, DEC, MFMA><<<unsigned(grid), 64 * NW, lds, s>>>(md, A);
   NGL_LAUNCHED();
   return NGL_OK;

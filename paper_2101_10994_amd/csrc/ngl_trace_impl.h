@@ -902,32 +902,11 @@ static __global__ void k_zero_counter(unsigned int* c) {
   if (threadIdx.x == 0) *c = 0u;
 }
 
-// Enough blocks to fill every CU at the kernel's occupancy (one value per
-// instantiation, computed on first use).
-template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW, class DEC>
-static int persistent_grid(size_t lds) {
-  static int cached = 0;
-  if (cached) return cached;
-  int dev = 0, cus = 0, per = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 1024;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 1024;
-  const void* kern = reinterpret_cast<const void*>(&k_sphere_trace<M, FT, XYZ, ANALYTIC, MFMA, NW, DEC>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
-  cached = cus * per;
-  return cached;
-}
-
 template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW, class DEC>
 static int launch_trace_nw(const ngl_model& md, const TraceArgs& A, hipStream_t s, size_t lds) {
   k_zero_counter<<<1, 64, 0, s>>>(A.counter);
-  int grid = persistent_grid<M, FT, XYZ, ANALYTIC, MFMA, NW, DEC>(lds);
-  const int bpc = option(NGL_OPT_TRACE_BLOCKS_PER_CU);
-  if (bpc > 0) {
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    if (cus * bpc < grid) grid = cus * bpc;
-  }
+  const void* kern = reinterpret_cast<const void*>(&k_sphere_trace<M, FT, XYZ, ANALYTIC, MFMA, NW, DEC>);
+  int grid = resident_grid(kern, 64 * NW, lds, option(NGL_OPT_TRACE_BLOCKS_PER_CU));
   const int64_t need = (A.R + 64 * NW - 1) / (64 * NW);
   if (need < grid) grid = int(need);
   k_sphere_trace<M, FT, XYZ, ANALYTIC, MFMA, NW, DEC><<<grid, 64 * NW, lds, s>>>(md, A);
@@ -937,18 +916,10 @@ static int launch_trace_nw(const ngl_model& md, const TraceArgs& A, hipStream_t 
 
 template <int M, typename FT, bool XYZ, int NW, class DEC>
 static int launch_trace_wide_nw(const ngl_model& md, const TraceArgs& A, hipStream_t s, size_t lds) {
-  static int cached = 0;
-  if (!cached) {
-    int dev = 0, cus = 256, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    const void* kern = reinterpret_cast<const void*>(&k_sphere_trace_wide<M, FT, XYZ, NW, DEC>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
-    cached = cus * per;
-  }
   k_zero_counter<<<1, 64, 0, s>>>(A.counter);
   constexpr int NS = 64 / wide_lanes<M>();
-  int grid = cached;
+  const void* kern = reinterpret_cast<const void*>(&k_sphere_trace_wide<M, FT, XYZ, NW, DEC>);
+  int grid = resident_grid(kern, 64 * NW, lds, option(NGL_OPT_TRACE_BLOCKS_PER_CU));
   const int64_t need = (A.R + NS * NW - 1) / (NS * NW);
   if (need < grid) grid = int(need);
   k_sphere_trace_wide<M, FT, XYZ, NW, DEC><<<grid, 64 * NW, lds, s>>>(md, A);
@@ -987,18 +958,8 @@ static int launch_trace(const ngl_model& md, const TraceArgs& A, hipStream_t s) 
 
 template <int M, typename FT, bool XYZ, int NW, class DEC>
 static int launch_batch_nw(const BatchArgs& B, hipStream_t s, size_t lds) {
-  static int per = 0;
-  static int cus = 0;
-  if (!per) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    const void* kern = reinterpret_cast<const void*>(&k_trace_batch<M, FT, XYZ, NW, DEC>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
-  }
-  int grid = cus * per;
-  const int cap = option(NGL_OPT_TRACE_BLOCKS_PER_CU);
-  if (cap > 0 && cap < per) grid = cus * cap;
+  const void* kern = reinterpret_cast<const void*>(&k_trace_batch<M, FT, XYZ, NW, DEC>);
+  const int grid = resident_grid(kern, 64 * NW, lds, option(NGL_OPT_TRACE_BLOCKS_PER_CU));
   k_trace_batch<M, FT, XYZ, NW, DEC><<<grid, 64 * NW, lds, s>>>(B);
   NGL_LAUNCHED();
   return NGL_OK;
@@ -1017,16 +978,9 @@ static int launch_batch(const BatchArgs& B, bool any_blend, int H, hipStream_t s
 
 template <int M, typename FT, bool XYZ, int NW, class DEC>
 static int launch_batch_wide_nw(const BatchArgs& B, hipStream_t s, size_t lds) {
-  static int per = 0;
-  static int cus = 0;
-  if (!per) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    const void* kern = reinterpret_cast<const void*>(&k_trace_batch_wide<M, FT, XYZ, NW, DEC>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
-  }
-  k_trace_batch_wide<M, FT, XYZ, NW, DEC><<<cus * per, 64 * NW, lds, s>>>(B);
+  const void* kern = reinterpret_cast<const void*>(&k_trace_batch_wide<M, FT, XYZ, NW, DEC>);
+  const int grid = resident_grid(kern, 64 * NW, lds, option(NGL_OPT_TRACE_BLOCKS_PER_CU));
+  k_trace_batch_wide<M, FT, XYZ, NW, DEC><<<grid, 64 * NW, lds, s>>>(B);
   NGL_LAUNCHED();
   return NGL_OK;
 }
@@ -1071,16 +1025,9 @@ static __global__ void k_batch_init(unsigned int* counters, unsigned int* live, 
 
 template <int M, typename FT, bool XYZ, bool MFMA, int NW, class DEC>
 static int launch_buckets_nw(const ngl_model& md, const BucketArgs& B, hipStream_t s, size_t lds) {
-  static int per = 0, cus = 0;
-  if (!per) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    const void* kern = reinterpret_cast<const void*>(&k_trace_buckets<M, FT, XYZ, MFMA, NW, DEC>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
-  }
-  k_trace_buckets<M, FT, XYZ, MFMA, NW, DEC><<<cus * per, 64 * NW, lds, s>>>(md, B);
+  const void* kern = reinterpret_cast<const void*>(&k_trace_buckets<M, FT, XYZ, MFMA, NW, DEC>);
+  const int grid = resident_grid(kern, 64 * NW, lds, option(NGL_OPT_TRACE_BLOCKS_PER_CU));
+  k_trace_buckets<M, FT, XYZ, MFMA, NW, DEC><<<grid, 64 * NW, lds, s>>>(md, B);
   NGL_LAUNCHED();
   return NGL_OK;
 }
@@ -1099,16 +1046,9 @@ static int launch_buckets(const ngl_model& md, const BucketArgs& B, hipStream_t 
 
 template <int M, typename FT, bool XYZ, int NW, class DEC>
 static int launch_buckets_wide_nw(const ngl_model& md, const BucketArgs& B, hipStream_t s, size_t lds) {
-  static int per = 0, cus = 0;
-  if (!per) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      cus = 256;
-    const void* kern = reinterpret_cast<const void*>(&k_trace_buckets_wide<M, FT, XYZ, NW, DEC>);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, 64 * NW, lds) != hipSuccess || per < 1) per = 1;
-  }
-  k_trace_buckets_wide<M, FT, XYZ, NW, DEC><<<cus * per, 64 * NW, lds, s>>>(md, B);
+  const void* kern = reinterpret_cast<const void*>(&k_trace_buckets_wide<M, FT, XYZ, NW, DEC>);
+  const int grid = resident_grid(kern, 64 * NW, lds, option(NGL_OPT_TRACE_BLOCKS_PER_CU));
+  k_trace_buckets_wide<M, FT, XYZ, NW, DEC><<<grid, 64 * NW, lds, s>>>(md, B);
   NGL_LAUNCHED();
   return NGL_OK;
 }

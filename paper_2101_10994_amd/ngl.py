@@ -45,7 +45,7 @@ class ngl_model(C.Structure):
                 ("cell", P * MAX_DEPTH), ("child_mask", P * MAX_DEPTH), ("first_child", P * MAX_DEPTH),
                 ("parent", P * MAX_DEPTH), ("corners", P * MAX_LODS), ("feat", P * MAX_LODS),
                 ("W1", P * MAX_LODS), ("b1", P * MAX_LODS), ("w2", P * MAX_LODS), ("b2", P),
-                ("corner_adj_off", P * MAX_LODS), ("corner_adj", P * MAX_LODS)]
+                ("corner_adj_off", P * MAX_LODS), ("corner_adj", P * MAX_LODS), ("W1_packed", P * MAX_LODS)]
 
 
 class ngl_octree_host(C.Structure):
@@ -111,7 +111,22 @@ EXPORTS = {
     "ngl_sample_surface": (C.c_int, [P, P, i64, i32, C.c_float, P, P, P, C.c_size_t, P]),
     "ngl_training_points": (C.c_int, [P, P, i64, i64, P, i64, i64, C.c_float, P, P, P]),
     "ngl_adam_step": (C.c_int, [P, i32, P, P, P, P, P, P]),
+    "ngl_packed_decoder_bytes": (C.c_int, [P, P]),
+    "ngl_pack_decoders": (C.c_int, [P, P, C.c_size_t, P]),
+    "ngl_workspace_bytes": (C.c_int, [C.c_int, P, i64, i64, P]),
 }
+
+# ngl_workspace_bytes operations
+(OP_TRACE_OCTREE, OP_SPHERE_TRACE, OP_SPHERE_TRACE_LOD, OP_TRAIN, OP_SAMPLE_SURFACE, OP_OCTREE_BUILD_DEVICE,
+ OP_PACK_DECODERS) = range(7)
+
+
+def workspace_bytes(op: int, model=None, n: int = 0, aux: int = 0) -> int:
+    """Device bytes the call `op` needs (ngl_workspace_bytes)."""
+    b = C.c_size_t()
+    _check(lib().ngl_workspace_bytes(int(op), model.ref if model is not None else None, int(n), int(aux),
+                                     C.addressof(b)))
+    return int(b.value)
 
 
 def lib():
@@ -322,8 +337,10 @@ class Model:
     (float32 or bfloat16); b1[l], w2[l]: [h] float32; b2: [L] float32."""
 
     def __init__(self, tree: Octree, feats: Sequence[torch.Tensor], W1: Sequence[torch.Tensor],
-                 b1: Sequence[torch.Tensor], w2: Sequence[torch.Tensor], b2: torch.Tensor, with_xyz: bool = True):
+                 b1: Sequence[torch.Tensor], w2: Sequence[torch.Tensor], b2: torch.Tensor, with_xyz: bool = True,
+                 pack: bool = False):
         self.tree = tree
+        self._packed = None
         self.num_lods = tree.num_lods
         assert len(feats) == self.num_lods and len(W1) == self.num_lods
         self.feats = [_dev(f) for f in feats]
@@ -351,6 +368,28 @@ class Model:
         if tuple(self.b2.shape) != (self.num_lods,):
             raise NGLError("b2 must have num_lods entries")
         self._struct = self._make_struct()
+        if pack:
+            self.pack()
+
+    def pack(self):
+        """Pre-pack the decoders' first layers in matrix-core fragment order
+        (ngl_pack_decoders); kernels then copy them instead of rebuilding
+        them per block.  Call again after W1 or b1 change (refresh() does)."""
+        nb = C.c_size_t()
+        _check(lib().ngl_packed_decoder_bytes(self.ref, C.addressof(nb)))
+        if self._packed is None or self._packed.numel() < nb.value:
+            self._packed = torch.empty(int(nb.value), dtype=torch.uint8, device=self.b2.device)
+        _check(lib().ngl_pack_decoders(self.ref, _ptr(self._packed), int(nb.value), _stream()))
+
+    def unpack(self):
+        """Drop the packed decoders (kernels build fragments from W1, b1)."""
+        self._packed = None
+        for lv in range(MAX_LODS):
+            self._struct.W1_packed[lv] = None
+
+    @property
+    def packed(self) -> bool:
+        return self._packed is not None
 
     def _make_struct(self):
         s = ngl_model()
@@ -380,8 +419,11 @@ class Model:
         return C.addressof(self._struct)
 
     def refresh(self):
-        """Rebuild the C view after parameters were reassigned."""
+        """Rebuild the C view after parameters were reassigned (and re-pack
+        the decoders if they were packed)."""
         self._struct = self._make_struct()
+        if self._packed is not None:
+            self.pack()
 
 
 # ---------------------------------------------------------------------------

@@ -248,6 +248,44 @@ def embedded_decoders(rng, num_lods: int, m: int, hidden: int, with_xyz: bool = 
     return d
 
 
+def spread_decoders(rng, num_lods: int, m: int, hidden: int, with_xyz: bool = True, noise: float = 0.05):
+    """Decoders that read channel L-1 of the summed feature like
+    embedded_decoders, but through every hidden unit: units come in pairs
+    (u_k, -u_k) with output weights (+c_k, -c_k), so the pair contributes
+    c_k (ReLU(u_k) - ReLU(-u_k)) = c_k u_k.  Each u_k = a_k z_{L-1} + r_k .
+    [x, z_other] + b_k has random weights on every input; the last pair's
+    r and b are chosen so that sum_k c_k r_k = 0 and sum_k c_k b_k = 0, and
+    sum_k c_k a_k = 1, so in exact arithmetic the output is z_{L-1} (and
+    b2 = 0).  The cancellation spreads the result over all hidden units
+    with terms much larger than the output, so the accumulation order and
+    the rounding of the weights, positions and features reach the result.
+    Returns float64 arrays with the layout of decoders()."""
+    din = m + (3 if with_xyz else 0)
+    off = 3 if with_xyz else 0
+    K = hidden // 2
+    W1 = np.zeros((num_lods, hidden, din))
+    b1 = np.zeros((num_lods, hidden))
+    w2 = np.zeros((num_lods, hidden))
+    for L in range(num_lods):
+        c = rng.uniform(0.5, 1.5, size=K) * rng.choice([-1.0, 1.0], size=K) / K
+        a = rng.uniform(0.5, 1.5, size=K) * np.sign(c)
+        a /= float(np.dot(c, a))
+        r = rng.normal(0.0, noise, size=(K, din))
+        r[:, off + L] = 0.0
+        b = rng.normal(0.0, noise, size=K)
+        r[K - 1] = -np.dot(c[:K - 1], r[:K - 1]) / c[K - 1]
+        b[K - 1] = -np.dot(c[:K - 1], b[:K - 1]) / c[K - 1]
+        u = r.copy()
+        u[:, off + L] = a
+        W1[L, 0::2] = u
+        W1[L, 1::2] = -u
+        b1[L, 0::2] = b
+        b1[L, 1::2] = -b
+        w2[L, 0::2] = c
+        w2[L, 1::2] = -c
+    return dict(W1=W1, b1=b1, w2=w2, b2=np.zeros(num_lods))
+
+
 # --------------------------------------------------------------------------
 # Cameras and rays
 # --------------------------------------------------------------------------

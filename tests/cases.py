@@ -60,13 +60,19 @@ def _round(a, dtype):
 
 
 def make_case(shape, res, L, m, H, seed=0, sigma=0.01, with_xyz=True, feat_dtype="f32", w_dtype="f32",
-              embedded=False):
+              embedded=False, spread=False):
+    """embedded: SDF-embedded features with the two-unit embedded decoder;
+    spread: the same features read through every hidden unit
+    (workloads.spread_decoders)."""
     ijk = W.occupancy_ijk(shape, res)
     otree = oracle.Octree(ijk, L)
     rs = W.rngs(seed)
-    if embedded:
+    if embedded or spread:
         feats = W.embedded_features(rs[W.STREAM_FEAT], shape, otree.corner_positions(), m, sigma)
-        dec = W.embedded_decoders(rs[W.STREAM_DEC], L, m, H, with_xyz)
+        if spread:
+            dec = W.spread_decoders(rs[W.STREAM_DEC], L, m, H, with_xyz)
+        else:
+            dec = W.embedded_decoders(rs[W.STREAM_DEC], L, m, H, with_xyz)
     else:
         feats = W.features(rs[W.STREAM_FEAT], otree.ncorner, m, sigma)
         dec = W.decoders(rs[W.STREAM_DEC], L, m + (3 if with_xyz else 0), H)

@@ -1,14 +1,18 @@
 """Batched persistent rendering: several models (different octree depths,
-cameras and LODs) traced by one launch.  Each view must equal the
-single-view path (camera rays, ray-octree intersection, sphere trace) bit
-for bit -- that path is the one checked against the oracle -- every ray must
-end, and the per-view clocks must be ordered."""
+cameras and LODs) traced by one launch.  Every view is checked against the
+oracle directly (its own camera rays, hit lists and trace at the view's LOD
+and alpha), and must equal the single-view path (camera rays, ray-octree
+intersection, sphere trace) bit for bit; every ray must end, and the
+per-view clocks must be ordered."""
 import numpy as np
 import pytest
 
 from paper_2101_10994_amd import workloads as W
 
+import oracle
+
 from cases import make_case
+from tracecmp import check, oracle_reference, report, summary
 
 pytestmark = pytest.mark.gpu
 
@@ -54,6 +58,41 @@ def test_batch_equals_single_view(alphas):
             b = out[sl].cpu().numpy()
             assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), (i, key)
         assert int((single["status"] == ngl.HIT).sum()) > 100
+
+
+@pytest.mark.parametrize("alphas", [(0.0, 0.0, 0.0, 0.0), (0.0, 0.5, 0.0, 0.25)])
+def test_batch_views_match_oracle(alphas):
+    """Each view of one batched launch against the oracle: the oracle builds
+    the view's float32 camera rays itself (the GPU's agree to 5e-7), traces
+    them at the view's LOD and alpha, and a ray is also marginal when its
+    status changes under a 2e-6 turn of its direction."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    cases = batch_cases()
+    models = [c.gpu_model() for c in cases]
+    rng = np.random.default_rng(13)
+    views = []
+    for i, c in enumerate(cases):
+        cam = W.camera_on_sphere(rng, 2.6, 112 + 16 * i, 96 + 8 * i)
+        lod = c.L if alphas[i] == 0.0 else c.L - 1
+        views.append(ngl.make_view(cam.eye, cam.width, cam.height, lod, alphas[i]))
+    br = ngl.BatchRenderer(models, views, pair_capacity=1 << 20)
+    br.render(100, 1e-4)
+    torch.cuda.synchronize()
+    assert not br.overflowed()
+    out = {}
+    for i, (c, v) in enumerate(zip(cases, views)):
+        co, cd = oracle.camera_rays(tuple(v.eye), (0, 0, 0), (0, 1, 0), 45.0, v.width, v.height)
+        o32, d32 = np.ascontiguousarray(co.astype(np.float32)), np.ascontiguousarray(cd.astype(np.float32))
+        r = oracle_reference(c, o32, d32, v.lod, v.alpha, 100, 1e-4, dir_eps=2e-6)
+        sl = br.view_slice(i)
+        g = {"t": br.t[sl].cpu().numpy(), "status": br.status[sl].cpu().numpy(),
+             "hit_vox": br.hit_vox[sl].cpu().numpy()}
+        voxel = 2.0 / 2 ** (c.L + 1)
+        nhit, nmarg = check(g, r, voxel, max_marginal=0.03)
+        out["view%d_L%d_a%g" % (i, v.lod, v.alpha)] = summary(g, r, voxel)
+        assert nhit > 100
+    report("batch_vs_oracle_" + "_".join("%g" % a for a in alphas), out)
 
 
 def test_batch_rejects_mixed_formats():

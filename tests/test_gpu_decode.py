@@ -1,7 +1,8 @@
 """GPU parity: the decoder alone (Eq. 2's per-LOD MLP) on given [x, z]
-against the FP64 oracle.  FP32 weights: |d| <= 1e-5 s; BF16 weights (inputs
-rounded to BF16 on the GPU): |d| <= 2e-3 s1, with s and s1 the oracle's
-magnitude scales of each point."""
+against the FP64 oracle.  FP32 weights: |d| <= 1e-5 s; BF16 weights (BF16
+rows used as stored, FP32 rows split into two BF16 parts on the GPU):
+|d| <= 5e-5 s1 and |d| <= 2e-3 s, with s and s1 the oracle's magnitude
+scales of each point (see the BF16 bars of the query tests)."""
 import numpy as np
 import pytest
 
@@ -11,7 +12,7 @@ from paper_2101_10994_amd import workloads as W
 from cases import make_case
 
 pytestmark = pytest.mark.gpu
-TOL, TOL16 = 1e-5, 2e-3
+TOL, TOL16_S1, TOL16_S = 1e-5, 5e-5, 2e-3
 
 
 def run(case, lod, P, zdt, seed=0, scale=0.3):
@@ -42,7 +43,8 @@ def test_bf16_weights(m, H, zdt):
     case = make_case(W.tiny_shape(), 16, 3, m, H, seed=m + H, w_dtype="bf16")
     for lod in (1, 3):
         g, o = run(case, lod, 4099, zdt, seed=lod)
-        check(g, o, TOL16, "scale1")
+        check(g, o, TOL16_S1, "scale1")
+        check(g, o, TOL16_S, "scale")
 
 
 @pytest.mark.parametrize("with_xyz", [True, False])
@@ -50,7 +52,8 @@ def test_without_position_and_ragged_sizes(with_xyz):
     case = make_case(W.tiny_shape(), 16, 3, 32, 128, seed=3, w_dtype="bf16", with_xyz=with_xyz)
     for P in (1, 15, 16, 17, 63, 65, 1000):
         g, o = run(case, 2, P, "bf16", seed=P)
-        check(g, o, TOL16, "scale1")
+        check(g, o, TOL16_S1, "scale1")
+        check(g, o, TOL16_S, "scale")
 
 
 @pytest.mark.parametrize("zdt", ["bf16", "f32"])
@@ -73,7 +76,8 @@ def test_paper_scale_decoder():
     g = ngl.decode_sdf(case.gpu_model(), 5, z.cuda(), x=torch.from_numpy(x).cuda()).cpu().numpy()
     idx = np.arange(0, P, 97)
     o = oracle.decode(case.oracle_model(), 5, z.to(torch.float64).numpy()[idx], np.ascontiguousarray(x[:, idx]))
-    check(g[idx].astype(np.float64), o, TOL16, "scale1")
+    check(g[idx].astype(np.float64), o, TOL16_S1, "scale1")
+    check(g[idx].astype(np.float64), o, TOL16_S, "scale")
 
 
 def test_arguments():

@@ -13,7 +13,7 @@ from cases import edge_points, make_case, paper_case, tiny_case
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
-TOL16 = 2e-3
+TOL16 = 5e-5  # BF16 weights: the query bound against s1 (BF16 bars of the query tests)
 
 
 def check(n_gpu, o, h, tol=TOL, scale="scale"):

@@ -125,13 +125,32 @@ def test_empty_and_edge_sizes(f32_decoder):
 
 # ---------------------------------------------------------------------------
 # BF16 decoder on the matrix cores (FP32 accumulation), FP16/BF16/FP32 features.
-# Bar: |d - oracle| <= 2e-3 s1, the oracle evaluated in FP64 on the same stored
-# (rounded) parameters.  The residual error is the BF16 rounding of the first
-# layer's inputs z (relative 2^-9), which moves each pre-activation by at most
-# 2^-9 sum_i |W1_ki z_i|; s1 = |b2| + sum_k |w2_k| (|b1_k| + sum_i |W1_ki in_i|)
-# is that magnitude, so 2e-3 s1 bounds it.
+# The oracle is evaluated in FP64 on the same stored (rounded) parameters.  The
+# BF16 weights are exact matrix-core operands; every FP32 activation enters as
+# hi + lo with both parts BF16, whose representation error is at most 2^-16
+# relative (2^-8 for each rounding), so each pre-activation moves by at most
+# 2^-16 (|b1_k| + sum_i |W1_ki in_i|) plus FP32 accumulation.  Two bars:
+#   |d - oracle| <= 5e-5 s1,  s1 = |b2| + sum_k |w2_k| (|b1_k| + sum_i |W1_ki in_i|)
+#     (the error analysis above, with room for FP32 accumulation), and
+#   |d - oracle| <= 2e-3 s   (the stated 2e-3 relative SDF, taken against the
+#     same cancellation scale s as the FP32 bar).
+# The plain relative error |d - oracle| / |oracle| is reported where |oracle|
+# >= 1e-2 of the sample's rms.
 # ---------------------------------------------------------------------------
-TOL16 = 2e-3
+TOL16_S1 = 5e-5
+TOL16_S = 2e-3
+
+
+def check16(g, o):
+    """Voxels and validity bit-exact, SDF within both BF16 bars; returns the
+    worst error against s1 and against s and the plain relative error."""
+    check(g, o, TOL16_S1, "scale1")
+    check(g, o, TOL16_S, "scale")
+    err = np.abs(g["sdf"].astype(np.float64) - o["sdf"])
+    big = np.abs(o["sdf"]) >= 1e-2 * np.sqrt(np.mean(o["sdf"] ** 2))
+    rel = float((err[big] / np.abs(o["sdf"][big])).max()) if big.any() else 0.0
+    return (float((err / np.maximum(o["scale1"], 1e-30)).max()), float((err / np.maximum(o["scale"], 1e-30)).max()),
+            rel)
 
 
 @pytest.mark.parametrize("fdt", ["f32", "f16", "bf16"])
@@ -139,16 +158,17 @@ def test_bf16_decoder_tiny(fdt):
     case = tiny_case(sigma=0.2, feat_dtype=fdt, w_dtype="bf16")
     rng = np.random.default_rng(21)
     x = edge_points(case.ijk, 16, 3, rng)
-    worst = 0.0
+    worst = []
     for lod in (1, 2, 3):
         g, o = run_both(case, x, lod)
-        worst = max(worst, check(g, o, TOL16, "scale1"))
+        worst.append(check16(g, o))
     app = rng.uniform(0, 1, size=x.shape[1]).astype(np.float32)
     g, o = run_both(case, x, 2, alpha_pp=app)
-    worst = max(worst, check(g, o, TOL16, "scale1"))
+    worst.append(check16(g, o))
     g, o = run_both(case, x, 1, alpha=0.3)
-    worst = max(worst, check(g, o, TOL16, "scale1"))
-    print("bf16 decoder (%s features): worst |err|/s = %.2e" % (fdt, worst))
+    worst.append(check16(g, o))
+    w = np.max(np.array(worst), axis=0)
+    print("bf16 decoder (%s features): worst |err|/s1 %.2e, |err|/s %.2e, relative %.2e" % (fdt, *w))
 
 
 @pytest.mark.parametrize("m,H,xyz", [(8, 16, False), (16, 64, True), (64, 32, True)])
@@ -156,37 +176,23 @@ def test_bf16_decoder_shapes(m, H, xyz):
     case = make_case(W.tiny_shape(), 16, 3, m, H, sigma=0.2, with_xyz=xyz, feat_dtype="f16", w_dtype="bf16")
     x = edge_points(case.ijk, 16, 3, np.random.default_rng(m + H))
     g, o = run_both(case, x, 3)
-    check(g, o, TOL16, "scale1")
+    check16(g, o)
 
 
-def test_precision_config_sampled():
-    """7 LODs (resolutions 4..256) over 32 spheres + 4 tori, FP16 features and
-    BF16 decoders; 2^22 queries at continuous LOD 5 + alpha, alpha ~ U[0,1] per
-    query, on the GPU; the oracle checks a 32,768-point sample and the error
-    is reported per discrete LOD."""
-    import torch
-    from paper_2101_10994_amd import ngl
-    case = make_case(W.prec_shape(0), 256, 7, 32, 128, feat_dtype="f16", w_dtype="bf16")
-    rng = np.random.default_rng(5)
-    x = W.soa(W.paper_queries(0, case.shape, 1 << 22))
-    app = rng.uniform(0, 1, size=x.shape[1]).astype(np.float32)
-    gm = case.gpu_model()
-    g = ngl.query_sdf(gm, torch.from_numpy(x).cuda(), 5, alpha_pp=torch.from_numpy(app).cuda(), want_valid=True,
-                      want_vox=True)
-    g = {k: v.cpu().numpy() for k, v in g.items()}
-    idx = np.random.default_rng(2).choice(x.shape[1], 32768, replace=False)
-    xs = np.ascontiguousarray(x[:, idx])
-    o = oracle.query(case.otree, case.oracle_model(), xs, 5, alpha_pp=app[idx], want_vox=True)
-    check({"vox": g["vox"][:, idx], "valid": g["valid"][idx], "sdf": g["sdf"][idx]}, o, TOL16, "scale1")
-    om = case.oracle_model()
-    for lod in range(1, 8):
-        gl = ngl.query_sdf(gm, torch.from_numpy(xs).cuda(), lod)["sdf"].cpu().numpy()
-        ol = oracle.query(case.otree, om, xs, lod)
-        rel = np.abs(gl - ol["sdf"]) / ol["scale1"]
-        assert rel.max() <= TOL16, (lod, rel.max())
-        print("precision config LOD %d: max |err|/s1 %.2e, median %.2e, max |err| %.2e, max |err|/s %.2e"
-              % (lod, rel.max(), np.median(rel), np.abs(gl - ol["sdf"]).max(),
-                 (np.abs(gl - ol["sdf"]) / ol["scale"]).max()))
+def test_bf16_spread_decoder_paper_scale():
+    """The paper-scale octree with SDF-embedded FP16 features read through
+    every hidden unit (workloads.spread_decoders, BF16 weights): a decoder
+    whose output is one input channel, where rounding that channel to a
+    single BF16 value would cost up to 2^-8 of the SDF."""
+    case = make_case(W.paper_shape(0), 64, 5, 32, 128, spread=True, feat_dtype="f16", w_dtype="bf16")
+    rng = np.random.default_rng(31)
+    x = edge_points(case.ijk, 64, 5, rng, n_in=16384, n_uniform=4096)
+    for lod in (3, 5):
+        g, o = run_both(case, x, lod)
+        w = check16(g, o)
+        print("bf16 spread decoder LOD %d: |err|/s1 %.2e, |err|/s %.2e, relative %.2e" % (lod, *w))
+    g, o = run_both(case, x, 4, alpha_pp=rng.uniform(0, 1, x.shape[1]).astype(np.float32))
+    check16(g, o)
 
 
 COOP_CASES = {

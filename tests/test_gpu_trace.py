@@ -10,50 +10,9 @@ import oracle
 from paper_2101_10994_amd import workloads as W
 
 from cases import make_case, paper_case, tiny_case
+from tracecmp import check, report, summary, trace_both
 
 pytestmark = pytest.mark.gpu
-
-
-def trace_both(case, eye, width, height, lod, alpha, max_steps, delta, analytic=None, sample=None):
-    import torch
-    from paper_2101_10994_amd import ngl
-    gm = case.gpu_model()
-    # both sides trace the same float32 rays, generated by the oracle
-    co, cd = oracle.camera_rays(eye, (0, 0, 0), (0, 1, 0), 45.0, width, height)
-    on, dn = co.astype(np.float32), cd.astype(np.float32)
-    o, d = torch.from_numpy(on).cuda(), torch.from_numpy(dn).cuda()
-    depth = (lod + 1 if alpha > 0 else lod) + 1
-    hits = ngl.trace_octree(gm, o, d, depth)
-    g = ngl.sphere_trace(gm, o, d, lod, alpha, hits, max_steps, delta, analytic_sphere=analytic)
-    g = {k: v.cpu().numpy() for k, v in g.items() if k != "ws"}
-    idx = np.arange(on.shape[1]) if sample is None else sample
-    os_, ds_ = np.ascontiguousarray(on[:, idx]), np.ascontiguousarray(dn[:, idx])
-    oh = oracle.trace_octree(case.otree, os_, ds_, depth)
-    om = None if analytic is not None else case.oracle_model()
-    run = lambda dl, mt: oracle.sphere_trace(case.otree, om, os_, ds_, lod, alpha, oh, max_steps, dl,
-                                             analytic_sphere=analytic, margin_t=mt)
-    r = run(delta, 1e-5)
-    # A ray is marginal when its oracle outcome is not stable: the status
-    # changes for a 2% change of the hit threshold (far above the ~1e-6
-    # FP32/FP64 difference of a distance), or a step lands within 1e-5 of a
-    # voxel bound, where skipping to the next voxel depends on rounding.
-    lo, hi = run(delta * 0.98, 0.0), run(delta * 1.02, 0.0)
-    r["marginal"] = (r["marginal"].astype(bool) | (lo["status"] != r["status"]) |
-                     (hi["status"] != r["status"])).astype(np.uint8)
-    return {k: v[idx] for k, v in g.items()}, r
-
-
-def check(g, r, voxel, max_marginal=0.01, dt_voxels=0.05):
-    marg = r["marginal"].astype(bool)
-    agree = g["status"] == r["status"]
-    assert np.all(agree | marg), np.nonzero(~agree & ~marg)[0][:10]
-    assert marg.mean() <= max_marginal, marg.mean()
-    both = (g["status"] == oracle.HIT) & (r["status"] == oracle.HIT) & ~marg
-    dt = np.abs(g["t"][both].astype(np.float64) - r["t"][both]) / voxel
-    if both.any():
-        assert np.quantile(dt, 0.999) <= dt_voxels, np.quantile(dt, 0.999)
-        assert np.mean(g["hit_vox"][both] != r["hit_vox"][both]) <= 1e-3
-    return int(both.sum()), int(marg.sum())
 
 
 def test_analytic_sphere_matches_oracle_and_closed_form():
@@ -90,6 +49,32 @@ def test_paper_scale_embedded_sampled(f32_decoder):
     nhit, nmarg = check(g, r, 2 / 64, max_marginal=0.03)
     print("paper-scale trace: %d common hits, %d marginal of %d rays" % (nhit, nmarg, len(idx)))
     assert nhit > 10000
+
+
+def test_paper_scale_spread_decoder_sampled(f32_decoder):
+    """1024x1024 render of the 5-LOD union through a decoder whose output
+    depends on every hidden unit (workloads.spread_decoders), FP32 weights:
+    32,768 sampled rays traced by the oracle.  Unlike the embedded decoder,
+    the accumulation order of the first and second layers reaches the
+    result here."""
+    case = make_case(W.paper_shape(0), 64, 5, 32, 128, spread=True)
+    idx = np.random.default_rng(4).choice(1024 * 1024, 32768, replace=False)
+    g, r = trace_both(case, W.PAPER.eye, 1024, 1024, 5, 0.0, 100, 1e-4, sample=idx)
+    nhit, nmarg = check(g, r, 2 / 64, max_marginal=0.03)
+    report("trace_paper_spread_f32_%s" % ["valu", "mfma"][f32_decoder], summary(g, r, 2 / 64))
+    assert nhit > 10000
+
+
+def test_paper_scale_spread_decoder_bf16_sampled():
+    """As above with FP16 features and BF16 weights on the matrix cores,
+    blended (L = 4 + 0.35) and at LOD 5."""
+    case = make_case(W.paper_shape(0), 64, 5, 32, 128, spread=True, feat_dtype="f16", w_dtype="bf16")
+    for lod, alpha in ((5, 0.0), (4, 0.35)):
+        idx = np.random.default_rng(5 + lod).choice(1024 * 1024, 16384, replace=False)
+        g, r = trace_both(case, W.PAPER.eye, 1024, 1024, lod, alpha, 100, 1e-4, sample=idx)
+        nhit, nmarg = check(g, r, 2 / 64, max_marginal=0.03)
+        report("trace_paper_spread_bf16_lod%d_a%g" % (lod, alpha), summary(g, r, 2 / 64))
+        assert nhit > 4000
 
 
 def test_stop_rules_and_invalid_rays():
@@ -133,6 +118,8 @@ PHASE_CASES = {
     "m16-bf16": lambda: make_case(W.paper_shape(0), 32, 4, 16, 32, embedded=True, feat_dtype="bf16",
                                   w_dtype="bf16"),
     "m64": lambda: make_case(W.paper_shape(0), 32, 4, 64, 64, embedded=True, with_xyz=False),
+    "m32-spread-bf16": lambda: make_case(W.paper_shape(0), 64, 5, 32, 128, spread=True, feat_dtype="f16",
+                                         w_dtype="bf16"),
 }
 
 
