@@ -53,14 +53,14 @@ TRAVERSAL_BYTES = 16
 COUNTERS = {
     # both launches of the phased FP32 trace (first 24 evaluations, then the wide kernel)
     "k_sphere_trace": {"sources": ["ngl_trace_impl.h", "ngl_device.h", "ngl_mfma.h"],
-                       "sha256": "b3e62dcbe54c211863b933e63da94edeb50220b31f1ab3b049a8f2eae5645e4b",
-                       "fetch_kib": 220675.5 + 24850.8, "write_kib": 38948.4 + 3662.1},
+                       "sha256": "dbb305cd3160276fbb0af4f12b894dfa8156fec8c7d3839fd7543c88f5a94a72",
+                       "fetch_kib": 220557.8 + 24146.3, "write_kib": 39035.5 + 3650.4},
     # k_query_coop, FP32 features and matrix-core decoder
     "k_query": {"sources": ["ngl_query_impl.h", "ngl_device.h", "ngl_mfma.h"],
-                "sha256": "ea9654b73c633fa82bb86ffd497b9c19bb034b838e22a5e4b87897d383b47cc2",
-                "fetch_kib": 113972.5, "write_kib": 4096.0},
+                "sha256": "dd5e8fa38a0019245989e6beb3fa0ce339ccc11869176e0a478ae329f4b965a2",
+                "fetch_kib": 114020.2, "write_kib": 4096.0},
 }
-FETCH_SCALE = (256 << 10) / 131088.0
+FETCH_SCALE = (256 << 10) / 131088.1
 WRITE_SCALE = (256 << 10) / 262144.0
 
 
@@ -108,13 +108,13 @@ def setup(device):
     tree = ngl.Octree(ijk, cfg.num_lods, device=device)
     rs = W.rngs(0)
     feats = W.embedded_features(rs[W.STREAM_FEAT], shape, tree.corner_positions(), cfg.feat_dim)
-    dec = W.embedded_decoders(rs[W.STREAM_DEC], cfg.num_lods, cfg.feat_dim, cfg.hidden)
+    dec = W.spread_decoders(rs[W.STREAM_DEC], cfg.num_lods, cfg.feat_dim, cfg.hidden)
     f32 = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=device)
     model = ngl.Model(tree, [f32(f) for f in feats], [f32(w) for w in dec["W1"]], [f32(b) for b in dec["b1"]],
-                      [f32(w) for w in dec["w2"]], f32(dec["b2"]))
+                      [f32(w) for w in dec["w2"]], f32(dec["b2"]), pack=True)
     # the BF16-MFMA form of the same model: FP16 features, BF16 first layer
     half = ngl.Model(tree, [f32(f).half() for f in feats], [f32(w).bfloat16() for w in dec["W1"]],
-                     [f32(b) for b in dec["b1"]], [f32(w) for w in dec["w2"]], f32(dec["b2"]))
+                     [f32(b) for b in dec["b1"]], [f32(w) for w in dec["w2"]], f32(dec["b2"]), pack=True)
     xq = W.soa(W.paper_queries(0, shape, cfg.n_query))
     xt, tg = W.train_points(1, shape, W.TRAIN.n_query)
     return dict(cfg=cfg, shape=shape, ijk=ijk, tree=tree, model=model, half=half, feats=feats, dec=dec,
@@ -156,7 +156,7 @@ def main():
                     help="skip the decoder-alone, LOD-selection, fitting and octree-build components")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, run one plain 256 MiB device copy (counter calibration)")
-    ap.add_argument("--only", choices=["query", "frame", "train", "half", "decoder"], default=None,
+    ap.add_argument("--only", choices=["query", "frame", "train", "half", "decoder", "precision"], default=None,
                     help="run a single component (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -336,30 +336,43 @@ def main():
         tr_ms = mean(ttr)
         comp["train"] = {"ms": tr_ms, "points_per_s": S["xt"].shape[1] / (tr_ms * 1e-3), "points": S["xt"].shape[1]}
 
-    # Roofline of the kernel behind `value` (the query kernel, one launch per
-    # batch, timed alone): the feature gather is priced against HBM with its
-    # algorithmic bytes; the measured HBM traffic of the same launch and the
-    # FP32 flop rate are reported beside it.  The trace (a phased pair of
-    # launches) and the training step (several kernels) report their own
-    # algorithmic rates under components.
+    # Roofline of the kernel behind `value` (the cooperative query kernel,
+    # one launch per batch, timed alone with HIP events on its stream).  Its
+    # binding roof is FP32 compute: the measured HBM traffic per launch gives
+    # an arithmetic intensity whose HBM roof (intensity x 8 TB/s) lies above
+    # the FP32 peak, and the feature table is served from the caches.  All
+    # flops (first layer on the FP32 matrix cores, trilinear weights and the
+    # second layer on the vector ALUs) are priced at the FP32 peak.  The
+    # HBM-priced view (algorithmic bytes, which the caches absorb, and the
+    # measured traffic) is kept beside it.
     roof = None
-    cand = []
     if do_q:
-        cand.append(("k_query", comp["query"]["ms"], QUERY_BYTES * cfg.n_query, EVAL_FLOPS * cfg.n_query))
-        comp["query"]["algorithmic_GBps"] = QUERY_BYTES * cfg.n_query / (comp["query"]["ms"] * 1e6)
-        comp["query"]["hbm_traffic_bytes"] = measured_traffic("k_query")
+        ms = comp["query"]["ms"]
+        nbytes, flops = QUERY_BYTES * cfg.n_query, EVAL_FLOPS * cfg.n_query
+        traffic = measured_traffic("k_query")
+        tfl = flops / (ms * 1e-3) / 1e12
+        comp["query"]["algorithmic_GBps"] = nbytes / (ms * 1e6)
+        comp["query"]["hbm_traffic_bytes"] = traffic
+        roof = {"kernel": "k_query_coop", "bound": "mfma", "achieved": tfl, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": tfl / FP32_PEAK_TFLOPS, "traffic": traffic,
+                "flops_per_launch": flops, "flops_per_query": EVAL_FLOPS,
+                "hbm": {"algorithmic_bytes_per_launch": nbytes, "algorithmic_GBps": nbytes / (ms * 1e6),
+                        "measured_GBps": traffic / (ms * 1e6) if traffic else None,
+                        "measured_frac": traffic / (ms * 1e6) / HBM_PEAK_GBS if traffic else None,
+                        "hbm_roof_tflops": (flops / traffic) * HBM_PEAK_GBS / 1e3 if traffic else None},
+                "targets": {"north_star_gather_hbm_frac": 0.5, "north_star_decoder_mfma_frac": 0.4}}
     if do_f:
         ev = comp["frame"]["sdf_evals"]
-        comp["frame"]["trace_algorithmic_GBps"] = TRACE_STEP_BYTES * ev / (comp["frame"]["trace_ms"] * 1e6)
-        comp["frame"]["trace_hbm_traffic_bytes"] = measured_traffic("k_sphere_trace")
-    if cand:
-        name, ms, nbytes, flops = cand[0]
-        if nbytes is not None:
-            ach = nbytes / (ms * 1e-3) / 1e9
-            tfl = flops / (ms * 1e-3) / 1e12
-            roof = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(name),
-                    "algorithmic_bytes": nbytes, "fp32_tflops": tfl, "fp32_frac": tfl / FP32_PEAK_TFLOPS}
+        tms = comp["frame"]["trace_ms"]
+        traffic = measured_traffic("k_sphere_trace")
+        tfl = EVAL_FLOPS * ev / (tms * 1e-3) / 1e12
+        comp["frame"]["trace_roofline"] = {
+            "kernels": "k_sphere_trace + k_sphere_trace_wide", "bound": "mfma", "achieved": tfl,
+            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tfl / FP32_PEAK_TFLOPS,
+            "algorithmic_GBps": TRACE_STEP_BYTES * ev / (tms * 1e6), "traffic": traffic,
+            "measured_hbm_frac": traffic / (tms * 1e6) / HBM_PEAK_GBS if traffic else None}
+        comp["frame"]["trace_algorithmic_GBps"] = TRACE_STEP_BYTES * ev / (tms * 1e6)
+        comp["frame"]["trace_hbm_traffic_bytes"] = traffic
 
     if args.calibrate_copy:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
@@ -376,11 +389,15 @@ def main():
         comp["decoder_bf16"] = run_decoder(S, dev, args.steps, args.warmup)
     if args.only is None and not args.no_extras:
         comp["frame_lod_select"] = run_lod_select(model, cfg, o, d, buf, args.steps, args.warmup)
+    if args.only == "precision" or (args.only is None and not args.no_extras):
+        comp["precision"] = run_precision(dev, max(3, args.steps // 2), 1)
+    if args.only is None and not args.no_extras:
         comp["fit"] = run_fit(S, dev)
         comp["octree_build"] = run_octree_build(dev, args.steps)
         if do_h:
             hq = comp["bf16_form"]["queries_per_s"] * DEC_MFMA_FLOPS / 1e12
-            comp["bf16_form"]["fused_decoder_mfma_frac"] = hq / BF16_PEAK_TFLOPS
+            # computed from the query rate (the counters of the fused kernel are in profiles/)
+            comp["bf16_form"]["fused_decoder_mfma_frac_computed"] = hq / BF16_PEAK_TFLOPS
 
     cpu = None
     if not args.no_cpu and do_q:
@@ -430,14 +447,105 @@ def run_decoder(S, dev, steps, warmup):
             "note": "2*32*128 flops per point (first layer on z); inputs 80 B per point"}
 
 
-def run_lod_select(model, cfg, o, d, buf, steps, warmup):
-    """The step's 1024^2 frame with per-pixel LOD selection: LOD 5 up to
-    distance 1.6 from the eye, LOD 2 from 3.2 on, linear in between (the
-    traversal runs to the LOD-5 depth; rays are grouped by LOD on the
-    device and each group is traced with its two decoders)."""
+LOD_SELECT = (2.0, 3.0, 5.0, 2.0)  # d_near, d_far, lod_near, lod_far
+
+
+def run_precision(dev, steps, warmup):
+    """The precision workload: 7 LODs (resolutions 4..256) over a seeded union
+    of 32 spheres and 4 tori, 32-dim FP16 features, BF16 decoders on the
+    matrix cores (SDF-embedded features read through every hidden unit),
+    packed.  Timed: 2^22 queries (half uniform, half near-surface) at
+    L = 5 + alpha with alpha ~ U[0,1) per query, and one 1920x1080 frame
+    (camera, traversal to depth 7, trace at L = 5 + alpha for one seeded
+    alpha, FD normals at the hits).  The FP32 form of the same stored values
+    (FP32 matrix-core decoder) runs the same queries and frame once for the
+    BF16 form's error."""
     import torch
     from paper_2101_10994_amd import ngl
-    sel = ngl.lod_select(1.6, 3.2, 5.0, 2.0)
+    from paper_2101_10994_amd import workloads as W
+    cfg = W.PREC
+    t0 = time.perf_counter()
+    shape = W.prec_shape(0)
+    ijk = W.occupancy_ijk(shape, 256)
+    tree = ngl.Octree(ijk, cfg.num_lods, device=dev)
+    rs = W.rngs(0)
+    feats = W.embedded_features(rs[W.STREAM_FEAT], shape, tree.corner_positions(), cfg.feat_dim)
+    dec = W.spread_decoders(rs[W.STREAM_DEC], cfg.num_lods, cfg.feat_dim, cfg.hidden)
+    f32 = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+    b1, w2, b2 = [f32(b) for b in dec["b1"]], [f32(w) for w in dec["w2"]], f32(dec["b2"])
+    half = ngl.Model(tree, [f32(f).half() for f in feats], [f32(w).bfloat16() for w in dec["W1"]], b1, w2, b2,
+                     pack=True)
+    full = ngl.Model(tree, [f.float() for f in half.feats], [w.float() for w in half.W1], b1, w2, b2, pack=True)
+    x = torch.from_numpy(W.soa(W.paper_queries(0, shape, cfg.n_query))).to(dev)
+    app = torch.from_numpy(np.random.default_rng(5).uniform(0, 1, cfg.n_query).astype(np.float32)).to(dev)
+    alpha = float(np.float32(np.random.default_rng(1080).uniform(0.0, 1.0)))
+    lod = cfg.query_lod
+    depth = lod + 2
+    R = cfg.width * cfg.height
+    o = torch.empty((3, R), dtype=torch.float32, device=dev)
+    d = torch.empty((3, R), dtype=torch.float32, device=dev)
+    ngl.camera_rays(cfg.eye, (0, 0, 0), (0, 1, 0), 45.0, cfg.width, cfg.height, out=(o, d))
+    first = ngl.trace_octree(half, o, d, depth)
+    buf = ngl.TraceBuffers(R, first["max_list"], dev)
+    hits = dict(vox=buf.vox, t_in=buf.t_in, t_out=buf.t_out, ray_off=buf.ray_off)
+    mk = lambda: dict(t=torch.empty(R, dtype=torch.float32, device=dev),
+                      status=torch.empty(R, dtype=torch.uint8, device=dev),
+                      steps=torch.empty(R, dtype=torch.int32, device=dev),
+                      hit_vox=torch.empty(R, dtype=torch.int32, device=dev))
+    tr, tr32 = mk(), mk()
+    sdf = torch.empty(cfg.n_query, dtype=torch.float32, device=dev)
+    nrm = torch.empty((3, R), dtype=torch.float32, device=dev)
+    h_fd = 2.0 / 256 / 16.0
+    setup_s = time.perf_counter() - t0
+    tq, tc, tt, ts, tn = Timer(), Timer(), Timer(), Timer(), Timer()
+    for k in range(warmup + steps):
+        timed = k >= warmup
+        with (tq if timed else Timer()):
+            ngl.query_sdf(half, x, lod, alpha_pp=app, out=sdf)
+        with (tc if timed else Timer()):
+            ngl.camera_rays(cfg.eye, (0, 0, 0), (0, 1, 0), 45.0, cfg.width, cfg.height, out=(o, d))
+        with (tt if timed else Timer()):
+            ngl.trace_octree_into(half, o, d, depth, buf)
+        with (ts if timed else Timer()):
+            ngl.sphere_trace(half, o, d, lod, alpha, hits, cfg.max_steps, cfg.delta, out=tr)
+        with (tn if timed else Timer()):
+            ngl.sdf_normals(half, lod, alpha, h_fd, rays=(o, d, tr["t"], tr["status"]), out=nrm)
+    torch.cuda.synchronize()
+    assert int(buf.counts[1]) <= buf.capacity, "pair list overflowed during timing"
+    med = lambda tm: float(np.median(tm.values()))
+    sdf32 = ngl.query_sdf(full, x, lod, alpha_pp=app)["sdf"]
+    ngl.sphere_trace(full, o, d, lod, alpha, hits, cfg.max_steps, cfg.delta, out=tr32)
+    torch.cuda.synchronize()
+    st, st32 = tr["status"].cpu().numpy(), tr32["status"].cpu().numpy()
+    both = (st == ngl.HIT) & (st32 == ngl.HIT)
+    dt = np.abs(tr["t"].cpu().numpy()[both].astype(np.float64) - tr32["t"].cpu().numpy()[both]) / (2.0 / 256)
+    err = (sdf - sdf32).abs()
+    frame_ms = med(tc) + med(tt) + med(ts) + med(tn)
+    return {"lods": cfg.num_lods, "finest_res": 256, "voxels": int(tree.nvox.sum()), "corners": int(tree.ncorner.sum()),
+            "features": "f16", "decoder": "bf16 MFMA (activations as bf16 hi+lo), fp32 accumulate",
+            "queries": cfg.n_query, "query_lod": "5 + alpha, alpha ~ U[0,1) per query",
+            "query_ms": med(tq), "queries_per_s": cfg.n_query / (med(tq) * 1e-3),
+            "image": [cfg.width, cfg.height], "frame_alpha": alpha, "frame_ms": frame_ms, "fps": 1e3 / frame_ms,
+            "camera_ms": med(tc), "traverse_ms": med(tt), "trace_ms": med(ts), "normals_ms": med(tn),
+            "final_pairs": int(buf.counts[0]), "visible_px": int((st == ngl.HIT).sum()),
+            "sdf_evals": int(tr["steps"].sum()),
+            "vs_fp32_form": {"max_abs_sdf_diff": float(err.max()), "median_abs_sdf_diff": float(err.median()),
+                             "status_agree_frac": float((st == st32).mean()),
+                             "hit_dt_finest_voxels_p50": float(np.median(dt)) if dt.size else None,
+                             "hit_dt_finest_voxels_p999": float(np.quantile(dt, 0.999)) if dt.size else None,
+                             "hit_dt_finest_voxels_max": float(dt.max()) if dt.size else None},
+            "setup_s": setup_s}
+
+
+def run_lod_select(model, cfg, o, d, buf, steps, warmup):
+    """The step's 1024^2 frame with per-pixel LOD selection: LOD 5 up to
+    distance 2.0 from the eye (the nearest surfaces are at about 1.6), LOD 2
+    from 3.0 on, linear in between (the traversal runs to the LOD-5 depth;
+    rays are grouped by LOD on the device and each group is traced with its
+    two decoders)."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    sel = ngl.lod_select(*LOD_SELECT)
     hits = dict(vox=buf.vox, t_in=buf.t_in, t_out=buf.t_out, ray_off=buf.ray_off)
     tt, ts = Timer(), Timer()
     out = None
@@ -455,7 +563,7 @@ def run_lod_select(model, cfg, o, d, buf, steps, warmup):
     st = out["status"].cpu().numpy()
     hit = st == ngl.HIT
     trav, trace = float(np.mean(tt.values())), float(np.mean(ts.values()))
-    return {"selection": {"d_near": 1.6, "d_far": 3.2, "lod_near": 5.0, "lod_far": 2.0},
+    return {"selection": dict(zip(("d_near", "d_far", "lod_near", "lod_far"), LOD_SELECT)),
             "traverse_ms": trav, "trace_ms": trace, "ms": trav + trace, "visible_px": int(hit.sum()),
             "sdf_evals": int(out["steps"].sum()), "mean_lod_of_hits": float(lod[hit].mean()) if hit.any() else None,
             "rays_per_lod": {str(L): int(((np.floor(lod) == L) | ((L == 5) & (lod >= 5))).sum()) for L in (2, 3, 4, 5)}}
@@ -533,10 +641,11 @@ def run_batch(dev, steps, warmup):
         tree = ngl.Octree(ijk, L, device=dev)
         rs = W.rngs(100 + i)
         feats = W.embedded_features(rs[W.STREAM_FEAT], it["shape"], tree.corner_positions(), cfg.feat_dim)
-        dec = W.embedded_decoders(rs[W.STREAM_DEC], L, cfg.feat_dim, cfg.hidden)
+        dec = W.spread_decoders(rs[W.STREAM_DEC], L, cfg.feat_dim, cfg.hidden)
         f32 = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
         models.append(ngl.Model(tree, [f32(f).half() for f in feats], [f32(w).bfloat16() for w in dec["W1"]],
-                                [f32(b) for b in dec["b1"]], [f32(w) for w in dec["w2"]], f32(dec["b2"])))
+                                [f32(b) for b in dec["b1"]], [f32(w) for w in dec["w2"]], f32(dec["b2"]),
+                                pack=True))
         views.append(ngl.make_view(it["camera"].eye, cfg.width, cfg.height, it["lod"]))
     setup_s = time.perf_counter() - t0
     cap = 1 << 22
@@ -586,9 +695,21 @@ def run_batch(dev, steps, warmup):
     return out
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(S, budget_s):
     """The FP64 oracle on a bounded sample of the same workload, timed on the
-    host cores; scaled to the metric's unit."""
+    host cores (median of 3 runs after one warm-up, and once on one thread);
+    scaled to the metric's unit."""
     import oracle
     cfg = S["cfg"]
     t0 = time.perf_counter()
@@ -602,39 +723,73 @@ def cpu_baseline(S, budget_s):
                       np.asarray(dec["b2"], np.float32).astype(np.float64))
     build_s = time.perf_counter() - t0
     cores = oracle.max_threads()
-    # queries: grow the sample until about a third of the budget is spent
+
+    def median3(fn):
+        fn()
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    def one_thread(fn):
+        oracle.set_threads(1)
+        try:
+            t = time.perf_counter()
+            fn()
+            return time.perf_counter() - t
+        finally:
+            oracle.set_threads(cores)
+
+    # queries: grow the sample until one run takes about a twelfth of the budget
     n = 4096
     xq = S["xq_host"]
     while True:
         t0 = time.perf_counter()
         oracle.query(otree, om, np.ascontiguousarray(xq[:, :n]), cfg.num_lods)
         dt = time.perf_counter() - t0
-        if dt > budget_s / 6 or n >= xq.shape[1]:
+        if dt > budget_s / 12 or n >= xq.shape[1]:
             break
         n = min(xq.shape[1], n * 4)
-    qps = n / dt
+    xs = np.ascontiguousarray(xq[:, :n])
+    qps = n / median3(lambda: oracle.query(otree, om, xs, cfg.num_lods))
+    n1 = max(1024, n // max(cores, 1))
+    x1 = np.ascontiguousarray(xq[:, :n1])
+    qps1 = n1 / one_thread(lambda: oracle.query(otree, om, x1, cfg.num_lods))
     # frame: every k-th ray of the 1024^2 camera, scaled to the full frame
     co, cd = oracle.camera_rays(cfg.eye, (0, 0, 0), (0, 1, 0), 45.0, cfg.width, cfg.height)
-    stride = 64
-    idx = np.arange(0, cfg.width * cfg.height, stride)
-    o = np.ascontiguousarray(co[:, idx].astype(np.float32))
-    d = np.ascontiguousarray(cd[:, idx].astype(np.float32))
-    t0 = time.perf_counter()
-    hits = oracle.trace_octree(otree, o, d, cfg.num_lods + 1)
-    r = oracle.sphere_trace(otree, om, o, d, cfg.num_lods, 0.0, hits, cfg.max_steps, cfg.delta)
     h_fd = 2.0 / (4 << (cfg.num_lods - 1)) / 16.0
-    oracle.normals(otree, om, cfg.num_lods, 0.0, h_fd, rays=(o, d, r["t"].astype(np.float32), r["status"]))
-    frame_s = (time.perf_counter() - t0) * stride
-    out = {"value": qps, "unit": "queries/s", "cores": cores, "kind": "oracle",
-           "sample": "%d of the 2^20 queries at LOD 5; frame from every %dth ray of the 1024^2 camera "
-                     "(traversal + trace + normals), scaled x%d" % (n, stride, stride),
-           "fps_1024": 1.0 / frame_s, "octree_build_s": build_s}
+
+    def frame(stride):
+        idx = np.arange(0, cfg.width * cfg.height, stride)
+        o = np.ascontiguousarray(co[:, idx].astype(np.float32))
+        d = np.ascontiguousarray(cd[:, idx].astype(np.float32))
+
+        def run():
+            hits = oracle.trace_octree(otree, o, d, cfg.num_lods + 1)
+            r = oracle.sphere_trace(otree, om, o, d, cfg.num_lods, 0.0, hits, cfg.max_steps, cfg.delta)
+            oracle.normals(otree, om, cfg.num_lods, 0.0, h_fd, rays=(o, d, r["t"].astype(np.float32), r["status"]))
+        return run
+
+    stride = 16
+    frame_s = median3(frame(stride)) * stride
+    stride1 = stride * max(cores, 1)
+    frame1_s = one_thread(frame(stride1)) * stride1
     # training step on a sample
     nt = 8192
-    t0 = time.perf_counter()
-    oracle.train_fwd_bwd(otree, om, np.ascontiguousarray(S["xt_host"][:, :nt]), S["tg_host"][:nt])
-    out["train_points_per_s"] = nt / (time.perf_counter() - t0)
-    return out
+    xt = np.ascontiguousarray(S["xt_host"][:, :nt])
+    tp = nt / median3(lambda: oracle.train_fwd_bwd(otree, om, xt, S["tg_host"][:nt]))
+    nt1 = 1024
+    xt1 = np.ascontiguousarray(S["xt_host"][:, :nt1])
+    tp1 = nt1 / one_thread(lambda: oracle.train_fwd_bwd(otree, om, xt1, S["tg_host"][:nt1]))
+    return {"value": qps, "unit": "queries/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": "%d of the 2^20 queries at LOD 5; frame from every %dth ray of the 1024^2 camera "
+                      "(traversal + trace + normals), scaled x%d; training on %d points; median of 3 runs "
+                      "after a warm-up; one-thread runs on %d queries, every %dth ray, %d training points"
+                      % (n, stride, stride, nt, n1, stride1, nt1),
+            "fps_1024": 1.0 / frame_s, "train_points_per_s": tp, "octree_build_s": build_s,
+            "one_thread": {"queries_per_s": qps1, "fps_1024": 1.0 / frame1_s, "train_points_per_s": tp1}}
 
 
 if __name__ == "__main__":
