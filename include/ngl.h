@@ -365,6 +365,24 @@ int ngl_sphere_trace_workspace(size_t* bytes);
  * workspace below this size runs the single launch. */
 int ngl_sphere_trace_workspace_rays(int64_t R, size_t* bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ngl_sphere_trace with its phased workspace in a device array the library
+ * owns (one per GPU, NGL_STATIC_TRACE_BYTES, held until the process ends)
+ * instead of a caller workspace.  Same arguments and results as
+ * ngl_sphere_trace with a workspace of ngl_sphere_trace_workspace_rays(R)
+ * bytes, for R <= NGL_STATIC_TRACE_MAX_RAYS (NGL_E_CAPACITY above).  The
+ * call allocates nothing: it runs no hipMalloc/hipFree and the array's
+ * counters are cleared by a kernel on `stream`.  Every call on one GPU
+ * shares that GPU's array, so calls that overlap on one GPU (other streams,
+ * other threads) race: serialise them. */
+#define NGL_STATIC_TRACE_MAX_RAYS (1 << 21)
+#define NGL_STATIC_TRACE_BYTES (256 + 6 * 4 * (size_t)NGL_STATIC_TRACE_MAX_RAYS)
+int ngl_sphere_trace_static(const ngl_model* m, const float* o, const float* d, int64_t R, int32_t lod,
+                            float alpha, const int32_t* pair_vox, const float* t_in, const float* t_out,
+                            const int32_t* ray_off, const ngl_trace_params* params, float* t_hit,
+                            uint8_t* status, int32_t* steps, int32_t* hit_vox, void* stream);
+
 /* Per-pixel LOD selection (Sec. 3.4, LOD Selection): the continuous LOD of
  * a ray moves linearly from lod_near at distance d_near to lod_far at
  * d_far (constant outside), where the distance is the entry t of the ray's

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 namespace ngl {
 
@@ -23,8 +24,8 @@ struct PhaseWS {
   int32_t* st_k;
   float* st_prev;
   int32_t* ids[2];
-  static size_t align(size_t b) { return (b + 255) & ~size_t(255); }
-  static size_t bytes(int64_t R) { return 256 + 6 * align(4 * size_t(R)); }
+  static constexpr size_t align(size_t b) { return (b + 255) & ~size_t(255); }
+  static constexpr size_t bytes(int64_t R) { return 256 + 6 * align(4 * size_t(R)); }
   PhaseWS(void* ws, int64_t R) {
     char* p = static_cast<char*>(ws);
     const size_t a = align(4 * size_t(R));
@@ -40,6 +41,33 @@ struct PhaseWS {
 
 __global__ void k_phase_init(unsigned* c) {
   if (threadIdx.x < 8) c[threadIdx.x] = 0u;
+}
+
+// Workspace of ngl_sphere_trace_static: the phased layout for
+// NGL_STATIC_TRACE_MAX_RAYS rays (4 * R is a multiple of 256, so PhaseWS's
+// aligned arrays fill it exactly).  Host code never passes this name to a
+// kernel: its device address, per GPU, comes from static_trace_ws().
+static_assert(PhaseWS::bytes(NGL_STATIC_TRACE_MAX_RAYS) == NGL_STATIC_TRACE_BYTES, "static trace workspace size");
+static __device__ __align__(256) char scratch[NGL_STATIC_TRACE_BYTES];
+
+// Device address of `scratch` on the current GPU, looked up once per GPU
+// (each GPU holds its own copy of the array).
+static int static_trace_ws(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  NGL_HIP(hipGetDevice(&dev));
+  NGL_REQUIRE(dev >= 0 && dev < kMaxDevices, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    NGL_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    NGL_REQUIRE(p != nullptr, "no device address for the static trace workspace");
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return NGL_OK;
 }
 
 static int batch_by_width(const ngl_model& m, const BatchArgs& B, bool any_blend, hipStream_t s) {
@@ -211,6 +239,20 @@ int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t
     if (rc) return rc;
   }
   return NGL_OK;
+}
+
+int ngl_sphere_trace_static(const ngl_model* m, const float* o, const float* d, int64_t R, int32_t lod,
+                            float alpha, const int32_t* pair_vox, const float* t_in, const float* t_out,
+                            const int32_t* ray_off, const ngl_trace_params* params, float* t_hit,
+                            uint8_t* status, int32_t* steps, int32_t* hit_vox, void* stream) {
+  if (R > NGL_STATIC_TRACE_MAX_RAYS)
+    NGL_FAIL(NGL_E_CAPACITY, "ngl_sphere_trace_static: %lld rays exceed NGL_STATIC_TRACE_MAX_RAYS (%d)",
+             (long long)R, NGL_STATIC_TRACE_MAX_RAYS);
+  void* ws = nullptr;
+  int rc = ngl::static_trace_ws(&ws);
+  if (rc) return rc;
+  return ngl_sphere_trace(m, o, d, R, lod, alpha, pair_vox, t_in, t_out, ray_off, params, t_hit, status, steps,
+                          hit_vox, ws, NGL_STATIC_TRACE_BYTES, stream);
 }
 
 int ngl_sphere_trace_workspace_rays(int64_t R, size_t* bytes) {

@@ -114,6 +114,7 @@ EXPORTS = {
     "ngl_packed_decoder_bytes": (C.c_int, [P, P]),
     "ngl_pack_decoders": (C.c_int, [P, P, C.c_size_t, P]),
     "ngl_workspace_bytes": (C.c_int, [C.c_int, P, i64, i64, P]),
+    "ngl_sphere_trace_static": (C.c_int, [P, P, P, i64, i32, C.c_float, P, P, P, P, P, P, P, P, P, P]),
 }
 
 # ngl_workspace_bytes operations
@@ -606,6 +607,29 @@ def sphere_trace(model: Model, o, d, lod: int, alpha: float, hits: dict, max_ste
                                   _ptr(hits["t_in"]), _ptr(hits["t_out"]), _ptr(hits["ray_off"]), C.addressof(prm),
                                   _ptr(out["t"]), _ptr(out["status"]), _ptr(out["steps"]), _ptr(out["hit_vox"]),
                                   _ptr(out["ws"]), out["ws"].numel(), _stream()))
+    return out
+
+
+STATIC_TRACE_MAX_RAYS = 1 << 21
+
+
+def sphere_trace_static(model: Model, o, d, lod: int, alpha: float, hits: dict, max_steps: int, delta: float,
+                        t_far: float = 5.0, osc_check: bool = False, out=None):
+    """Sphere trace one view without a caller workspace
+    (ngl_sphere_trace_static: the library's per-GPU array, no allocation in
+    the call; calls on one GPU must not overlap)."""
+    R = o.shape[1]
+    dev = o.device
+    if out is None:
+        out = dict(t=torch.empty(R, dtype=torch.float32, device=dev),
+                   status=torch.empty(R, dtype=torch.uint8, device=dev),
+                   steps=torch.empty(R, dtype=torch.int32, device=dev),
+                   hit_vox=torch.empty(R, dtype=torch.int32, device=dev))
+    prm = trace_params(max_steps, delta, t_far, osc_check)
+    _check(lib().ngl_sphere_trace_static(model.ref, _ptr(o), _ptr(d), R, int(lod), float(alpha), _ptr(hits["vox"]),
+                                         _ptr(hits["t_in"]), _ptr(hits["t_out"]), _ptr(hits["ray_off"]),
+                                         C.addressof(prm), _ptr(out["t"]), _ptr(out["status"]), _ptr(out["steps"]),
+                                         _ptr(out["hit_vox"]), _stream()))
     return out
 
 
