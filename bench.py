@@ -235,13 +235,13 @@ def main():
                 with tt:
                     ngl.trace_octree_into(model, o, d, lod + 1, buf)
                 with ts:
-                    ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr)
+                    ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr, image_width=W_)
                 with tn:
                     ngl.sdf_normals(model, lod, 0.0, h_fd, rays=(o, d, tr["t"], tr["status"]), out=nrm)
             else:
                 ngl.camera_rays(eye, (0, 0, 0), (0, 1, 0), 45.0, W_, H_, out=(o, d))
                 ngl.trace_octree_into(model, o, d, lod + 1, buf)
-                ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr)
+                ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr, image_width=W_)
                 ngl.sdf_normals(model, lod, 0.0, h_fd, rays=(o, d, tr["t"], tr["status"]), out=nrm)
         if do_v:
             # FP32 decoder on the vector ALUs (the per-lane form), for comparison
@@ -250,10 +250,10 @@ def main():
                 with tvq:
                     ngl.query_sdf(model, S["xq"], lod, out=sdf_v)
                 with tvs:
-                    ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_v)
+                    ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_v, image_width=W_)
             else:
                 ngl.query_sdf(model, S["xq"], lod, out=sdf_v)
-                ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_v)
+                ngl.sphere_trace(model, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_v, image_width=W_)
             ngl.set_option(ngl.OPT_F32_DECODER, f32_mode)
         if do_h:
             # BF16-MFMA form: same queries; the trace reuses the frame's hit lists
@@ -264,12 +264,12 @@ def main():
                 with thq:
                     ngl.query_sdf(half, S["xq"], lod, out=sdf_h)
                 with ths:
-                    ngl.sphere_trace(half, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_h)
+                    ngl.sphere_trace(half, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_h, image_width=W_)
                 with thn:
                     ngl.sdf_normals(half, lod, 0.0, h_fd, rays=(o, d, tr_h["t"], tr_h["status"]), out=nrm_h)
             else:
                 ngl.query_sdf(half, S["xq"], lod, out=sdf_h)
-                ngl.sphere_trace(half, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_h)
+                ngl.sphere_trace(half, o, d, lod, 0.0, hits, cfg.max_steps, cfg.delta, out=tr_h, image_width=W_)
                 ngl.sdf_normals(half, lod, 0.0, h_fd, rays=(o, d, tr_h["t"], tr_h["status"]), out=nrm_h)
         if do_t:
             if timed:
@@ -507,14 +507,14 @@ def run_precision(dev, steps, warmup):
         with (tt if timed else Timer()):
             ngl.trace_octree_into(half, o, d, depth, buf)
         with (ts if timed else Timer()):
-            ngl.sphere_trace(half, o, d, lod, alpha, hits, cfg.max_steps, cfg.delta, out=tr)
+            ngl.sphere_trace(half, o, d, lod, alpha, hits, cfg.max_steps, cfg.delta, out=tr, image_width=cfg.width)
         with (tn if timed else Timer()):
             ngl.sdf_normals(half, lod, alpha, h_fd, rays=(o, d, tr["t"], tr["status"]), out=nrm)
     torch.cuda.synchronize()
     assert int(buf.counts[1]) <= buf.capacity, "pair list overflowed during timing"
     med = lambda tm: float(np.median(tm.values()))
     sdf32 = ngl.query_sdf(full, x, lod, alpha_pp=app)["sdf"]
-    ngl.sphere_trace(full, o, d, lod, alpha, hits, cfg.max_steps, cfg.delta, out=tr32)
+    ngl.sphere_trace(full, o, d, lod, alpha, hits, cfg.max_steps, cfg.delta, out=tr32, image_width=cfg.width)
     torch.cuda.synchronize()
     st, st32 = tr["status"].cpu().numpy(), tr32["status"].cpu().numpy()
     both = (st == ngl.HIT) & (st32 == ngl.HIT)

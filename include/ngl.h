@@ -330,6 +330,11 @@ typedef struct {
   int32_t osc_check;  /* 1: stop (STALLED) when |d_k - d_{k-1}| < 6 delta */
   int32_t analytic;   /* 1: replace the model by the exact SDF of `sphere` */
   float sphere[4];    /* cx, cy, cz, radius for analytic mode */
+  int32_t image_width; /* > 0: the rays are an image of this width, row-major
+                          (a multiple of 8, and R a multiple of 8 widths); they
+                          are then handed to the wavefronts in 8x8 pixel tiles,
+                          so a wavefront's rays meet nearby voxels.  0: in ray
+                          order.  Results do not depend on it. */
 } ngl_trace_params;
 
 /* Adaptive-stepping sphere trace (Sec. 3.4, Fig. 3) over the hit lists of

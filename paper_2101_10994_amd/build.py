@@ -43,12 +43,26 @@ def _compile(src: str) -> str:
     return obj
 
 
+def _includes(path: str, seen: set) -> set:
+    """The project headers `path` includes, directly or not."""
+    import re
+    with open(path) as f:
+        for name in re.findall(r'^\s*#\s*include\s+"([^"]+)"', f.read(), flags=re.M):
+            for d in (CSRC, INCLUDE):
+                h = os.path.join(d, name)
+                if os.path.exists(h) and h not in seen:
+                    seen.add(h)
+                    _includes(h, seen)
+                    break
+    return seen
+
+
 def _stale(src: str) -> bool:
-    """The object is missing or older than its source or any header."""
+    """The object is missing or older than its source or a header it includes."""
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
     if not os.path.exists(obj):
         return True
-    deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+    deps = [src] + sorted(_includes(src, set()))
     t = os.path.getmtime(obj)
     return any(os.path.getmtime(d) > t for d in deps)
 

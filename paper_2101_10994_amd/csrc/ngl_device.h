@@ -186,6 +186,61 @@ __device__ inline bool slab_f32(const float o[3], const float inv[3], const floa
   return ok && (tmax >= t0c);
 }
 
+// Slab tests of the eight children of cell c (packed) at `depth` against one
+// ray.  The children's boxes along axis a are bounded by three planes
+// p_k = -1 + (2 c_a + k) 2^-depth, k = 0, 1, 2 (exact dyadic values, the
+// same expressions box_of gives for the child cells), so the plane
+// distances (p_k - o_a) inv_a are formed once per axis; each child then
+// takes the same compare-and-select steps, in the same order, as slab_f32
+// on its own box, so every result is the same bits.
+struct ChildSlabs {
+  float nr[3][2], fr[3][2];  // near and far distance per axis and child bit
+  bool inside[3][2];         // axes with infinite inv: o within the child's extent
+  bool inf[3];
+  __device__ ChildSlabs(const float o[3], const float inv[3], uint32_t c, int depth) {
+#pragma clang fp contract(off)
+    const float step = 2.0f / float(1 << (depth + 1));
+    const int ijk[3] = {cell_x(c), cell_y(c), cell_z(c)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int b2 = 2 * ijk[a];
+      const float p[3] = {-1.0f + float(b2) * step, -1.0f + float(b2 + 1) * step, -1.0f + float(b2 + 2) * step};
+      inf[a] = __builtin_isinf(inv[a]);
+      float t[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) t[k] = (p[k] - o[a]) * inv[a];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        inside[a][b] = p[b] <= o[a] && o[a] <= p[b + 1];
+        const float t0 = t[b], t1 = t[b + 1];
+        nr[a][b] = t0 < t1 ? t0 : t1;
+        fr[a][b] = t0 < t1 ? t1 : t0;
+      }
+    }
+  }
+  // child ch = bx | by << 1 | bz << 2
+  __device__ bool test(int ch, float& t_in, float& t_out) const {
+#pragma clang fp contract(off)
+    float tmin = -__builtin_inff(), tmax = __builtin_inff();
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int b = (ch >> a) & 1;
+      if (inf[a]) {
+        ok = ok && inside[a][b];
+      } else {
+        const float n = nr[a][b], f = fr[a][b];
+        tmin = n > tmin ? n : tmin;
+        tmax = f < tmax ? f : tmax;
+      }
+    }
+    const float t0c = tmin > 0.0f ? tmin : 0.0f;
+    t_in = t0c;
+    t_out = tmax;
+    return ok && (tmax >= t0c);
+  }
+};
+
 // Box of cell `c` (packed) at `depth`; exact dyadic bounds.
 __device__ inline void box_of(uint32_t c, int depth, float lo[3], float hi[3]) {
   const float step = 2.0f / float(1 << depth);

@@ -28,23 +28,37 @@ static __global__ __launch_bounds__(kBlock) void k_radix_hist(const uint32_t* __
   hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of n uint32 values in place by one block of 1024 lanes;
-// *total (nullable) receives the sum.
+// Exclusive scan of n uint32 values in place by one block of 1024 lanes
+// (a must be 16-byte aligned); *total (nullable) receives the sum.  Each
+// lane owns 32 consecutive values of a tile of 32 Ki values and loads them
+// as eight 16-byte vectors, so a tile's loads are all in flight together
+// (the radix-sort histograms, 256 x grid values, take a few tiles).
 static __global__ __launch_bounds__(1024) void k_scan_inplace(uint32_t* __restrict__ a, int64_t n, uint32_t* total) {
-  constexpr int ITEMS = 8;
+  constexpr int ITEMS = 32;
   __shared__ uint32_t part[16];
   __shared__ uint32_t carry_s;
   if (threadIdx.x == 0) carry_s = 0;
   __syncthreads();
   for (int64_t base = 0; base < n; base += 1024 * ITEMS) {
     uint32_t v[ITEMS];
-    uint32_t local = 0;
     const int64_t b0 = base + int64_t(threadIdx.x) * ITEMS;
+    if (b0 + ITEMS <= n) {
+      const uint4* src = reinterpret_cast<const uint4*>(a + b0);
 #pragma unroll
-    for (int q = 0; q < ITEMS; ++q) {
-      v[q] = b0 + q < n ? a[b0 + q] : 0u;
-      local += v[q];
+      for (int q = 0; q < ITEMS / 4; ++q) {
+        const uint4 u = src[q];
+        v[4 * q] = u.x;
+        v[4 * q + 1] = u.y;
+        v[4 * q + 2] = u.z;
+        v[4 * q + 3] = u.w;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < ITEMS; ++q) v[q] = b0 + q < n ? a[b0 + q] : 0u;
     }
+    uint32_t local = 0;
+#pragma unroll
+    for (int q = 0; q < ITEMS; ++q) local += v[q];
     uint32_t x = local;
     const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -62,10 +76,27 @@ static __global__ __launch_bounds__(1024) void k_scan_inplace(uint32_t* __restri
       tot += s;
     }
     uint32_t run = carry_s + pre + x - local;
+    if (b0 + ITEMS <= n) {
+      uint4* dst = reinterpret_cast<uint4*>(a + b0);
 #pragma unroll
-    for (int q = 0; q < ITEMS; ++q) {
-      if (b0 + q < n) a[b0 + q] = run;
-      run += v[q];
+      for (int q = 0; q < ITEMS / 4; ++q) {
+        uint4 u;
+        u.x = run;
+        run += v[4 * q];
+        u.y = run;
+        run += v[4 * q + 1];
+        u.z = run;
+        run += v[4 * q + 2];
+        u.w = run;
+        run += v[4 * q + 3];
+        dst[q] = u;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < ITEMS; ++q) {
+        if (b0 + q < n) a[b0 + q] = run;
+        run += v[q];
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) carry_s += tot;

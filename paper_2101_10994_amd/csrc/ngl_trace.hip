@@ -11,6 +11,31 @@
 
 namespace ngl {
 
+// Runners per feature width: the translation unit of the model's feature
+// type (FP32, FP16 or BF16).
+#define NGL_FT_SWITCH(fn, M_, ...)                          \
+  switch (md.feat_dtype) {                                  \
+    case NGL_F32: return fn##_m##M_##_f32(__VA_ARGS__);     \
+    case NGL_F16: return fn##_m##M_##_f16(__VA_ARGS__);     \
+    default: return fn##_m##M_##_bf16(__VA_ARGS__);         \
+  }
+#define NGL_TRACE_WIDTH_RUNNERS(M_)                                                                        \
+  static int trace_run_m##M_(const ngl_model& md, const TraceArgs& A, hipStream_t s) {                     \
+    NGL_FT_SWITCH(trace_run, M_, md, A, s)                                                                 \
+  }                                                                                                        \
+  static int batch_run_m##M_(const ngl_model& md, const BatchArgs& B, bool any_blend, hipStream_t s) {     \
+    NGL_FT_SWITCH(batch_run, M_, md, B, any_blend, s)                                                      \
+  }                                                                                                        \
+  static int bucket_run_m##M_(const ngl_model& md, const BucketArgs& B, hipStream_t s) {                   \
+    NGL_FT_SWITCH(bucket_run, M_, md, B, s)                                                                \
+  }
+NGL_TRACE_WIDTH_RUNNERS(8)
+NGL_TRACE_WIDTH_RUNNERS(16)
+NGL_TRACE_WIDTH_RUNNERS(32)
+NGL_TRACE_WIDTH_RUNNERS(64)
+#undef NGL_TRACE_WIDTH_RUNNERS
+#undef NGL_FT_SWITCH
+
 static int trace_by_width(const ngl_model& m, const TraceArgs& A, hipStream_t s) {
   NGL_BY_WIDTH(m.feat_dim, trace_run, m, A, s)
 }
@@ -192,6 +217,9 @@ int ngl_sphere_trace(const ngl_model* m, const float* o, const float* d, int64_t
   NGL_REQUIRE(R >= 0 && R < (int64_t(1) << 31), "ray count out of range");
   NGL_REQUIRE(params->max_steps >= 0, "max_steps must be >= 0");
   NGL_REQUIRE(alpha >= 0.0f && alpha < 1.0f, "alpha must be in [0,1)");
+  NGL_REQUIRE(params->image_width == 0 || (params->image_width > 0 && params->image_width % 8 == 0 &&
+                                           R % (8 * int64_t(params->image_width)) == 0),
+              "image_width %d: needs a multiple of 8 and R a multiple of 8 widths", params->image_width);
   if (!analytic) {
     NGL_REQUIRE(lod >= 1 && lod <= m->num_lods, "lod %d outside 1..%d", lod, m->num_lods);
     NGL_REQUIRE(!(alpha > 0.0f) || lod < m->num_lods, "blending needs lod < num_lods");
@@ -484,7 +512,10 @@ int ngl_render_batch(const ngl_model* models, const void* table, const ngl_view*
   BatchArgs B{};
   B.table = static_cast<const ngl_model*>(table);
   B.n = n;
-  for (int i = 0; i < n; ++i) B.view[i] = BatchView{L.base[i], I.R[i], views[i].lod, views[i].alpha};
+  for (int i = 0; i < n; ++i) {
+    const bool tiles = views[i].width % 8 == 0 && views[i].height % 8 == 0;
+    B.view[i] = BatchView{L.base[i], I.R[i], views[i].lod, views[i].alpha, tiles ? views[i].width : 0};
+  }
   B.o = L.o;
   B.d = L.d;
   B.cap = pair_capacity;

@@ -104,6 +104,18 @@ __device__ __forceinline__ void ancestor_chain(const ngl_model& md, int v, int L
   }
 }
 
+// Ray served at queue position q: with an image width W (a multiple of 8,
+// the image a whole number of 8-row bands) the queue walks 8x8 pixel tiles
+// in row-major order, so 64 consecutive positions are a tile of
+// neighbouring pixels; otherwise q itself.
+__device__ inline int queue_ray(int64_t q, int W) {
+  if (W <= 0) return int(q);
+  const int64_t tile = q >> 6, tiles_x = W >> 3;
+  const int w = int(q & 63);
+  const int64_t row = (tile / tiles_x) * 8 + (w >> 3), col = (tile % tiles_x) * 8 + (w & 7);
+  return int(row * W + col);
+}
+
 #ifndef NGL_TRACE_COOP
 #define NGL_TRACE_COOP 1
 #endif
@@ -177,7 +189,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
         if (ray < 0) {
           const int64_t my = int64_t(base) + __popcll(need & ((1ull << lane) - 1ull));
           if (my < R) {
-            ray = ids ? ids[my] : int(my);
+            ray = ids ? ids[my] : queue_ray(my, A.prm.image_width);
             if (A.alpha_pp) al = A.alpha_pp[ray];
             p = A.ray_off[ray];
             e = A.ray_off[ray + 1];
@@ -470,7 +482,7 @@ __device__ __forceinline__ void serve_queue_wide(const ngl_model& md, const Trac
         if (int64_t(base) + n >= R) exhausted = true;
         const int64_t my = int64_t(base) + __popcll(need & ((1ull << lead) - 1ull));
         if (ray < 0 && my < R) {
-          ray = ids ? ids[my] : int(my);
+          ray = ids ? ids[my] : queue_ray(my, A.prm.image_width);
           if (A.alpha_pp) al = A.alpha_pp[ray];
           p = A.ray_off[ray];
           e = A.ray_off[ray + 1];
@@ -651,6 +663,7 @@ struct BatchView {
   int64_t R;
   int32_t lod;
   float alpha;
+  int32_t tile_w;    // image width when the view is served in 8x8 tiles, else 0
 };
 
 struct BatchArgs {
@@ -704,6 +717,7 @@ __device__ inline TraceArgs batch_view_args(const BatchArgs& B, int v) {
   A.t_out = B.t_out + int64_t(v) * B.cap;
   A.ray_off = B.ray_off + base + v;
   A.prm = B.prm;
+  A.prm.image_width = B.view[v].tile_w;
   A.t_hit = B.t_hit;
   A.status = B.status;
   A.steps = B.steps;
@@ -1080,27 +1094,32 @@ struct TraceOp {
   static int run(const ngl_model& md, const TraceArgs& A, hipStream_t s) { return launch_trace<M, FT, XYZ, false>(md, A, s); }
 };
 
-// Per-width runners, defined in ngl_trace_m<width>.hip.
-#define NGL_TRACE_DECLARE(M_)                                                            \
-  int trace_run_m##M_(const ngl_model& md, const TraceArgs& A, hipStream_t s);           \
-  int batch_run_m##M_(const ngl_model& md, const BatchArgs& B, bool any_blend, hipStream_t s); \
-  int bucket_run_m##M_(const ngl_model& md, const BucketArgs& B, hipStream_t s);
+// Per-width and per-feature-type runners, defined in
+// ngl_trace_m<width>_<type>.hip (one translation unit each, so the heavy
+// kernel instantiations compile in parallel).
+#define NGL_TRACE_DECLARE_FT(M_, T_)                                                                      \
+  int trace_run_m##M_##_##T_(const ngl_model& md, const TraceArgs& A, hipStream_t s);                     \
+  int batch_run_m##M_##_##T_(const ngl_model& md, const BatchArgs& B, bool any_blend, hipStream_t s);     \
+  int bucket_run_m##M_##_##T_(const ngl_model& md, const BucketArgs& B, hipStream_t s);
+#define NGL_TRACE_DECLARE(M_) NGL_TRACE_DECLARE_FT(M_, f32) NGL_TRACE_DECLARE_FT(M_, f16) NGL_TRACE_DECLARE_FT(M_, bf16)
 NGL_TRACE_DECLARE(8)
 NGL_TRACE_DECLARE(16)
 NGL_TRACE_DECLARE(32)
 NGL_TRACE_DECLARE(64)
 #undef NGL_TRACE_DECLARE
+#undef NGL_TRACE_DECLARE_FT
 int trace_run_analytic(const ngl_model& md, const TraceArgs& A, hipStream_t s);
 
-#define NGL_TRACE_DEFINE(M_)                                                                        \
-  int trace_run_m##M_(const ngl_model& md, const TraceArgs& A, hipStream_t s) {                     \
-    return dispatch_ft<TraceOp, M_>(md, A, s);                                                      \
-  }                                                                                                 \
-  int batch_run_m##M_(const ngl_model& md, const BatchArgs& B, bool any_blend, hipStream_t s) {     \
-    return dispatch_ft<BatchOp, M_>(md, B, any_blend, s);                                           \
-  }                                                                                                 \
-  int bucket_run_m##M_(const ngl_model& md, const BucketArgs& B, hipStream_t s) {                   \
-    return dispatch_ft<BucketOp, M_>(md, B, s);                                                     \
+#define NGL_TRACE_DEFINE_FT(M_, T_, FT_)                                                                   \
+  int trace_run_m##M_##_##T_(const ngl_model& md, const TraceArgs& A, hipStream_t s) {                     \
+    return md.with_xyz ? TraceOp<M_, FT_, true>::run(md, A, s) : TraceOp<M_, FT_, false>::run(md, A, s);    \
+  }                                                                                                        \
+  int batch_run_m##M_##_##T_(const ngl_model& md, const BatchArgs& B, bool any_blend, hipStream_t s) {     \
+    return md.with_xyz ? BatchOp<M_, FT_, true>::run(md, B, any_blend, s)                                  \
+                       : BatchOp<M_, FT_, false>::run(md, B, any_blend, s);                                \
+  }                                                                                                        \
+  int bucket_run_m##M_##_##T_(const ngl_model& md, const BucketArgs& B, hipStream_t s) {                   \
+    return md.with_xyz ? BucketOp<M_, FT_, true>::run(md, B, s) : BucketOp<M_, FT_, false>::run(md, B, s);  \
   }
 
 }  // namespace ngl

@@ -1,0 +1,8 @@
+// Sphere-tracing kernel instantiations for feature width 16, FP16 features.
+#include "ngl_trace_impl.h"
+
+namespace ngl {
+
+NGL_TRACE_DEFINE_FT(16, f16, F16)
+
+}  // namespace ngl

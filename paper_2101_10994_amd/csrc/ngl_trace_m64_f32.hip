@@ -1,0 +1,8 @@
+// Sphere-tracing kernel instantiations for feature width 64, FP32 features.
+#include "ngl_trace_impl.h"
+
+namespace ngl {
+
+NGL_TRACE_DEFINE_FT(64, f32, F32)
+
+}  // namespace ngl

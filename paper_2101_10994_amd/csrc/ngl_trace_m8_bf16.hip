@@ -1,0 +1,8 @@
+// Sphere-tracing kernel instantiations for feature width 8, BF16 features.
+#include "ngl_trace_impl.h"
+
+namespace ngl {
+
+NGL_TRACE_DEFINE_FT(8, bf16, BF16)
+
+}  // namespace ngl

@@ -1,0 +1,8 @@
+// Sphere-tracing kernel instantiations for feature width 8, FP16 features.
+#include "ngl_trace_impl.h"
+
+namespace ngl {
+
+NGL_TRACE_DEFINE_FT(8, f16, F16)
+
+}  // namespace ngl

@@ -1,10 +1,10 @@
 // Primary rays and the breadth-first ray-octree intersection (Sec. 3.4,
 // Alg. 1; subroutines of App. C) on gfx950.
 //
-// Per depth, three launches over the current list of ray-voxel pairs:
+// Per depth, two launches over the current list of ray-voxel pairs:
 //   k_decide_count  Decide (FP32 slab tests) and a per-block sum
-//   k_scan_blocks   exclusive sum of the block sums (one block), list size
-//   k_decide_emit   block-level exclusive scan of the decisions, then
+//   k_decide_emit   each block sums the block sums before its own (its
+//                   offset of the ExclusiveSum), scans its decisions, then
 //                   Subdivide (children front to back) or Compactify
 // so the global ExclusiveSum is reduce-then-scan with the block partition
 // fixed by (list size, grid).  Lists live in caller workspace, sizes stay
@@ -69,7 +69,7 @@ struct Level {
   int depth;              // depth of the input list (root pass: 0)
   bool final_out;         // the produced list is at the target depth
   int64_t cap;
-  uint32_t* bsum;         // [kTravGrid] block sums, then exclusive offsets
+  uint32_t* bsum;         // [kTravGrid] block sums
   int64_t* n_out;         // device size of the produced list
   int64_t* counts;        // [0] final pair count, [1] largest list needed
   int32_t* ray_out;
@@ -111,14 +111,11 @@ __device__ inline uint32_t decide_children(const ngl_model& md, int d, const flo
   *cmask = m;
   *fc = md.first_child[d][vox];
   uint32_t hm = 0;
-  const int base[3] = {2 * cell_x(c), 2 * cell_y(c), 2 * cell_z(c)};
+  const ChildSlabs S(o, inv, c, d);
 #pragma unroll
   for (int ch = 0; ch < 8; ++ch) {
-    if (m >> ch & 1u) {
-      float lo[3], hi[3], ti, to;
-      box_of(pack_cell(base[0] + (ch & 1), base[1] + (ch >> 1 & 1), base[2] + (ch >> 2 & 1)), d + 1, lo, hi);
-      if (slab_f32(o, inv, lo, hi, ti, to)) hm |= 1u << ch;
-    }
+    float ti, to;
+    if ((m >> ch & 1u) && S.test(ch, ti, to)) hm |= 1u << ch;
   }
   return hm;
 }
@@ -171,55 +168,34 @@ __global__ __launch_bounds__(kBlock) void k_decide_count(ngl_model md, Level L) 
   }
 }
 
-// ExclusiveSum over the kTravGrid block sums (one block of 1024 lanes).
-__global__ __launch_bounds__(1024) void k_scan_blocks(Level L) {
-  constexpr int PER = kTravGrid / 1024;
-  __shared__ uint64_t part[1024 / 64];
-  uint64_t v[PER];
-  uint64_t local = 0;
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    v[k] = L.bsum[threadIdx.x * PER + k];
-    local += v[k];
-  }
-  uint64_t x = local;
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint64_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
-  }
-  if (lane == 63) part[threadIdx.x >> 6] = x;
-  __syncthreads();
-  uint64_t pre = 0, total = 0;
-#pragma unroll
-  for (int w = 0; w < 1024 / 64; ++w) {
-    const uint64_t s = part[w];
-    if (w < int(threadIdx.x >> 6)) pre += s;
-    total += s;
-  }
-  uint64_t run = pre + x - local;
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    // offsets can exceed 32 bits only beyond the capacity; clamp, the
-    // emit pass never writes past cap anyway
-    L.bsum[threadIdx.x * PER + k] = uint32_t(run < 0xffffffffull ? run : 0xffffffffull);
-    run += v[k];
-  }
-  if (threadIdx.x == 0) {
-    *L.n_out = int64_t(total);
-    if (int64_t(total) > L.counts[1]) L.counts[1] = int64_t(total);
-    if (L.final_out) L.counts[0] = int64_t(total);
-  }
-}
-
 template <bool ROOT>
 __global__ __launch_bounds__(kBlock) void k_decide_emit(ngl_model md, Level L) {
   const int64_t n = list_size(L, ROOT);
   int64_t begin, end;
   chunk_of(n, begin, end);
-  int64_t offset = L.bsum[blockIdx.x];
   __shared__ uint32_t part[kBlock / 64];
+  // this block's offset: the sum of the block sums before it; the last block
+  // also reports the list size
+  int64_t offset;
+  {
+    __shared__ uint64_t red[kBlock / 64];
+    uint64_t v = 0;
+    for (int b = threadIdx.x; b < int(blockIdx.x); b += kBlock) v += L.bsum[b];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint64_t o = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) o += red[w];
+    offset = int64_t(o);
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+      const int64_t total = offset + int64_t(L.bsum[blockIdx.x]);
+      *L.n_out = total;
+      if (total > L.counts[1]) L.counts[1] = total;
+      if (L.final_out) L.counts[0] = total;
+    }
+  }
   const int64_t cap = L.cap;
   for (int64_t base = begin; base < end; base += kBlock) {
     const int64_t t = base + threadIdx.x;
@@ -274,6 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_emit(ngl_model md, Level L) {
           const float centre = -1.0f + (float(ijk[a]) + 0.5f) * step;  // exact dyadic
           oct |= (o[a] > centre ? 1 : 0) << a;
         }
+        const ChildSlabs S(o, inv, c, d);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
           const int ch = q ^ oct;
@@ -282,10 +259,8 @@ __global__ __launch_bounds__(kBlock) void k_decide_emit(ngl_model md, Level L) {
               L.ray_out[k] = ray;
               L.vox_out[k] = fc + __popc(m & ((1u << ch) - 1u));
               if (L.final_out) {
-                float lo[3], hi[3], a0, a1;
-                box_of(pack_cell(2 * ijk[0] + (ch & 1), 2 * ijk[1] + (ch >> 1 & 1), 2 * ijk[2] + (ch >> 2 & 1)), d + 1,
-                       lo, hi);
-                slab_f32(o, inv, lo, hi, a0, a1);
+                float a0, a1;
+                S.test(ch, a0, a1);
                 L.tin_out[k] = a0;
                 L.tout_out[k] = a1;
               }
@@ -460,11 +435,9 @@ int ngl_trace_octree(const ngl_model* m, const float* o, const float* d, int64_t
     }
     if (root) {
       k_decide_count<true><<<kTravGrid, kBlock, 0, s>>>(*m, L);
-      k_scan_blocks<<<1, 1024, 0, s>>>(L);
       k_decide_emit<true><<<kTravGrid, kBlock, 0, s>>>(*m, L);
     } else {
       k_decide_count<false><<<kTravGrid, kBlock, 0, s>>>(*m, L);
-      k_scan_blocks<<<1, 1024, 0, s>>>(L);
       k_decide_emit<false><<<kTravGrid, kBlock, 0, s>>>(*m, L);
     }
   }

@@ -61,7 +61,7 @@ class ngl_view(C.Structure):
 
 class ngl_trace_params(C.Structure):
     _fields_ = [("max_steps", i32), ("delta", C.c_float), ("t_far", C.c_float), ("osc_check", i32),
-                ("analytic", i32), ("sphere", C.c_float * 4)]
+                ("analytic", i32), ("sphere", C.c_float * 4), ("image_width", i32)]
 
 
 class ngl_shape(C.Structure):
@@ -571,8 +571,10 @@ def trace_octree(model: Model, o: torch.Tensor, d: torch.Tensor, target_depth: i
                 count=n, max_list=int(counts[1]), buffers=buf)
 
 
-def trace_params(max_steps: int, delta: float, t_far: float = 5.0, osc_check: bool = False, analytic_sphere=None):
+def trace_params(max_steps: int, delta: float, t_far: float = 5.0, osc_check: bool = False, analytic_sphere=None,
+                 image_width: int = 0):
     p = ngl_trace_params()
+    p.image_width = int(image_width)
     p.max_steps = int(max_steps)
     p.delta = float(delta)
     p.t_far = float(t_far)
@@ -585,9 +587,12 @@ def trace_params(max_steps: int, delta: float, t_far: float = 5.0, osc_check: bo
 
 
 def sphere_trace(model: Model, o, d, lod: int, alpha: float, hits: dict, max_steps: int, delta: float,
-                 t_far: float = 5.0, osc_check: bool = False, analytic_sphere=None, out=None, phased: bool = True):
+                 t_far: float = 5.0, osc_check: bool = False, analytic_sphere=None, out=None, phased: bool = True,
+                 image_width: int = 0):
     """Sphere trace one view (ngl_sphere_trace).  `phased` sizes the
-    workspace for the phased form (same results, long rays compacted)."""
+    workspace for the phased form (same results, long rays compacted);
+    image_width > 0 serves the rays of that row-major image in 8x8 tiles
+    (same results)."""
     R = o.shape[1]
     dev = o.device
     if out is None:
@@ -595,7 +600,7 @@ def sphere_trace(model: Model, o, d, lod: int, alpha: float, hits: dict, max_ste
                    status=torch.empty(R, dtype=torch.uint8, device=dev),
                    steps=torch.empty(R, dtype=torch.int32, device=dev),
                    hit_vox=torch.empty(R, dtype=torch.int32, device=dev))
-    prm = trace_params(max_steps, delta, t_far, osc_check, analytic_sphere)
+    prm = trace_params(max_steps, delta, t_far, osc_check, analytic_sphere, image_width)
     if "ws" not in out:
         nb = C.c_size_t()
         if phased:

@@ -37,7 +37,7 @@ def test_struct_layout_matches_header():
     import ctypes as C
     # 6 int32 + 10+8 int64 + 4*10 + 5*8 + 1 + 2*8 + 8 pointers
     assert C.sizeof(ngl.ngl_model) == 6 * 4 + 18 * 8 + (4 * 10 + 5 * 8 + 1 + 2 * 8 + 8) * 8
-    assert C.sizeof(ngl.ngl_trace_params) == 4 * 5 + 16
+    assert C.sizeof(ngl.ngl_trace_params) == 4 * 6 + 16
 
 
 def test_plan_rejects_bad_input():

@@ -154,3 +154,25 @@ def test_phased_trace_is_bitwise_the_single_launch(name, f32_decoder):
     finally:
         for k, v in zip(keys, old):
             ngl.set_option(k, v)
+
+
+@pytest.mark.parametrize("name", ["m32-f32", "m32-spread-bf16", "m8"])
+def test_tile_order_is_bitwise_the_ray_order(name, f32_decoder):
+    """Serving an image's rays in 8x8 pixel tiles (image_width > 0) changes
+    only which rays share a wavefront: every output is the same bits, one
+    phase or phased, blended or not; widths that do not tile are rejected."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    gm = PHASE_CASES[name]().gpu_model()
+    L = gm.num_lods
+    o, d = ngl.camera_rays(W.PAPER.eye, (0, 0, 0), (0, 1, 0), 45.0, 384, 256)
+    for lod, alpha in ((L, 0.0), (L - 2, 0.4)):
+        hits = ngl.trace_octree(gm, o, d, (lod + 1 if alpha > 0 else lod) + 1)
+        for phased in (False, True):
+            ref = ngl.sphere_trace(gm, o, d, lod, alpha, hits, 100, 1e-4, phased=phased)
+            got = ngl.sphere_trace(gm, o, d, lod, alpha, hits, 100, 1e-4, phased=phased, image_width=384)
+            for key in ("t", "status", "steps", "hit_vox"):
+                assert torch.equal(got[key], ref[key]), (lod, alpha, phased, key)
+    for bad in (100, 388, -8, 96 * 5):
+        with pytest.raises(ngl.NGLError):
+            ngl.sphere_trace(gm, o, d, L, 0.0, hits, 100, 1e-4, image_width=bad)
