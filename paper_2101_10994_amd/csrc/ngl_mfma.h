@@ -170,10 +170,15 @@ __device__ inline void stage_slice8(float* stage, int row, int off, const float*
 }
 
 template <int M, bool XYZ>
-__device__ inline void stage_rest(float* stage, const float x[3]) {
+__device__ inline void stage_rest_row(float* stage, int r, const float x[3]) {
   using S = MfmaShape<M, XYZ>;
-  float4* row = reinterpret_cast<float4*>(stage + (threadIdx.x & 63) * S::ROW);
+  float4* row = reinterpret_cast<float4*>(stage + r * S::ROW);
   row[M / 4] = XYZ ? make_float4(x[0], x[1], x[2], 0.0f) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+template <int M, bool XYZ>
+__device__ inline void stage_rest(float* stage, const float x[3]) {
+  stage_rest_row<M, XYZ>(stage, threadIdx.x & 63, x);
 }
 
 // B fragments of one staged point for the BF16 form: for each feature
@@ -203,42 +208,53 @@ __device__ inline void bf16_b_frags(const float* row, int g, bf16x8 (&bh)[MfmaSh
   bp = __builtin_bit_cast(bf16x8, t);
 }
 
-// First layer on the matrix cores, second layer and reduction in FP32: the
-// decoder output for this lane's staged point (all 64 lanes must call it).
-// `live` (wave-uniform) marks the lanes whose output is used: a 16-lane
-// point tile without any is skipped (its lanes get b2).
+// First layer on the matrix cores, second layer and reduction in FP32 for
+// one tile of 16 staged points (rows[16][ROW]): lane l returns the output of
+// point l%16 less b2 (all 64 lanes must call it).
+template <int M, bool XYZ>
+__device__ inline float tile_decode(const uint4* frag, const float* w2s, const float* rows, int H) {
+  using S = MfmaShape<M, XYZ>;
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, j = lane & 15;
+  bf16x8 bh[S::KZ], bl[S::KZ], bp;
+  bf16_b_frags<M, XYZ>(rows + j * S::ROW, g, bh, bl, bp);
+  float part = 0.0f;
+  for (int h = 0; h < H / 16; ++h) {
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < S::KZ; ++s) {
+      const bf16x8 a = __builtin_bit_cast(bf16x8, frag[(h * S::KS + s) * 64 + lane]);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh[s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl[s], acc, 0, 0, 0);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, frag[(h * S::KS + S::KZ) * 64 + lane]),
+                                                  bp, acc, 0, 0, 0);
+    const float4 w = *reinterpret_cast<const float4*>(w2s + 16 * h + 4 * g);
+    part = fmaf(w.x, relu_bits(acc[0]), part);
+    part = fmaf(w.y, relu_bits(acc[1]), part);
+    part = fmaf(w.z, relu_bits(acc[2]), part);
+    part = fmaf(w.w, relu_bits(acc[3]), part);
+  }
+  // sum over the four row groups of the tile (lanes j, j+16, j+32, j+48)
+  part += __shfl_xor(part, 16, 64);
+  part += __shfl_xor(part, 32, 64);
+  return part;
+}
+
+// The decoder output for this lane's staged point of the wavefront's 64
+// rows (all 64 lanes must call it).  `live` (wave-uniform) marks the lanes
+// whose output is used: a 16-lane point tile without any is skipped (its
+// lanes get b2).
 template <int M, bool XYZ>
 __device__ inline float wave_decode(const uint4* frag, const float* w2s, float b2, const float* stage, int H,
                                     uint64_t live) {
   using S = MfmaShape<M, XYZ>;
-  const int lane = threadIdx.x & 63;
-  const int g = lane >> 4, j = lane & 15;
+  const int g = (threadIdx.x & 63) >> 4;
   float mine = 0.0f;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     if (((live >> (16 * t)) & 0xffffull) == 0) continue;
-    bf16x8 bh[S::KZ], bl[S::KZ], bp;
-    bf16_b_frags<M, XYZ>(stage + (16 * t + j) * S::ROW, g, bh, bl, bp);
-    float part = 0.0f;
-    for (int h = 0; h < H / 16; ++h) {
-      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int s = 0; s < S::KZ; ++s) {
-        const bf16x8 a = __builtin_bit_cast(bf16x8, frag[(h * S::KS + s) * 64 + lane]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh[s], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl[s], acc, 0, 0, 0);
-      }
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, frag[(h * S::KS + S::KZ) * 64 + lane]),
-                                                    bp, acc, 0, 0, 0);
-      const float4 w = *reinterpret_cast<const float4*>(w2s + 16 * h + 4 * g);
-      part = fmaf(w.x, relu_bits(acc[0]), part);
-      part = fmaf(w.y, relu_bits(acc[1]), part);
-      part = fmaf(w.z, relu_bits(acc[2]), part);
-      part = fmaf(w.w, relu_bits(acc[3]), part);
-    }
-    // sum over the four row groups of the tile (lanes j, j+16, j+32, j+48)
-    part += __shfl_xor(part, 16, 64);
-    part += __shfl_xor(part, 32, 64);
+    const float part = tile_decode<M, XYZ>(frag, w2s, stage + 16 * t * S::ROW, H);
     if (g == t) mine = part;
   }
   return b2 + mine;
@@ -312,9 +328,9 @@ __device__ inline void stage_slice8_32(float* stage, int row, int off, const flo
 }
 
 template <int M, bool XYZ>
-__device__ inline void stage_rest32(float* stage, const float x[3]) {
+__device__ inline void stage_rest32_row(float* stage, int r, const float x[3]) {
   using S = MfmaShape32<M, XYZ>;
-  float* row = stage + (threadIdx.x & 63) * S::ROW;
+  float* row = stage + r * S::ROW;
 #pragma unroll
   for (int k = 0; k < S::KP; ++k) {
     if (k < S::OFF) row[k] = x[k < 3 ? k : 0];
@@ -324,32 +340,45 @@ __device__ inline void stage_rest32(float* stage, const float x[3]) {
 }
 
 template <int M, bool XYZ>
-__device__ inline float wave_decode32(const float* frag, const float* w2s, float b2, const float* stage, int H,
-                                      uint64_t live) {
+__device__ inline void stage_rest32(float* stage, const float x[3]) {
+  stage_rest32_row<M, XYZ>(stage, threadIdx.x & 63, x);
+}
+
+template <int M, bool XYZ>
+__device__ inline float tile_decode32(const float* frag, const float* w2s, const float* rows, int H) {
   using S = MfmaShape32<M, XYZ>;
   const int lane = threadIdx.x & 63;
   const int g = lane >> 4, j = lane & 15;
+  float b[S::KS];
+#pragma unroll
+  for (int s = 0; s < S::KS; ++s) b[s] = rows[j * S::ROW + 4 * s + g];
+  float part = 0.0f;
+  for (int h = 0; h < H / 16; ++h) {
+    floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < S::KS; ++s)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(h * S::KS + s) * 64 + lane], b[s], acc, 0, 0, 0);
+    const float4 w = *reinterpret_cast<const float4*>(w2s + 16 * h + 4 * g);
+    part = fmaf(w.x, relu_bits(acc[0]), part);
+    part = fmaf(w.y, relu_bits(acc[1]), part);
+    part = fmaf(w.z, relu_bits(acc[2]), part);
+    part = fmaf(w.w, relu_bits(acc[3]), part);
+  }
+  part += __shfl_xor(part, 16, 64);
+  part += __shfl_xor(part, 32, 64);
+  return part;
+}
+
+template <int M, bool XYZ>
+__device__ inline float wave_decode32(const float* frag, const float* w2s, float b2, const float* stage, int H,
+                                      uint64_t live) {
+  using S = MfmaShape32<M, XYZ>;
+  const int g = (threadIdx.x & 63) >> 4;
   float mine = 0.0f;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     if (((live >> (16 * t)) & 0xffffull) == 0) continue;
-    float b[S::KS];
-#pragma unroll
-    for (int s = 0; s < S::KS; ++s) b[s] = stage[(16 * t + j) * S::ROW + 4 * s + g];
-    float part = 0.0f;
-    for (int h = 0; h < H / 16; ++h) {
-      floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int s = 0; s < S::KS; ++s)
-        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(frag[(h * S::KS + s) * 64 + lane], b[s], acc, 0, 0, 0);
-      const float4 w = *reinterpret_cast<const float4*>(w2s + 16 * h + 4 * g);
-      part = fmaf(w.x, relu_bits(acc[0]), part);
-      part = fmaf(w.y, relu_bits(acc[1]), part);
-      part = fmaf(w.z, relu_bits(acc[2]), part);
-      part = fmaf(w.w, relu_bits(acc[3]), part);
-    }
-    part += __shfl_xor(part, 16, 64);
-    part += __shfl_xor(part, 32, 64);
+    const float part = tile_decode32<M, XYZ>(frag, w2s, stage + 16 * t * S::ROW, H);
     if (g == t) mine = part;
   }
   return b2 + mine;
@@ -374,6 +403,25 @@ struct DecBF16 {
                                  uint64_t live = ~0ull) {
     return wave_decode<M, XYZ>(f, w2s, b2, st, H, live);
   }
+  // one 16-point tile (rows[16][ROW]): staging row r, and the decode
+  static constexpr int TILE_ELEMS = 16 * MfmaShape<M, XYZ>::ROW;
+  static constexpr int TILE_BYTES = 4 * TILE_ELEMS;
+  __device__ static void tile_rest(Stage* rows, int r, const float x[3]) { stage_rest_row<M, XYZ>(rows, r, x); }
+  template <int D>
+  __device__ static void tile_slice(Stage* rows, int r, int off, const float* v) {
+    float* w = rows + r * MfmaShape<M, XYZ>::ROW + off;
+    if constexpr (D % 4 == 0) {
+#pragma unroll
+      for (int q = 0; q < D / 4; ++q)
+        reinterpret_cast<float4*>(w)[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i) w[i] = v[i];
+    }
+  }
+  __device__ static float tile(const Frag* f, const float* w2s, const Stage* rows, int H) {
+    return tile_decode<M, XYZ>(f, w2s, rows, H);
+  }
 };
 
 template <int M, bool XYZ>
@@ -394,6 +442,18 @@ struct DecF32 {
                                  uint64_t live = ~0ull) {
     return wave_decode32<M, XYZ>(f, w2s, b2, st, H, live);
   }
+  static constexpr int TILE_ELEMS = 16 * MfmaShape32<M, XYZ>::ROW;
+  static constexpr int TILE_BYTES = 4 * TILE_ELEMS;
+  __device__ static void tile_rest(Stage* rows, int r, const float x[3]) { stage_rest32_row<M, XYZ>(rows, r, x); }
+  template <int D>
+  __device__ static void tile_slice(Stage* rows, int r, int off, const float* v) {
+    float* w = rows + r * MfmaShape32<M, XYZ>::ROW + MfmaShape32<M, XYZ>::OFF + off;
+#pragma unroll
+    for (int i = 0; i < D; ++i) w[i] = v[i];
+  }
+  __device__ static float tile(const Frag* f, const float* w2s, const Stage* rows, int H) {
+    return tile_decode32<M, XYZ>(f, w2s, rows, H);
+  }
 };
 
 // LDS carve-up shared by the kernels that decode with a policy:
@@ -405,12 +465,13 @@ struct DecLds {
   float* w2s0;
   float* w2s1;
   typename DEC::Stage* stage;  // this wavefront's staging rows
-  __device__ DecLds(char* smem, int H, bool blend) {
+  // stage_elems: staging elements per wavefront (64 rows, or one 16-row tile)
+  __device__ DecLds(char* smem, int H, bool blend, int stage_elems = DEC::STAGE_ELEMS) {
     frag0 = reinterpret_cast<typename DEC::Frag*>(smem);
     frag1 = frag0 + DEC::frag_elems(H);
     w2s0 = reinterpret_cast<float*>(frag1 + (blend ? DEC::frag_elems(H) : 0));
     w2s1 = w2s0 + H;
-    stage = reinterpret_cast<typename DEC::Stage*>(w2s1 + H) + (threadIdx.x >> 6) * DEC::STAGE_ELEMS;
+    stage = reinterpret_cast<typename DEC::Stage*>(w2s1 + H) + (threadIdx.x >> 6) * stage_elems;
   }
   __host__ __device__ static size_t fixed_bytes(int H, bool blend) {
     return size_t(DEC::frag_bytes(H)) * (blend ? 2 : 1) + 2 * sizeof(float) * size_t(H);
@@ -502,6 +563,47 @@ template <class DEC, int G>
 __device__ __forceinline__ void stage_slices(typename DEC::Stage* st, int r, int g, const float (*acc)[8]) {
 #pragma unroll
   for (int s = 0; s < G; ++s) DEC::stage_slice(st, (64 / G) * s + r, 8 * g, acc[s]);
+}
+
+// Tile-wise cooperative gather: the wavefront gathers and decodes its 64
+// points one 16-point tile at a time, the 4 lanes of group r = lane / 4
+// serving point r of the tile, lane g = lane % 4 holding the M/4 feature
+// elements [g M/4, g M/4 + M/4).  Only one tile's accumulators and one
+// tile's staging rows are live, which keeps register and LDS use low enough
+// for three to four wavefronts per SIMD.
+template <int M>
+struct TileShape {
+  static constexpr int G = 4;      // lanes per point
+  static constexpr int D = M / 4;  // feature elements per lane
+};
+
+// One level for this lane's group: voxel vq, cell (qx, qy, qz) at level l
+// and position xq of the group's point; the slice of each corner row is
+// accumulated in the order of interp_level.  A point without a voxel at the
+// level (vq < 0) loads voxel 0's rows and keeps its accumulator.
+template <int M, typename FT>
+__device__ __forceinline__ void tile_level(const ngl_model& md, int l, int vq, const float xq[3], int qx, int qy,
+                                           int qz, int g, float* acc) {
+  constexpr int D = TileShape<M>::D;
+  const int4* cp = reinterpret_cast<const int4*>(md.corners[l - 1] + size_t(vq >= 0 ? vq : 0) * 8);
+  const int4 c0 = cp[0], c1 = cp[1];
+  const int cs[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
+  float fv[8][D];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) load_slice<M, FT, D>(md.feat[l - 1], cs[j], g * D, fv[j]);
+  float u[3];
+  cell_local(l, qx, qy, qz, xq, u);
+  float t[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) t[i] = acc[i];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float w = corner_weight(u, j);
+#pragma unroll
+    for (int i = 0; i < D; ++i) t[i] = fmaf(w, fv[j][i], t[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) acc[i] = vq >= 0 ? t[i] : acc[i];
 }
 
 }  // namespace ngl

@@ -161,49 +161,63 @@ __global__ __launch_bounds__(64 * NW) void k_query_mfma(ngl_model md, const floa
 }
 
 // Cooperative gather: lanes locate their own points as above, then the
-// wavefront gathers the 64 points' features in G rounds of 64/G points, a
-// group of G = M/8 lanes per point with lane g loading the 8 elements
-// [8g, 8g + 8) of each corner row.  A row (32 to 256 bytes) is then read
-// by a few lanes together, where one lane per point reads whole rows alone
-// and the vector cache serves one line per lane and load.  Every element
-// is accumulated in the same order as interp_level, so the results are
-// those of k_query_mfma bit for bit: the slices are packed straight into the
-// staging rows, where each lane adds the rest of its own row.
-// One evaluation of the wavefront's located points with the cooperative
-// gather and the matrix-core decoder(s): features of levels 1..lod, the
-// decoder lod, and with `blend` the Eq. 3 mix (weight a) with decoder lod+1
-// on z + the level lod+1 voxel vn.  Every lane must call it.
+// wavefront gathers and decodes its 64 points one 16-point tile at a time
+// (TileShape): the 4 lanes of group r serve point r of the tile, lane g
+// loading the elements [g M/4, g M/4 + M/4) of every corner row, so a row
+// (32 to 256 bytes) is read by 4 lanes together where one lane per point
+// reads whole rows alone.  Every element is accumulated in the same order
+// as interp_level and the staged decoder rows hold the same values, so the
+// results are those of k_query_mfma bit for bit.  Only one tile's
+// accumulators and staging rows are live at a time.
+// One evaluation of the wavefront's located points: features of levels
+// 1..lod, the decoder lod, and with `blend` the Eq. 3 mix (weight a, this
+// lane's) with decoder lod+1 on z + the level lod+1 voxel vn.  rows: this
+// wavefront's 16 staging rows.  Every lane must call it.
 template <int M, typename FT, class DEC>
 __device__ __forceinline__ float coop_eval(const ngl_model& md, const DecLds<DEC>& S, const float x[3],
                                            const int* vox, int cx, int cy, int cz, int vn, bool act, int lod, int Lp,
                                            bool blend, float a, float b2a, float b2b) {
-  const uint64_t live = __ballot(act);  // rounds without an active point are skipped
-  constexpr int G = CoopShape<M>::G, D = CoopShape<M>::D;
-  const int lane = threadIdx.x & 63, r = lane / G, g = lane % G;
+  const uint64_t live = __ballot(act);  // tiles without an active point are skipped
+  constexpr int D = TileShape<M>::D;
+  const int lane = threadIdx.x & 63, r = lane >> 2, g = lane & 3;
   const int H = md.hidden;
-  float acc[G][D];
+  typename DEC::Stage* rows = S.stage;
+  float mine = 0.0f;
 #pragma unroll
-  for (int s = 0; s < G; ++s)
+  for (int t = 0; t < 4; ++t) {
+    if (((live >> (16 * t)) & 0xffffull) == 0) continue;
+    const int q = 16 * t + r;  // the group's point
+    float xq[3];
 #pragma unroll
-    for (int i = 0; i < D; ++i) acc[s][i] = 0.0f;
+    for (int k = 0; k < 3; ++k) xq[k] = __shfl(x[k], q, 64);
+    const int qx = __shfl(cx, q, 64), qy = __shfl(cy, q, 64), qz = __shfl(cz, q, 64);
+    float acc[D];
 #pragma unroll
-  for (int l = 1; l <= NGL_MAX_LODS; ++l)
-    if (l <= lod && md.nvox[l + 1] > 0)
-      coop_level<M, FT, G, false>(md, l, Lp - l, act ? vox[l - 1] : -1, x, cx, cy, cz, r, g, acc, live);
-  stage_slices<DEC, G>(S.stage, r, g, acc);
-  DEC::stage_rest(S.stage, x);
-  wave_lds_sync();
-  float out = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H, live);
-  if (blend) {
-    // z_{L+1} = z_L + psi_{L+1}
+    for (int i = 0; i < D; ++i) acc[i] = 0.0f;
+#pragma unroll
+    for (int l = 1; l <= NGL_MAX_LODS; ++l)
+      if (l <= lod && md.nvox[l + 1] > 0) {
+        const int sh = Lp - l;
+        tile_level<M, FT>(md, l, __shfl(act ? vox[l - 1] : -1, q, 64), xq, qx >> sh, qy >> sh, qz >> sh, g, acc);
+      }
+    DEC::template tile_slice<D>(rows, r, g * D, acc);
+    if (g == 0) DEC::tile_rest(rows, r, xq);
     wave_lds_sync();
-    if (md.nvox[lod + 2] > 0) coop_level<M, FT, G, false>(md, lod + 1, 0, act ? vn : -1, x, cx, cy, cz, r, g, acc, live);
-    stage_slices<DEC, G>(S.stage, r, g, acc);
+    const float p0 = DEC::tile(S.frag0, S.w2s0, rows, H);
+    float out = b2a + p0;
+    if (blend) {
+      // z_{L+1} = z_L + psi_{L+1}
+      wave_lds_sync();
+      if (md.nvox[lod + 2] > 0) tile_level<M, FT>(md, lod + 1, __shfl(act ? vn : -1, q, 64), xq, qx, qy, qz, g, acc);
+      DEC::template tile_slice<D>(rows, r, g * D, acc);
+      wave_lds_sync();
+      const float p1 = DEC::tile(S.frag1, S.w2s1, rows, H);
+      out = (1.0f - a) * out + a * (b2b + p1);
+    }
     wave_lds_sync();
-    out = (1.0f - a) * out + a * DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H, live);
+    if ((lane >> 4) == t) mine = out;  // lane 16 t + j owns point 16 t + j
   }
-  wave_lds_sync();
-  return out;
+  return mine;
 }
 
 template <int M, typename FT, bool XYZ, int NW, class DEC>
@@ -214,7 +228,7 @@ __global__ __launch_bounds__(64 * NW) void k_query_coop(ngl_model md, const floa
   extern __shared__ __align__(16) char smem[];
   const int H = md.hidden;
   const bool blend = alpha_pp != nullptr || alpha > 0.0f;
-  DecLds<DEC> S(smem, H, blend);
+  DecLds<DEC> S(smem, H, blend, DEC::TILE_ELEMS);
   DEC::load(md, lod, S.frag0, S.w2s0);
   if (blend) DEC::load(md, lod + 1, S.frag1, S.w2s1);
   __syncthreads();
@@ -276,7 +290,7 @@ static int launch_query_coop(const ngl_model& md, const float* x, int64_t P, int
                              float* sdf, uint8_t* valid, int32_t* vox, hipStream_t s) {
   const bool blend = app != nullptr || alpha > 0.0f;
   const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, blend);
-  constexpr size_t R = DEC::STAGE_BYTES;
+  constexpr size_t R = DEC::TILE_BYTES;
   if (fixed + 4 * R <= 65536)
     return launch_query_coop_nw<M, FT, XYZ, 4, DEC>(md, x, P, lod, alpha, app, sdf, valid, vox, s, fixed + 4 * R);
   if (fixed + 2 * R <= 65536)

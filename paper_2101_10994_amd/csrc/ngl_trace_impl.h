@@ -120,6 +120,18 @@ __device__ inline int queue_ray(int64_t q, int W) {
 #define NGL_TRACE_COOP 1
 #endif
 
+// serve_queue gathers features cooperatively, one 16-ray tile at a time,
+// for FP32 features on the matrix cores (with 16-bit features one lane per
+// ray measured faster); its staging rows per wavefront follow.
+template <typename FT, bool ANALYTIC, bool MFMA>
+constexpr bool trace_coop() {
+  return MFMA && !ANALYTIC && NGL_TRACE_COOP && std::is_same<FT, F32>::value;
+}
+template <typename FT, bool ANALYTIC, bool MFMA, class DEC>
+constexpr int trace_stage_bytes() {
+  return trace_coop<FT, ANALYTIC, MFMA>() ? DEC::TILE_BYTES : DEC::STAGE_BYTES;
+}
+
 // One wavefront serves a view's ray queue.  Each lane keeps one ray; a lane
 // whose ray terminates takes the next ray from the queue, so every step is
 // evaluated on a compacted set of active rays.  Every ray ends after at most
@@ -147,7 +159,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
   const int H = md.hidden;
   // matrix-core tracers over FP32 features gather rows cooperatively (see
   // coop_level); with 16-bit features one lane per ray measured faster
-  constexpr bool COOP = MFMA && !ANALYTIC && NGL_TRACE_COOP && std::is_same<FT, F32>::value;
+  constexpr bool COOP = trace_coop<FT, ANALYTIC, MFMA>();
   int ray = -1, p = 0, e = 0, k = 0, cp = -1;
   // the current pair's t_in, t_out and voxel, loaded together when p moves
   int pc = -1, v_c = -1;
@@ -292,36 +304,49 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
       if constexpr (!ANALYTIC) {
         if constexpr (MFMA) {
           if constexpr (COOP) {
-            // cooperative gather of the evaluating lanes' features (rounds
-            // without one are skipped), packed straight into the staging rows
-            constexpr int G = CoopShape<M>::G, D = CoopShape<M>::D;
-            const int r = lane / G, g = lane % G;
+            // cooperative gather of the evaluating lanes' features, one
+            // 16-ray tile at a time (tiles without one are skipped), the 4
+            // lanes of group r serving ray 16 t + r
+            constexpr int D = TileShape<M>::D;
+            const int r = lane >> 2, g = lane & 3;
             const uint64_t okm = __ballot(ok);
-            float acc[G][D];
+            const bool mix = ok && al > 0.0f;  // Eq. 3 blend with the level lod+1 voxel
+            const uint64_t mixing = blend ? __ballot(mix) : 0ull;
+            typename DEC::Stage* rows = S.stage;
 #pragma unroll
-            for (int s = 0; s < G; ++s)
+            for (int tt = 0; tt < 4; ++tt) {
+              if (((okm >> (16 * tt)) & 0xffffull) == 0) continue;
+              const int q = 16 * tt + r;
+              float xq[3];
 #pragma unroll
-              for (int i = 0; i < D; ++i) acc[s][i] = 0.0f;
+              for (int a = 0; a < 3; ++a) xq[a] = __shfl(x[a], q, 64);
+              float acc[D];
 #pragma unroll
-            for (int l = 1; l <= NGL_MAX_LODS; ++l)
-              if (l <= lod)
-                coop_level<M, FT, G, true>(md, l, 0, ok ? vox[l - 1] : -1, x, int(cell[l - 1]), 0, 0, r, g, acc, okm);
-            stage_slices<DEC, G>(S.stage, r, g, acc);
-            DEC::stage_rest(S.stage, x);
-            wave_lds_sync();
-            dist = DEC::decode(S.frag0, S.w2s0, b2a, S.stage, H, okm);
-            const bool mix = ok && al > 0.0f;
-            const uint64_t mixing = __ballot(mix);
-            if (blend && mixing) {
+              for (int i = 0; i < D; ++i) acc[i] = 0.0f;
+#pragma unroll
+              for (int l = 1; l <= NGL_MAX_LODS; ++l)
+                if (l <= lod) {
+                  const uint32_t cq = uint32_t(__shfl(int(cell[l - 1]), q, 64));
+                  tile_level<M, FT>(md, l, __shfl(ok ? vox[l - 1] : -1, q, 64), xq, cell_x(cq), cell_y(cq), cell_z(cq),
+                                    g, acc);
+                }
+              DEC::template tile_slice<D>(rows, r, g * D, acc);
+              if (g == 0) DEC::tile_rest(rows, r, xq);
               wave_lds_sync();
-              coop_level<M, FT, G, true>(md, lod + 1, 0, mix ? vox[lod] : -1, x, int(cell[lod]), 0, 0, r, g, acc,
-                                         mixing);
-              stage_slices<DEC, G>(S.stage, r, g, acc);
+              float d = b2a + DEC::tile(S.frag0, S.w2s0, rows, H);
+              if (blend && ((mixing >> (16 * tt)) & 0xffffull)) {
+                wave_lds_sync();
+                const uint32_t cq = uint32_t(__shfl(int(cell[lod]), q, 64));
+                tile_level<M, FT>(md, lod + 1, __shfl(mix ? vox[lod] : -1, q, 64), xq, cell_x(cq), cell_y(cq),
+                                  cell_z(cq), g, acc);
+                DEC::template tile_slice<D>(rows, r, g * D, acc);
+                wave_lds_sync();
+                const float d1 = b2b + DEC::tile(S.frag1, S.w2s1, rows, H);
+                if (mix) d = (1.0f - al) * d + al * d1;
+              }
               wave_lds_sync();
-              const float d1 = DEC::decode(S.frag1, S.w2s1, b2b, S.stage, H, mixing);
-              if (mix) dist = (1.0f - al) * dist + al * d1;
+              if ((lane >> 4) == tt) dist = d;  // lane 16 tt + j owns ray slot 16 tt + j
             }
-            wave_lds_sync();
           } else {
           DEC::stage(S.stage, x, z);
           wave_lds_sync();
@@ -380,12 +405,20 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
 
 #undef NGL_FINISH
 
+// Register budget of the one-lane-per-ray tracers: at most 168 VGPRs, so
+// three wavefronts fit on a SIMD (the dependent feature loads need them to
+// overlap).
+#ifndef NGL_TRACE_WAVES_PER_EU
+#define NGL_TRACE_WAVES_PER_EU 3
+#endif
+
 template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, int NW, class DEC>
-__global__ __launch_bounds__(64 * NW) void k_sphere_trace(ngl_model md, TraceArgs A) {
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NGL_TRACE_WAVES_PER_EU)))
+void k_sphere_trace(ngl_model md, TraceArgs A) {
   extern __shared__ __align__(16) char smem[];
   const bool blend = trace_blend(A);
   const int H = md.hidden;
-  DecLds<DEC> S(smem, H, blend && MFMA);
+  DecLds<DEC> S(smem, H, blend && MFMA, trace_stage_bytes<FT, ANALYTIC, MFMA, DEC>() / 4);
   float b2a = 0.0f, b2b = 0.0f;
   if constexpr (MFMA) {
     DEC::load(md, A.lod, S.frag0, S.w2s0);
@@ -773,7 +806,7 @@ __global__ __launch_bounds__(64 * NW) void k_trace_batch(BatchArgs B) {
     __syncthreads();
     const TraceArgs A = batch_view_args(B, v);
     const bool blend = A.alpha > 0.0f;
-    DecLds<DEC> S(smem, H, blend);
+    DecLds<DEC> S(smem, H, blend, trace_stage_bytes<FT, false, true, DEC>() / 4);
     DEC::load(smd, A.lod, S.frag0, S.w2s0);
     if (blend) DEC::load(smd, A.lod + 1, S.frag1, S.w2s1);
     __syncthreads();
@@ -806,7 +839,7 @@ __global__ __launch_bounds__(64 * NW) void k_trace_batch_wide(BatchArgs B) {
     __syncthreads();
     const TraceArgs A = batch_view_args(B, v);
     const bool blend = A.alpha > 0.0f;
-    DecLds<DEC> S(smem, H, blend);
+    DecLds<DEC> S(smem, H, blend, trace_stage_bytes<FT, false, true, DEC>() / 4);
     S.stage = reinterpret_cast<typename DEC::Stage*>(smem + DecLds<DEC>::fixed_bytes(H, true)) +
               (threadIdx.x >> 6) * DEC::STAGE_ELEMS;
     float* zbuf = reinterpret_cast<float*>(smem + DecLds<DEC>::fixed_bytes(H, true) + NW * DEC::STAGE_BYTES) +
@@ -859,7 +892,7 @@ __global__ __launch_bounds__(64 * NW) void k_trace_buckets(ngl_model md, BucketA
       A.parked_n = B.base.parked_n + (lod - 1);
     }
     const bool blend = trace_blend(A);
-    DecLds<DEC> S(smem, H, blend && MFMA);
+    DecLds<DEC> S(smem, H, blend && MFMA, trace_stage_bytes<FT, false, MFMA, DEC>() / 4);
     float b2a = 0.0f, b2b = 0.0f;
     if constexpr (MFMA) {
       DEC::load(md, lod, S.frag0, S.w2s0);
@@ -955,11 +988,12 @@ static int launch_trace_mfma(const ngl_model& md, const TraceArgs& A, hipStream_
   if (A.wide) return launch_trace_wide<M, FT, XYZ, DEC>(md, A, s);
   const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, trace_blend(A));
   const int want = option(NGL_OPT_TRACE_WAVES);
-  if ((want == 0 || want >= 4) && fixed + 4 * DEC::STAGE_BYTES <= 65536)
-    return launch_trace_nw<M, FT, XYZ, false, true, 4, DEC>(md, A, s, fixed + 4 * DEC::STAGE_BYTES);
-  if ((want == 0 || want >= 2) && fixed + 2 * DEC::STAGE_BYTES <= 65536)
-    return launch_trace_nw<M, FT, XYZ, false, true, 2, DEC>(md, A, s, fixed + 2 * DEC::STAGE_BYTES);
-  return launch_trace_nw<M, FT, XYZ, false, true, 1, DEC>(md, A, s, fixed + DEC::STAGE_BYTES);
+  constexpr size_t SB = trace_stage_bytes<FT, false, true, DEC>();
+  if ((want == 0 || want >= 4) && fixed + 4 * SB <= 65536)
+    return launch_trace_nw<M, FT, XYZ, false, true, 4, DEC>(md, A, s, fixed + 4 * SB);
+  if ((want == 0 || want >= 2) && fixed + 2 * SB <= 65536)
+    return launch_trace_nw<M, FT, XYZ, false, true, 2, DEC>(md, A, s, fixed + 2 * SB);
+  return launch_trace_nw<M, FT, XYZ, false, true, 1, DEC>(md, A, s, fixed + SB);
 }
 
 template <int M, typename FT, bool XYZ, bool ANALYTIC>
@@ -983,11 +1017,12 @@ template <int M, typename FT, bool XYZ, class DEC>
 static int launch_batch(const BatchArgs& B, bool any_blend, int H, hipStream_t s) {
   const size_t fixed = DecLds<DEC>::fixed_bytes(H, any_blend);
   const int want = option(NGL_OPT_TRACE_WAVES);
-  if ((want == 0 || want >= 4) && fixed + 4 * DEC::STAGE_BYTES <= 65536)
-    return launch_batch_nw<M, FT, XYZ, 4, DEC>(B, s, fixed + 4 * DEC::STAGE_BYTES);
-  if ((want == 0 || want >= 2) && fixed + 2 * DEC::STAGE_BYTES <= 65536)
-    return launch_batch_nw<M, FT, XYZ, 2, DEC>(B, s, fixed + 2 * DEC::STAGE_BYTES);
-  return launch_batch_nw<M, FT, XYZ, 1, DEC>(B, s, fixed + DEC::STAGE_BYTES);
+  constexpr size_t SB = trace_stage_bytes<FT, false, true, DEC>();
+  if ((want == 0 || want >= 4) && fixed + 4 * SB <= 65536)
+    return launch_batch_nw<M, FT, XYZ, 4, DEC>(B, s, fixed + 4 * SB);
+  if ((want == 0 || want >= 2) && fixed + 2 * SB <= 65536)
+    return launch_batch_nw<M, FT, XYZ, 2, DEC>(B, s, fixed + 2 * SB);
+  return launch_batch_nw<M, FT, XYZ, 1, DEC>(B, s, fixed + SB);
 }
 
 template <int M, typename FT, bool XYZ, int NW, class DEC>
@@ -1051,11 +1086,10 @@ template <int M, typename FT, bool XYZ, bool MFMA, class DEC>
 static int launch_buckets(const ngl_model& md, const BucketArgs& B, hipStream_t s) {
   if constexpr (!MFMA) return launch_buckets_nw<M, FT, XYZ, false, 4, DEC>(md, B, s, 0);
   const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, true);
-  if (fixed + 4 * DEC::STAGE_BYTES <= 65536)
-    return launch_buckets_nw<M, FT, XYZ, MFMA, 4, DEC>(md, B, s, fixed + 4 * DEC::STAGE_BYTES);
-  if (fixed + 2 * DEC::STAGE_BYTES <= 65536)
-    return launch_buckets_nw<M, FT, XYZ, MFMA, 2, DEC>(md, B, s, fixed + 2 * DEC::STAGE_BYTES);
-  return launch_buckets_nw<M, FT, XYZ, MFMA, 1, DEC>(md, B, s, fixed + DEC::STAGE_BYTES);
+  constexpr size_t SB = trace_stage_bytes<FT, false, MFMA, DEC>();
+  if (fixed + 4 * SB <= 65536) return launch_buckets_nw<M, FT, XYZ, MFMA, 4, DEC>(md, B, s, fixed + 4 * SB);
+  if (fixed + 2 * SB <= 65536) return launch_buckets_nw<M, FT, XYZ, MFMA, 2, DEC>(md, B, s, fixed + 2 * SB);
+  return launch_buckets_nw<M, FT, XYZ, MFMA, 1, DEC>(md, B, s, fixed + SB);
 }
 
 template <int M, typename FT, bool XYZ, int NW, class DEC>
