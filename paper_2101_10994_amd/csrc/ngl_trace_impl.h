@@ -123,9 +123,12 @@ __device__ inline int queue_ray(int64_t q, int W) {
 // serve_queue gathers features cooperatively, one 16-ray tile at a time,
 // for FP32 features on the matrix cores (with 16-bit features one lane per
 // ray measured faster); its staging rows per wavefront follow.
+#ifndef NGL_TRACE_COOP_HALF
+#define NGL_TRACE_COOP_HALF 1
+#endif
 template <typename FT, bool ANALYTIC, bool MFMA>
 constexpr bool trace_coop() {
-  return MFMA && !ANALYTIC && NGL_TRACE_COOP && std::is_same<FT, F32>::value;
+  return MFMA && !ANALYTIC && NGL_TRACE_COOP && (NGL_TRACE_COOP_HALF || std::is_same<FT, F32>::value);
 }
 template <typename FT, bool ANALYTIC, bool MFMA, class DEC>
 constexpr int trace_stage_bytes() {
