@@ -442,6 +442,113 @@ __global__ __launch_bounds__(64 * NW) void k_normals(ngl_model md, NormalArgs A)
   }
 }
 
+// Matrix-core form: each block walks a contiguous range of the points and
+// queues the active ones (rays that hit, or every point) in LDS, so its
+// wavefronts only evaluate active points (a frame's misses get their zero
+// normal on the way).  Each of the six probes is one cooperative,
+// tile-wise evaluation (coop_eval), whose results are the bits of the
+// one-lane-per-point form.
+template <int M, typename FT, bool XYZ, int NW, class DEC>
+__global__ __launch_bounds__(64 * NW) void k_normals_coop(ngl_model md, NormalArgs A) {
+  constexpr int NB = 64 * NW;  // points evaluated per block pass
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int32_t queue[2 * NB];
+  __shared__ int qn;
+  const int H = md.hidden;
+  const int lod = A.lod;
+  const bool blend = A.alpha > 0.0f;
+  const int Lp = blend ? lod + 1 : lod;
+  DecLds<DEC> S(smem, H, blend, DEC::TILE_ELEMS);
+  DEC::load(md, lod, S.frag0, S.w2s0);
+  if (blend) DEC::load(md, lod + 1, S.frag1, S.w2s1);
+  if (threadIdx.x == 0) qn = 0;
+  __syncthreads();
+  const float b2a = md.b2[lod - 1];
+  const float b2b = blend ? md.b2[lod] : 0.0f;
+  const int64_t P = A.P;
+  int64_t chunk = (P + gridDim.x - 1) / gridDim.x;
+  chunk = (chunk + NB - 1) / NB * NB;
+  const int64_t begin = int64_t(blockIdx.x) * chunk;
+  const int64_t end = begin + chunk < P ? begin + chunk : P;
+  int64_t pos = begin;
+  for (;;) {
+    // 1. queue active points until a full pass is available or the range ends
+    while (qn < NB && pos < end) {
+      const int64_t p = pos + threadIdx.x;
+      bool act = false;
+      if (p < end) {
+        act = A.status ? A.status[p] == NGL_RAY_HIT : true;
+        if (!act) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) A.normals[a * P + p] = 0.0f;
+        }
+      }
+      const uint64_t m = __ballot(act);
+      int base = 0;
+      if ((threadIdx.x & 63) == 0 && m) base = atomicAdd(&qn, __popcll(m));
+      base = __shfl(base, 0, 64);
+      if (act) queue[base + __popcll(m & ((1ull << (threadIdx.x & 63)) - 1ull))] = int32_t(p);
+      pos += NB;
+      __syncthreads();
+    }
+    const int n = qn;
+    if (n == 0) break;
+    const int take = n < NB ? n : NB;
+    // 2. evaluate the six probes of up to NB queued points
+    const bool act = int(threadIdx.x) < take;
+    const int64_t p = act ? queue[threadIdx.x] : 0;
+    float x0[3] = {0.0f, 0.0f, 0.0f};
+    if (act) {
+      if (A.status) {
+        const float t = A.t_hit[p];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x0[a] = fmaf(t, A.d[a * P + p], A.o[a * P + p]);
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) x0[a] = A.x[a * P + p];
+      }
+    }
+    float g[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int e = 0; e < 6; ++e) {
+      const int a = e >> 1;
+      const float sgn = (e & 1) ? -1.0f : 1.0f;
+      float x[3] = {x0[0], x0[1], x0[2]};
+      x[a] = x0[a] + sgn * A.h;
+      int vox[NGL_MAX_LODS];
+      int cx, cy, cz, vlast, vn;
+      locate<NGL_MAX_LODS>(md, x, Lp, vox, &cx, &cy, &cz, &vlast, lod + 1, &vn);
+      if (!act) {
+#pragma unroll
+        for (int l = 0; l < NGL_MAX_LODS; ++l) vox[l] = -1;
+        vn = -1;
+      }
+      const float f = coop_eval<M, FT, DEC>(md, S, x, vox, cx, cy, cz, vn, act, lod, Lp, blend, A.alpha, b2a, b2b);
+      g[a] += sgn * f;
+    }
+    if (act) {
+      float nrm[3] = {0.0f, 0.0f, 0.0f};
+      const float inv2h = 0.5f / A.h;
+      const float gx = g[0] * inv2h, gy = g[1] * inv2h, gz = g[2] * inv2h;
+      const float len = sqrtf(gx * gx + gy * gy + gz * gz);
+      if (len > 0.0f) {
+        nrm[0] = gx / len;
+        nrm[1] = gy / len;
+        nrm[2] = gz / len;
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) A.normals[a * P + p] = nrm[a];
+    }
+    // 3. drop the evaluated points from the queue
+    __syncthreads();
+    const int rest = n - take;
+    for (int i = threadIdx.x; i < rest; i += NB) queue[i] = queue[take + i];
+    __syncthreads();
+    if (threadIdx.x == 0) qn = rest;
+    __syncthreads();
+  }
+}
+
 template <int M, typename FT, bool XYZ, class DEC, bool MFMA, int NW>
 static int launch_normals_nw(const ngl_model& md, const NormalArgs& A, hipStream_t s, size_t lds) {
   // one round of resident blocks looping over the points (each stages the
@@ -458,11 +565,19 @@ static int launch_normals_nw(const ngl_model& md, const NormalArgs& A, hipStream
 template <int M, typename FT, bool XYZ, class DEC, bool MFMA>
 static int launch_normals(const ngl_model& md, const NormalArgs& A, hipStream_t s) {
   const bool blend = A.alpha > 0.0f;
-  if constexpr (!MFMA) return launch_normals_nw<M, FT, XYZ, DEC, false, 2>(md, A, s, 0);
-  const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, blend);
-  if (fixed + 4 * DEC::STAGE_BYTES <= 65536)
-    return launch_normals_nw<M, FT, XYZ, DEC, MFMA, 4>(md, A, s, fixed + 4 * DEC::STAGE_BYTES);
-  return launch_normals_nw<M, FT, XYZ, DEC, MFMA, 2>(md, A, s, fixed + 2 * DEC::STAGE_BYTES);
+  if constexpr (!MFMA) {
+    return launch_normals_nw<M, FT, XYZ, DEC, false, 2>(md, A, s, 0);
+  } else {
+    constexpr int NW = 4;
+    const size_t lds = DecLds<DEC>::fixed_bytes(md.hidden, blend) + NW * size_t(DEC::TILE_BYTES);
+    const void* kern = reinterpret_cast<const void*>(&k_normals_coop<M, FT, XYZ, NW, DEC>);
+    int64_t grid = (A.P + 64 * NW - 1) / (64 * NW);
+    const int64_t cap = resident_grid(kern, 64 * NW, lds, 0);
+    if (grid > cap) grid = cap;
+    k_normals_coop<M, FT, XYZ, NW, DEC><<<unsigned(grid), 64 * NW, lds, s>>>(md, A);
+    NGL_LAUNCHED();
+    return NGL_OK;
+  }
 }
 
 template <int M, typename FT, bool XYZ>
