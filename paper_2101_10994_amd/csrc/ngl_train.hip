@@ -24,7 +24,7 @@
 namespace ngl {
 
 constexpr int kSortGrid = 512;  // most blocks of the radix-sort passes
-constexpr int kDecGrid = 128;   // most blocks per LOD of the decoder-gradient pass
+constexpr int kDecGrid = 204;   // most blocks per LOD of the decoder-gradient pass (5 LODs fill 256 CUs x 4)
 
 // Grids sized to the batch (small batches of the fitting loop would
 // otherwise pay for the full grids): about 1024 keys per sort block and
@@ -252,7 +252,8 @@ template <int M, bool XYZ>
 __global__ __launch_bounds__(kBlock) void k_dec_grad(ngl_model md, DecArgs A) {
   constexpr int OFF = XYZ ? 3 : 0;
   constexpr int DIN = M + OFF;
-  __shared__ float in_s[kTile][DIN];
+  constexpr int DP = (DIN + 3) / 4 * 4;  // staged row, padded to whole 16-byte vectors
+  __shared__ __align__(16) float in_s[kTile][DP];
   __shared__ float g_s[kTile];
   const int L = blockIdx.y + 1;
   const int H = md.hidden;
@@ -261,25 +262,25 @@ __global__ __launch_bounds__(kBlock) void k_dec_grad(ngl_model md, DecArgs A) {
   const int ph = threadIdx.x / H;
   const int64_t P = A.P;
   cptr<float> W1 = as_const<float>(md.W1[L - 1]);
-  float w[DIN];
+  float w[DP];
 #pragma unroll
-  for (int i = 0; i < DIN; ++i) w[i] = W1[k * DIN + i];
+  for (int i = 0; i < DP; ++i) w[i] = i < DIN ? W1[k * DIN + i] : 0.0f;
   const float bk = as_const<float>(md.b1[L - 1])[k];
   const float w2k = as_const<float>(md.w2[L - 1])[k];
-  float acc[DIN];
+  float acc[DP];
 #pragma unroll
-  for (int i = 0; i < DIN; ++i) acc[i] = 0.0f;
+  for (int i = 0; i < DP; ++i) acc[i] = 0.0f;
   float ab1 = 0.0f, aw2 = 0.0f, ab2 = 0.0f;
   int64_t chunk = (P + gridDim.x - 1) / gridDim.x;
   chunk = (chunk + kTile - 1) / kTile * kTile;
   const int64_t begin = int64_t(blockIdx.x) * chunk;
   const int64_t end = begin + chunk < P ? begin + chunk : P;
   for (int64_t base = begin; base < end; base += kTile) {
-    for (int e = threadIdx.x; e < kTile * DIN; e += kBlock) {
-      const int pp = e / DIN, i = e % DIN;
+    for (int e = threadIdx.x; e < kTile * DP; e += kBlock) {
+      const int pp = e / DP, i = e % DP;
       const int64_t p = base + pp;
       float v = 0.0f;
-      if (p < end) {
+      if (p < end && i < DIN) {
         if (i < OFF) v = A.xs[int64_t(i) * P + A.sidx[p]];
         else v = A.zrows[(int64_t(L - 1) * P + p) * M + (i - OFF)];
       }
@@ -291,15 +292,24 @@ __global__ __launch_bounds__(kBlock) void k_dec_grad(ngl_model md, DecArgs A) {
     }
     __syncthreads();
     for (int pp = ph; pp < kTile; pp += PH) {
+      float in[DP];
+#pragma unroll
+      for (int q = 0; q < DP / 4; ++q) {
+        const float4 v = reinterpret_cast<const float4*>(in_s[pp])[q];
+        in[4 * q] = v.x;
+        in[4 * q + 1] = v.y;
+        in[4 * q + 2] = v.z;
+        in[4 * q + 3] = v.w;
+      }
       float a = bk;
 #pragma unroll
-      for (int i = 0; i < DIN; ++i) a = fmaf(w[i], in_s[pp][i], a);
+      for (int i = 0; i < DIN; ++i) a = fmaf(w[i], in[i], a);
       const float g = g_s[pp];
       aw2 = fmaf(g, fmaxf(a, 0.0f), aw2);
       const float ga = a > 0.0f ? g * w2k : 0.0f;
       ab1 += ga;
 #pragma unroll
-      for (int i = 0; i < DIN; ++i) acc[i] = fmaf(ga, in_s[pp][i], acc[i]);
+      for (int i = 0; i < DIN; ++i) acc[i] = fmaf(ga, in[i], acc[i]);
     }
     if (threadIdx.x == 0)
       for (int pp = 0; pp < kTile; ++pp) ab2 += g_s[pp];
@@ -320,25 +330,38 @@ struct DecOut {
   float* db2;
 };
 
+// Each wavefront sums one output entry's nblk * PH partials: lane i takes
+// the partials i, i + 64, ... in order, then a fixed butterfly adds the
+// lanes (a fixed order, so the result is reproducible).  The extra
+// wavefront of block 0 sums db2.
 __global__ __launch_bounds__(kBlock) void k_dec_reduce(const float* __restrict__ part,
                                                        const float* __restrict__ part_b2, int H, int din, int PH,
                                                        int nblk, DecOut O) {
   const int L = blockIdx.y + 1;
-  const int e = blockIdx.x * kBlock + threadIdx.x;  // entry of [H][din+2]
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);  // entry of [H][din+2]
   const int W = din + 2;
+  const int n = nblk * PH;
   if (e < H * W) {
     const int k = e / W, i = e % W;
     float s = 0.0f;
-    for (int b = 0; b < nblk; ++b)
-      for (int ph = 0; ph < PH; ++ph) s += part[(((int64_t(L - 1) * kDecGrid + b) * PH + ph) * H + k) * W + i];
-    if (i < din) O.dW1[L - 1][k * din + i] = s;
-    else if (i == din) O.db1[L - 1][k] = s;
-    else O.dw2[L - 1][k] = s;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    for (int j = lane; j < n; j += 64) {
+      const int b = j / PH, ph = j % PH;
+      s += part[(((int64_t(L - 1) * kDecGrid + b) * PH + ph) * H + k) * W + i];
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+      if (i < din) O.dW1[L - 1][k * din + i] = s;
+      else if (i == din) O.db1[L - 1][k] = s;
+      else O.dw2[L - 1][k] = s;
+    }
+  } else if (e == H * W) {
     float s = 0.0f;
-    for (int b = 0; b < nblk; ++b) s += part_b2[int64_t(L - 1) * kDecGrid + b];
-    O.db2[L - 1] = s;
+    for (int b = lane; b < nblk; b += 64) s += part_b2[int64_t(L - 1) * kDecGrid + b];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) O.db2[L - 1] = s;
   }
 }
 
@@ -609,7 +632,8 @@ static int run_train(const ngl_model& md, const float* x, const float* target, c
   O.db2 = db2;
   const int din = M + (XYZ ? 3 : 0);
   const int H = md.hidden;
-  k_dec_reduce<<<dim3(unsigned((H * (din + 2) + kBlock - 1) / kBlock), Lm), kBlock, 0, s>>>(
+  const int waves = kBlock / 64;
+  k_dec_reduce<<<dim3(unsigned((H * (din + 2) + 1 + waves - 1) / waves), Lm), kBlock, 0, s>>>(
       w.dec_part, w.dec_b2, H, din, kBlock / H, dgrid, O);
   // 4. feature gradients, level by level
   for (int l = 1; l <= Lm; ++l) {
