@@ -190,54 +190,138 @@ __device__ inline bool slab_f32(const float o[3], const float inv[3], const floa
 // ray.  The children's boxes along axis a are bounded by three planes
 // p_k = -1 + (2 c_a + k) 2^-depth, k = 0, 1, 2 (exact dyadic values, the
 // same expressions box_of gives for the child cells), so the plane
-// distances (p_k - o_a) inv_a are formed once per axis; each child then
-// takes the same compare-and-select steps, in the same order, as slab_f32
-// on its own box, so every result is the same bits.
+// distances (p_k - o_a) inv_a are formed once per axis.  An axis the ray
+// runs parallel to (infinite inv) enters as the interval (-inf, +inf) for
+// the half holding the origin and (+inf, -inf) for the other: the first
+// leaves both running bounds unchanged, the second makes the child a miss,
+// which is what slab_f32's separate containment test decides.  Every child
+// then takes slab_f32's compare-and-select steps in slab_f32's order
+// (x, then y, then z), the x-y part shared by the two children that have
+// it, so each hit child's t_in and t_out are the same bits as slab_f32 on
+// its own box.
 struct ChildSlabs {
-  float nr[3][2], fr[3][2];  // near and far distance per axis and child bit
-  bool inside[3][2];         // axes with infinite inv: o within the child's extent
-  bool inf[3];
+  float nr[3][2], fr[3][2];  // entry and exit distance per axis and child bit
   __device__ ChildSlabs(const float o[3], const float inv[3], uint32_t c, int depth) {
 #pragma clang fp contract(off)
     const float step = 2.0f / float(1 << (depth + 1));
     const int ijk[3] = {cell_x(c), cell_y(c), cell_z(c)};
+    bool inf[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const int b2 = 2 * ijk[a];
-      const float p[3] = {-1.0f + float(b2) * step, -1.0f + float(b2 + 1) * step, -1.0f + float(b2 + 2) * step};
-      inf[a] = __builtin_isinf(inv[a]);
+      // p0 + step and p0 + 2 step are exact (multiples of step within [-1, 1])
+      const float p0 = -1.0f + float(2 * ijk[a]) * step;
+      const float p[3] = {p0, p0 + step, p0 + 2.0f * step};
       float t[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) t[k] = (p[k] - o[a]) * inv[a];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        inside[a][b] = p[b] <= o[a] && o[a] <= p[b + 1];
         const float t0 = t[b], t1 = t[b + 1];
         nr[a][b] = t0 < t1 ? t0 : t1;
         fr[a][b] = t0 < t1 ? t1 : t0;
       }
+      inf[a] = __builtin_isinf(inv[a]);
+    }
+    if (__builtin_expect(inf[0] || inf[1] || inf[2], 0)) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (inf[a]) {
+          const float p0 = -1.0f + float(2 * ijk[a]) * step;
+          const float p[3] = {p0, p0 + step, p0 + 2.0f * step};
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const bool inside = p[b] <= o[a] && o[a] <= p[b + 1];
+            nr[a][b] = inside ? -__builtin_inff() : __builtin_inff();
+            fr[a][b] = inside ? __builtin_inff() : -__builtin_inff();
+          }
+        }
+      }
     }
   }
-  // child ch = bx | by << 1 | bz << 2
-  __device__ bool test(int ch, float& t_in, float& t_out) const {
+  // All eight children: bit ch of the result is set when bit ch of `mask`
+  // is and the ray hits child ch (ch = bx | by << 1 | bz << 2); t_in and
+  // t_out are written for every child and meaningful for the hit ones.
+  __device__ uint32_t hits(uint32_t mask, float t_in[8], float t_out[8]) const {
 #pragma clang fp contract(off)
+    float mn[2][2], mx[2][2];
+#pragma unroll
+    for (int bx = 0; bx < 2; ++bx) {
+      const float n0 = nr[0][bx] > -__builtin_inff() ? nr[0][bx] : -__builtin_inff();
+      const float f0 = fr[0][bx] < __builtin_inff() ? fr[0][bx] : __builtin_inff();
+#pragma unroll
+      for (int by = 0; by < 2; ++by) {
+        mn[bx][by] = nr[1][by] > n0 ? nr[1][by] : n0;
+        mx[bx][by] = fr[1][by] < f0 ? fr[1][by] : f0;
+      }
+    }
+    uint32_t hm = 0;
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+      const int bx = ch & 1, by = (ch >> 1) & 1, bz = ch >> 2;
+      const float tmin = nr[2][bz] > mn[bx][by] ? nr[2][bz] : mn[bx][by];
+      const float tmax = fr[2][bz] < mx[bx][by] ? fr[2][bz] : mx[bx][by];
+      const float t0c = tmin > 0.0f ? tmin : 0.0f;
+      t_in[ch] = t0c;
+      t_out[ch] = tmax;
+      hm |= ((mask >> ch) & uint32_t(tmax >= t0c)) << ch;
+    }
+    return hm;
+  }
+  // Child ch alone, the same steps and bits as hits() gives for it.
+  __device__ static bool one(const float o[3], const float inv[3], uint32_t c, int depth, int ch, float& t_in,
+                             float& t_out) {
+#pragma clang fp contract(off)
+    const float step = 2.0f / float(1 << (depth + 1));
+    const int ijk[3] = {cell_x(c), cell_y(c), cell_z(c)};
     float tmin = -__builtin_inff(), tmax = __builtin_inff();
-    bool ok = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const int b = (ch >> a) & 1;
-      if (inf[a]) {
-        ok = ok && inside[a][b];
-      } else {
-        const float n = nr[a][b], f = fr[a][b];
-        tmin = n > tmin ? n : tmin;
-        tmax = f < tmax ? f : tmax;
+      const float p0 = -1.0f + float(2 * ijk[a]) * step;
+      const bool b = (ch >> a) & 1;
+      const float lo = b ? p0 + step : p0;
+      const float hi = b ? p0 + 2.0f * step : p0 + step;
+      const float t0 = (lo - o[a]) * inv[a];
+      const float t1 = (hi - o[a]) * inv[a];
+      float n = t0 < t1 ? t0 : t1;
+      float f = t0 < t1 ? t1 : t0;
+      if (__builtin_isinf(inv[a])) {
+        const bool inside = lo <= o[a] && o[a] <= hi;
+        n = inside ? -__builtin_inff() : __builtin_inff();
+        f = inside ? __builtin_inff() : -__builtin_inff();
       }
+      tmin = n > tmin ? n : tmin;
+      tmax = f < tmax ? f : tmax;
     }
     const float t0c = tmin > 0.0f ? tmin : 0.0f;
     t_in = t0c;
     t_out = tmax;
-    return ok && (tmax >= t0c);
+    return tmax >= t0c;
+  }
+  // The hit bits of hits() alone.  The running bounds start at -inf and
+  // +inf and never become NaN, and a NaN distance leaves them unchanged in
+  // both forms, so fmaxf/fminf give the same values as the selects up to
+  // the sign of zero, which the final comparison does not see.
+  __device__ uint32_t hit_mask(uint32_t mask) const {
+    float mn[2][2], mx[2][2];
+#pragma unroll
+    for (int bx = 0; bx < 2; ++bx) {
+      const float n0 = fmaxf(-__builtin_inff(), nr[0][bx]);
+      const float f0 = fminf(__builtin_inff(), fr[0][bx]);
+#pragma unroll
+      for (int by = 0; by < 2; ++by) {
+        mn[bx][by] = fmaxf(n0, nr[1][by]);
+        mx[bx][by] = fminf(f0, fr[1][by]);
+      }
+    }
+    uint32_t hm = 0;
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+      const int bx = ch & 1, by = (ch >> 1) & 1, bz = ch >> 2;
+      const float tmin = fmaxf(mn[bx][by], nr[2][bz]);
+      const float tmax = fminf(mx[bx][by], fr[2][bz]);
+      hm |= ((mask >> ch) & uint32_t(tmax >= fmaxf(tmin, 0.0f))) << ch;
+    }
+    return hm;
   }
 };
 

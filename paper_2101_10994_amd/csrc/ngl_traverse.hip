@@ -3,8 +3,8 @@
 //
 // Per depth, two launches over the current list of ray-voxel pairs:
 //   k_decide_count  Decide (FP32 slab tests) and a per-block sum
-//   k_decide_emit   each block sums the block sums before its own (its
-//                   offset of the ExclusiveSum), scans its decisions, then
+//   k_child_emit    each block sums the block sums before its own (its
+//   / k_root_emit   offset of the ExclusiveSum), scans its decisions, then
 //                   Subdivide (children front to back) or Compactify
 // so the global ExclusiveSum is reduce-then-scan with the block partition
 // fixed by (list size, grid).  Lists live in caller workspace, sizes stay
@@ -102,24 +102,6 @@ __device__ inline uint32_t decide_root(const Level& L, int64_t t, float& tin, fl
   return slab_f32(o, inv, lo, hi, tin, tout) ? 1u : 0u;
 }
 
-// Decide for the occupied children of hit pair (ray, vox) at depth d: bit c
-// of the result is set iff child c exists and the ray hits its box.
-__device__ inline uint32_t decide_children(const ngl_model& md, int d, const float o[3], const float inv[3],
-                                           int32_t vox, uint32_t* cmask, int32_t* fc) {
-  const uint32_t c = md.cell[d][vox];
-  const uint32_t m = md.child_mask[d][vox];
-  *cmask = m;
-  *fc = md.first_child[d][vox];
-  uint32_t hm = 0;
-  const ChildSlabs S(o, inv, c, d);
-#pragma unroll
-  for (int ch = 0; ch < 8; ++ch) {
-    float ti, to;
-    if ((m >> ch & 1u) && S.test(ch, ti, to)) hm |= 1u << ch;
-  }
-  return hm;
-}
-
 __device__ inline uint32_t wave_incl_scan(uint32_t x) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -130,10 +112,59 @@ __device__ inline uint32_t wave_incl_scan(uint32_t x) {
   return x;
 }
 
+// Inclusive scan of four 16-bit counters packed in one word (no carries:
+// every partial sum stays below 2^16).
+__device__ inline uint64_t wave_incl_scan4(uint64_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+__device__ inline uint32_t field16(uint64_t x, int u) { return uint32_t(x >> (16 * u)) & 0xffffu; }
+
 __device__ inline int64_t list_size(const Level& L, bool root) {
   if (root) return L.R;
   const int64_t n = *L.n_in;
   return n < L.cap ? n : L.cap;
+}
+
+// Each thread takes kTravU pairs of a block chunk at a time, kBlock apart
+// (coalesced), and issues every load of the group before its first use.
+constexpr int kTravU = 4;
+
+// Inputs of the child Decide of pair t (ray, voxel and its cell record).
+struct PairIn {
+  int32_t ray, vox, fc;
+  uint32_t cell, mask;
+  float o[3], inv[3];
+};
+
+__device__ inline void load_pairs(const ngl_model& md, const Level& L, const int64_t (&t)[kTravU],
+                                  const bool (&live)[kTravU], PairIn (&p)[kTravU]) {
+#pragma unroll
+  for (int u = 0; u < kTravU; ++u) {
+    p[u].ray = live[u] ? L.ray_in[t[u]] : 0;
+    p[u].vox = live[u] ? L.vox_in[t[u]] : 0;
+  }
+  const int d = L.depth;
+#pragma unroll
+  for (int u = 0; u < kTravU; ++u) {
+    if (live[u]) {
+      load_ray(L, p[u].ray, p[u].o, p[u].inv);
+      p[u].cell = md.cell[d][p[u].vox];
+      p[u].mask = md.child_mask[d][p[u].vox];
+      p[u].fc = md.first_child[d][p[u].vox];
+    }
+  }
+}
+
+// Bit ch of the result: child ch exists and the ray hits its box.
+__device__ inline uint32_t hit_children(const PairIn& p, int d) {
+  return ChildSlabs(p.o, p.inv, p.cell, d).hit_mask(p.mask);
 }
 
 template <bool ROOT>
@@ -142,18 +173,31 @@ __global__ __launch_bounds__(kBlock) void k_decide_count(ngl_model md, Level L) 
   int64_t begin, end;
   chunk_of(n, begin, end);
   uint32_t local = 0;
-  for (int64_t t = begin + threadIdx.x; t < end; t += kBlock) {
+  for (int64_t base = begin + threadIdx.x; base < end; base += kTravU * kBlock) {
+    int64_t t[kTravU];
+    bool live[kTravU];
+#pragma unroll
+    for (int u = 0; u < kTravU; ++u) {
+      t[u] = base + u * kBlock;
+      live[u] = t[u] < end;
+    }
     if constexpr (ROOT) {
-      float ti, to;
-      local += decide_root(L, t, ti, to);
+#pragma unroll
+      for (int u = 0; u < kTravU; ++u) {
+        float ti, to;
+        if (live[u]) local += decide_root(L, t[u], ti, to);
+      }
     } else {
-      float o[3], inv[3];
-      load_ray(L, L.ray_in[t], o, inv);
-      uint32_t cm;
-      int32_t fc;
-      const uint32_t hm = decide_children(md, L.depth, o, inv, L.vox_in[t], &cm, &fc);
-      L.hmask[t] = uint8_t(hm);
-      local += uint32_t(__popc(hm));
+      PairIn p[kTravU];
+      load_pairs(md, L, t, live, p);
+#pragma unroll
+      for (int u = 0; u < kTravU; ++u) {
+        if (live[u]) {
+          const uint32_t hm = hit_children(p[u], L.depth);
+          L.hmask[t[u]] = uint8_t(hm);
+          local += uint32_t(__popc(hm));
+        }
+      }
     }
   }
   __shared__ uint32_t part[kBlock / 64];
@@ -168,109 +212,183 @@ __global__ __launch_bounds__(kBlock) void k_decide_count(ngl_model md, Level L) 
   }
 }
 
-template <bool ROOT>
-__global__ __launch_bounds__(kBlock) void k_decide_emit(ngl_model md, Level L) {
-  const int64_t n = list_size(L, ROOT);
+// Block offset of the ExclusiveSum: the sum of the block sums before this
+// block; the last block also reports the list size.
+__device__ inline int64_t block_offset(const Level& L) {
+  __shared__ uint64_t red[kBlock / 64];
+  uint64_t v = 0;
+  for (int b = threadIdx.x; b < int(blockIdx.x); b += kBlock) v += L.bsum[b];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  uint64_t o = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) o += red[w];
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    const int64_t total = int64_t(o) + int64_t(L.bsum[blockIdx.x]);
+    *L.n_out = total;
+    if (total > L.counts[1]) L.counts[1] = total;
+    if (L.final_out) L.counts[0] = total;
+  }
+  return int64_t(o);
+}
+
+// Block-wide exclusive scan of kTravU counts per thread (pair (u, thread) in
+// list order u*kBlock + thread): start of each pair within the group and
+// the group total.
+__device__ inline void group_scan(const uint32_t (&D)[kTravU], uint32_t (&start)[kTravU], uint32_t& total) {
+  __shared__ uint64_t part[kBlock / 64];
+  uint64_t packed = 0;
+#pragma unroll
+  for (int u = 0; u < kTravU; ++u) packed |= uint64_t(D[u]) << (16 * u);
+  const uint64_t incl = wave_incl_scan4(packed);
+  if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = incl;
+  __syncthreads();
+  uint64_t pre = 0, tile = 0;
+#pragma unroll
+  for (int w = 0; w < kBlock / 64; ++w) {
+    const uint64_t s = part[w];
+    if (w < int(threadIdx.x >> 6)) pre += s;
+    tile += s;
+  }
+  __syncthreads();
+  uint32_t before = 0;
+#pragma unroll
+  for (int u = 0; u < kTravU; ++u) {
+    start[u] = before + field16(pre, u) + field16(incl, u) - D[u];
+    before += field16(tile, u);
+  }
+  total = before;
+}
+
+// Root pass: Compactify the rays that hit the root (at most one output per
+// input, so the writes are already in order).
+__global__ __launch_bounds__(kBlock) void k_root_emit(ngl_model md, Level L) {
+  const int64_t n = list_size(L, true);
   int64_t begin, end;
   chunk_of(n, begin, end);
-  __shared__ uint32_t part[kBlock / 64];
-  // this block's offset: the sum of the block sums before it; the last block
-  // also reports the list size
-  int64_t offset;
-  {
-    __shared__ uint64_t red[kBlock / 64];
-    uint64_t v = 0;
-    for (int b = threadIdx.x; b < int(blockIdx.x); b += kBlock) v += L.bsum[b];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-    __syncthreads();
-    uint64_t o = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) o += red[w];
-    offset = int64_t(o);
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-      const int64_t total = offset + int64_t(L.bsum[blockIdx.x]);
-      *L.n_out = total;
-      if (total > L.counts[1]) L.counts[1] = total;
-      if (L.final_out) L.counts[0] = total;
-    }
-  }
+  int64_t offset = block_offset(L);
   const int64_t cap = L.cap;
-  for (int64_t base = begin; base < end; base += kBlock) {
-    const int64_t t = base + threadIdx.x;
-    uint32_t D = 0, hm = 0;
-    float ti = 0.0f, to = 0.0f;
-    if (t < end) {
-      if constexpr (ROOT) {
-        D = decide_root(L, t, ti, to);
-      } else {
-        hm = L.hmask[t];
-        D = uint32_t(__popc(hm));
+  for (int64_t base = begin; base < end; base += kTravU * kBlock) {
+    uint32_t D[kTravU], start[kTravU], total;
+    float ti[kTravU], to[kTravU];
+#pragma unroll
+    for (int u = 0; u < kTravU; ++u) {
+      const int64_t t = base + u * kBlock + threadIdx.x;
+      D[u] = t < end ? decide_root(L, t, ti[u], to[u]) : 0u;
+    }
+    group_scan(D, start, total);
+#pragma unroll
+    for (int u = 0; u < kTravU; ++u) {
+      const int64_t k = offset + start[u];
+      if (D[u] && k < cap) {
+        L.ray_out[k] = int32_t(base + u * kBlock + threadIdx.x);
+        L.vox_out[k] = 0;
+        if (L.final_out) {
+          L.tin_out[k] = ti[u];
+          L.tout_out[k] = to[u];
+        }
       }
     }
-    const uint32_t incl = wave_incl_scan(D);
-    if ((threadIdx.x & 63) == 63) part[threadIdx.x >> 6] = incl;
-    __syncthreads();
-    uint32_t pre = 0, tile = 0;
+    offset += total;
+  }
+}
+
+// Child passes: Subdivide.  The hit children of a group of kTravU*kBlock
+// pairs fill a contiguous output range; the pairs' records go to LDS and
+// each thread then produces outputs j = thread, thread + kBlock, ... of the
+// range: its pair is the last one whose start is <= j (binary search over
+// the group's starts), its child the (j - start)-th hit child in front-to-
+// back order (child = visit ^ oct).  Consecutive threads write consecutive
+// outputs.
+__global__ __launch_bounds__(kBlock) void k_child_emit(ngl_model md, Level L) {
+  constexpr int G = kTravU * kBlock;
+  __shared__ uint16_t s_start[G];
+  __shared__ int32_t s_ray[G];
+  __shared__ int32_t s_fc[G];
+  __shared__ uint32_t s_cell[G];
+  __shared__ uint32_t s_info[G];  // visit-order hit bits | child mask << 8 | oct << 16
+  const int64_t n = list_size(L, false);
+  int64_t begin, end;
+  chunk_of(n, begin, end);
+  int64_t offset = block_offset(L);
+  const int64_t cap = L.cap;
+  const int d = L.depth;
+  const float step = 2.0f / float(1 << d);
+  for (int64_t base = begin; base < end; base += G) {
+    uint32_t D[kTravU], hm[kTravU], start[kTravU], total;
+    int32_t ray[kTravU], vox[kTravU];
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-      const uint32_t s = part[w];
-      if (w < int(threadIdx.x >> 6)) pre += s;
-      tile += s;
+    for (int u = 0; u < kTravU; ++u) {
+      const int64_t t = base + u * kBlock + threadIdx.x;
+      hm[u] = t < end ? L.hmask[t] : 0u;
+      D[u] = uint32_t(__popc(hm[u]));
+      ray[u] = D[u] ? L.ray_in[t] : 0;
+      vox[u] = D[u] ? L.vox_in[t] : 0;
     }
-    __syncthreads();
-    if (D) {
-      int64_t k = offset + pre + incl - D;
-      if constexpr (ROOT) {
-        // Compactify (root pass): keep the rays that hit the root
-        if (k < cap) {
-          L.ray_out[k] = int32_t(t);
-          L.vox_out[k] = 0;
-          if (L.final_out) {
-            L.tin_out[k] = ti;
-            L.tout_out[k] = to;
-          }
-        }
-      } else {
-        // Subdivide: hit children front to back, child = q XOR oct
-        const int32_t ray = L.ray_in[t];
-        const int32_t vox = L.vox_in[t];
-        float o[3], inv[3];
-        load_ray(L, ray, o, inv);
-        const int d = L.depth;
-        const uint32_t c = md.cell[d][vox];
-        const uint32_t m = md.child_mask[d][vox];
-        const int32_t fc = md.first_child[d][vox];
-        const float step = 2.0f / float(1 << d);
-        const int ijk[3] = {cell_x(c), cell_y(c), cell_z(c)};
+    uint32_t cell[kTravU], mask[kTravU];
+    int32_t fc[kTravU];
+    float o[kTravU][3];
+#pragma unroll
+    for (int u = 0; u < kTravU; ++u) {
+      if (D[u]) {
+        cell[u] = md.cell[d][vox[u]];
+        mask[u] = md.child_mask[d][vox[u]];
+        fc[u] = md.first_child[d][vox[u]];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) o[u][a] = L.o[a * L.R + ray[u]];
+      }
+    }
+    group_scan(D, start, total);
+#pragma unroll
+    for (int u = 0; u < kTravU; ++u) {
+      const int i = u * kBlock + threadIdx.x;
+      s_start[i] = uint16_t(start[u]);
+      if (D[u]) {
+        const int ijk[3] = {cell_x(cell[u]), cell_y(cell[u]), cell_z(cell[u])};
         int oct = 0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const float centre = -1.0f + (float(ijk[a]) + 0.5f) * step;  // exact dyadic
-          oct |= (o[a] > centre ? 1 : 0) << a;
+          oct |= (o[u][a] > centre ? 1 : 0) << a;
         }
-        const ChildSlabs S(o, inv, c, d);
+        uint32_t order = 0;  // bit r: the child visited r-th is hit
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int ch = q ^ oct;
-          if (hm >> ch & 1u) {
-            if (k < cap) {
-              L.ray_out[k] = ray;
-              L.vox_out[k] = fc + __popc(m & ((1u << ch) - 1u));
-              if (L.final_out) {
-                float a0, a1;
-                S.test(ch, a0, a1);
-                L.tin_out[k] = a0;
-                L.tout_out[k] = a1;
-              }
-            }
-            ++k;
-          }
+        for (int r = 0; r < 8; ++r) order |= ((hm[u] >> (r ^ oct)) & 1u) << r;
+        s_ray[i] = ray[u];
+        s_fc[i] = fc[u];
+        s_cell[i] = cell[u];
+        s_info[i] = order | mask[u] << 8 | uint32_t(oct) << 16;
+      }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < int(total); j += kBlock) {
+      int i = 0;
+#pragma unroll
+      for (int w = G / 2; w >= 1; w >>= 1)
+        if (s_start[i + w] <= j) i += w;
+      const uint32_t info = s_info[i];
+      uint32_t v = info & 0xffu;
+      for (int q = j - int(s_start[i]); q > 0; --q) v &= v - 1u;
+      const int ch = __builtin_ctz(v) ^ int(info >> 16);
+      const uint32_t m = (info >> 8) & 0xffu;
+      const int64_t k = offset + j;
+      if (k < cap) {
+        const int32_t r = s_ray[i];
+        L.ray_out[k] = r;
+        L.vox_out[k] = s_fc[i] + __popc(m & ((1u << ch) - 1u));
+        if (L.final_out) {
+          float oo[3], inv[3], a0, a1;
+          load_ray(L, r, oo, inv);
+          ChildSlabs::one(oo, inv, s_cell[i], d, ch, a0, a1);
+          L.tin_out[k] = a0;
+          L.tout_out[k] = a1;
         }
       }
     }
-    offset += tile;
+    __syncthreads();
+    offset += total;
   }
 }
 
@@ -435,10 +553,10 @@ int ngl_trace_octree(const ngl_model* m, const float* o, const float* d, int64_t
     }
     if (root) {
       k_decide_count<true><<<kTravGrid, kBlock, 0, s>>>(*m, L);
-      k_decide_emit<true><<<kTravGrid, kBlock, 0, s>>>(*m, L);
+      k_root_emit<<<kTravGrid, kBlock, 0, s>>>(*m, L);
     } else {
       k_decide_count<false><<<kTravGrid, kBlock, 0, s>>>(*m, L);
-      k_decide_emit<false><<<kTravGrid, kBlock, 0, s>>>(*m, L);
+      k_child_emit<<<kTravGrid, kBlock, 0, s>>>(*m, L);
     }
   }
   k_ray_offsets<<<unsigned((R + 1 + kBlock - 1) / kBlock), kBlock, 0, s>>>(pair_ray, counts, pair_capacity, R,
