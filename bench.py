@@ -360,7 +360,7 @@ def main():
                         "measured_GBps": traffic / (ms * 1e6) if traffic else None,
                         "measured_frac": traffic / (ms * 1e6) / HBM_PEAK_GBS if traffic else None,
                         "hbm_roof_tflops": (flops / traffic) * HBM_PEAK_GBS / 1e3 if traffic else None},
-                "targets": {"north_star_gather_hbm_frac": 0.5, "north_star_decoder_mfma_frac": 0.4}}
+                "targets": {"gather_hbm_frac": 0.5, "decoder_mfma_frac": 0.4}}
     if do_f:
         ev = comp["frame"]["sdf_evals"]
         tms = comp["frame"]["trace_ms"]

@@ -189,7 +189,7 @@ typedef struct {
   const int32_t* first_child[NGL_MAX_DEPTH]; /* device, depths 0..L */
   const int32_t* parent[NGL_MAX_DEPTH];      /* device, depths 1..L+1 */
   const int32_t* corners[NGL_MAX_LODS];      /* device, [nvox[l+1]][8] */
-  const void* feat[NGL_MAX_LODS];            /* device, [ncorner[l-1]][m], feat_dtype */
+  const void* feat[NGL_MAX_LODS];            /* device, [ncorner[l-1]][m], feat_dtype; below 4 GiB per level */
   const void* W1[NGL_MAX_LODS];              /* device, [h][din] row-major, w_dtype */
   const float* b1[NGL_MAX_LODS];             /* device, [h] */
   const float* w2[NGL_MAX_LODS];             /* device, [h] */

@@ -48,11 +48,12 @@ __device__ inline float f16_to_f32(uint32_t bits16) {
   return (float)__builtin_bit_cast(_Float16, (uint16_t)bits16);
 }
 
-// acc[k] += w * row[k] for row `c` of a [n][M] feature table.
+// acc[k] += w * row[k] for row `c` of a [n][M] feature table (below 4 GiB:
+// rows are addressed by a 32-bit byte offset, as in load_slice).
 template <int M, typename FT>
 __device__ inline void axpy_row(const void* base, int c, float w, float* acc) {
   if constexpr (std::is_same<FT, F32>::value) {
-    const float4* r = reinterpret_cast<const float4*>(static_cast<const float*>(base) + size_t(c) * M);
+    const float4* r = reinterpret_cast<const float4*>(static_cast<const char*>(base) + uint32_t(c) * uint32_t(M * 4));
 #pragma unroll
     for (int q = 0; q < M / 4; ++q) {
       const float4 v = r[q];
@@ -62,7 +63,7 @@ __device__ inline void axpy_row(const void* base, int c, float w, float* acc) {
       acc[4 * q + 3] = fmaf(w, v.w, acc[4 * q + 3]);
     }
   } else {
-    const uint4* r = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(base) + size_t(c) * M);
+    const uint4* r = reinterpret_cast<const uint4*>(static_cast<const char*>(base) + uint32_t(c) * uint32_t(M * 2));
 #pragma unroll
     for (int q = 0; q < M / 8; ++q) {
       uint4 v = r[q];
@@ -372,10 +373,14 @@ __device__ inline void interp_level(const ngl_model& md, int lvl, int v, int cx,
 }
 
 // v[i] = row[off + i] as float, i < D: a D-wide slice of row `c`.
+// Rows are addressed by a 32-bit byte offset from the table base (a level's
+// table is below 4 GiB), which the loads take as a scalar base plus a
+// vector offset.
 template <int M, typename FT, int D>
 __device__ inline void load_slice(const void* base, int c, int off, float* v) {
   if constexpr (std::is_same<FT, F32>::value) {
-    const float* r = static_cast<const float*>(base) + size_t(c) * M + off;
+    const uint32_t ob = uint32_t(c) * uint32_t(M * 4) + uint32_t(off * 4);
+    const float* r = reinterpret_cast<const float*>(static_cast<const char*>(base) + ob);
     if constexpr (D % 4 == 0) {
 #pragma unroll
       for (int q = 0; q < D / 4; ++q) {
@@ -390,7 +395,8 @@ __device__ inline void load_slice(const void* base, int c, int off, float* v) {
       for (int i = 0; i < D; ++i) v[i] = r[i];
     }
   } else {
-    const uint16_t* r = static_cast<const uint16_t*>(base) + size_t(c) * M + off;
+    const uint32_t ob = uint32_t(c) * uint32_t(M * 2) + uint32_t(off * 2);
+    const uint16_t* r = reinterpret_cast<const uint16_t*>(static_cast<const char*>(base) + ob);
     uint32_t h[D];
     if constexpr (D % 8 == 0) {
 #pragma unroll
@@ -419,7 +425,8 @@ __device__ inline void load_slice(const void* base, int c, int off, float* v) {
 template <int M, typename FT, int D>
 __device__ inline void axpy_slice(const void* base, int c, int off, float w, float* acc) {
   if constexpr (std::is_same<FT, F32>::value) {
-    const float* r = static_cast<const float*>(base) + size_t(c) * M + off;
+    const float* r = reinterpret_cast<const float*>(static_cast<const char*>(base) + uint32_t(c) * uint32_t(M * 4) +
+                                                    uint32_t(off * 4));
     float v[D];
     if constexpr (D % 4 == 0) {
 #pragma unroll
@@ -437,7 +444,8 @@ __device__ inline void axpy_slice(const void* base, int c, int off, float w, flo
 #pragma unroll
     for (int i = 0; i < D; ++i) acc[i] = fmaf(w, v[i], acc[i]);
   } else {
-    const uint16_t* r = static_cast<const uint16_t*>(base) + size_t(c) * M + off;
+    const uint16_t* r = reinterpret_cast<const uint16_t*>(static_cast<const char*>(base) + uint32_t(c) * uint32_t(M * 2) +
+                                                          uint32_t(off * 2));
     uint16_t h[D];
     if constexpr (D % 8 == 0) {
 #pragma unroll

@@ -84,12 +84,15 @@ __device__ inline void lod_of_distance(const ngl_lod_select& s, int num_lods, fl
   *alpha = a;
 }
 
-// Voxels and cells of levels 1..Lp on the ancestor chain of pair voxel v
-// (level Lpair; parents always exist).  With `known`, vox and cell hold the
-// chain of an earlier pair of the same ray, and the walk stops at the first
-// ancestor already held: everything above it is the same.
+// Voxels of levels 1..Lp on the ancestor chain of pair voxel v (level
+// Lpair; parents always exist) and the cell of the level-Lc voxel, Lc =
+// min(Lp, Lpair); the cell of an ancestor at level l <= Lc is that cell's
+// coordinates shifted right by Lc - l (cells nest).  With `known`, vox and
+// cLc hold the chain of an earlier pair of the same ray, and the walk stops
+// at the first ancestor already held: everything above it is the same.
 __device__ __forceinline__ void ancestor_chain(const ngl_model& md, int v, int Lpair, int Lp, bool known, int* vox,
-                                               uint32_t* cell) {
+                                               uint32_t* cLc) {
+  const int Lc = Lp < Lpair ? Lp : Lpair;
   int w = v;
 #pragma unroll
   for (int l = NGL_MAX_LODS; l >= 1; --l) {
@@ -97,11 +100,17 @@ __device__ __forceinline__ void ancestor_chain(const ngl_model& md, int v, int L
       if (l <= Lp) {
         if (known && vox[l - 1] == w) break;
         vox[l - 1] = w;
-        cell[l - 1] = md.cell[l + 1][w];
+        if (l == Lc) *cLc = md.cell[l + 1][w];
       }
       w = md.parent[l + 1][w];
     }
   }
+}
+
+// Packed cell at level l of the ancestor of the level-Lc cell c.
+__device__ __forceinline__ uint32_t cell_at(uint32_t c, int Lc, int l) {
+  const int sh = Lc - l;
+  return pack_cell(cell_x(c) >> sh, cell_y(c) >> sh, cell_z(c) >> sh);
 }
 
 // Ray served at queue position q: with an image width W (a multiple of 8,
@@ -149,6 +158,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
   const int Lp = blend ? lod + 1 : lod;
   const int PD = A.pair_depth > 0 ? A.pair_depth : Lp + 1;  // depth of the pairs
   const int Lpair = PD - 1;                                 // their feature level
+  const int Lc = Lp < Lpair ? Lp : Lpair;                   // deepest level of the held chain
   const int64_t nv_t = ANALYTIC ? 0 : md.nvox[PD];
   int64_t R = A.R;  // queue length
   const int32_t* ids = A.ray_ids;
@@ -171,12 +181,9 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
   float t = 0.0f, prev = __builtin_inff();
   float oo[3] = {0.0f, 0.0f, 0.0f}, dd[3] = {0.0f, 0.0f, 0.0f};
   int vox[NGL_MAX_LODS];
-  uint32_t cell[NGL_MAX_LODS];
+  uint32_t cLc = 0;  // cell of the level-Lc voxel (the blend level lod + 1 when Lc = Lp)
 #pragma unroll
-  for (int l = 0; l < NGL_MAX_LODS; ++l) {
-    vox[l] = 0;
-    cell[l] = 0;
-  }
+  for (int l = 0; l < NGL_MAX_LODS; ++l) vox[l] = 0;
   bool exhausted = false;  // wave-uniform
   unsigned nfin = 0;       // rays this lane finished since the last report
 #define NGL_FINISH(st_, hv_)            \
@@ -290,15 +297,15 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
             NGL_FINISH(NGL_RAY_INVALID, -1);  // hit list does not belong to this depth
           } else {
             if (p != cp) {
-              ancestor_chain(md, v, Lpair, Lp, cp >= 0, vox, cell);
+              ancestor_chain(md, v, Lpair, Lp, cp >= 0, vox, &cLc);
               cp = p;
             }
             if constexpr (!COOP) {
 #pragma unroll
               for (int l = 1; l <= NGL_MAX_LODS; ++l)
                 if (l <= lod)
-                  interp_level<M, FT>(md, l, vox[l - 1], cell_x(cell[l - 1]), cell_y(cell[l - 1]),
-                                      cell_z(cell[l - 1]), x, z);
+                  interp_level<M, FT>(md, l, vox[l - 1], cell_x(cell_at(cLc, Lc, l)),
+                                      cell_y(cell_at(cLc, Lc, l)), cell_z(cell_at(cLc, Lc, l)), x, z);
             }
             ok = true;
           }
@@ -326,10 +333,11 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
               float acc[D];
 #pragma unroll
               for (int i = 0; i < D; ++i) acc[i] = 0.0f;
+              const uint32_t cq_lc = uint32_t(__shfl(int(cLc), q, 64));
 #pragma unroll
               for (int l = 1; l <= NGL_MAX_LODS; ++l)
                 if (l <= lod) {
-                  const uint32_t cq = uint32_t(__shfl(int(cell[l - 1]), q, 64));
+                  const uint32_t cq = cell_at(cq_lc, Lc, l);
                   tile_level<M, FT>(md, l, __shfl(ok ? vox[l - 1] : -1, q, 64), xq, cell_x(cq), cell_y(cq), cell_z(cq),
                                     g, acc);
                 }
@@ -339,7 +347,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
               float d = b2a + DEC::tile(S.frag0, S.w2s0, rows, H);
               if (blend && ((mixing >> (16 * tt)) & 0xffffull)) {
                 wave_lds_sync();
-                const uint32_t cq = uint32_t(__shfl(int(cell[lod]), q, 64));
+                const uint32_t cq = cq_lc;  // level lod + 1 = Lp
                 tile_level<M, FT>(md, lod + 1, __shfl(mix ? vox[lod] : -1, q, 64), xq, cell_x(cq), cell_y(cq),
                                   cell_z(cq), g, acc);
                 DEC::template tile_slice<D>(rows, r, g * D, acc);
@@ -359,7 +367,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
           const bool mix = ok && al > 0.0f;  // Eq. 3 blend with the level lod+1 voxel
           const uint64_t mixing = __ballot(mix);
           if (blend && mixing) {
-            if (mix) interp_level<M, FT>(md, lod + 1, vox[lod], cell_x(cell[lod]), cell_y(cell[lod]), cell_z(cell[lod]), x, z);
+            if (mix) interp_level<M, FT>(md, lod + 1, vox[lod], cell_x(cLc), cell_y(cLc), cell_z(cLc), x, z);
             wave_lds_sync();
             DEC::stage(S.stage, x, z);
             wave_lds_sync();
@@ -371,7 +379,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
         } else if (ok) {
           dist = decode_f32<M, XYZ>(md, lod, x, z);
           if (blend && al > 0.0f) {
-            interp_level<M, FT>(md, lod + 1, vox[lod], cell_x(cell[lod]), cell_y(cell[lod]), cell_z(cell[lod]), x, z);
+            interp_level<M, FT>(md, lod + 1, vox[lod], cell_x(cLc), cell_y(cLc), cell_z(cLc), x, z);
             dist = (1.0f - al) * dist + al * decode_f32<M, XYZ>(md, lod + 1, x, z);
           }
         }
@@ -464,6 +472,7 @@ __device__ __forceinline__ void serve_queue_wide(const ngl_model& md, const Trac
   const int Lp = blend ? lod + 1 : lod;
   const int PD = A.pair_depth > 0 ? A.pair_depth : Lp + 1;
   const int Lpair = PD - 1;
+  const int Lc = Lp < Lpair ? Lp : Lpair;
   const int64_t nv_t = md.nvox[PD];
   int64_t R = A.R;
   const int32_t* ids = A.ray_ids;
@@ -484,12 +493,9 @@ __device__ __forceinline__ void serve_queue_wide(const ngl_model& md, const Trac
   float t = 0.0f, prev = __builtin_inff();
   float oo[3] = {0.0f, 0.0f, 0.0f}, dd[3] = {0.0f, 0.0f, 0.0f};
   int vox[NGL_MAX_LODS];
-  uint32_t cell[NGL_MAX_LODS];
+  uint32_t cLc = 0;  // cell of the level-Lc voxel (the blend level lod + 1 when Lc = Lp)
 #pragma unroll
-  for (int l = 0; l < NGL_MAX_LODS; ++l) {
-    vox[l] = 0;
-    cell[l] = 0;
-  }
+  for (int l = 0; l < NGL_MAX_LODS; ++l) vox[l] = 0;
   bool exhausted = false;  // wave-uniform
   unsigned nfin = 0;
 #define NGL_FINISH_W(st_, hv_)          \
@@ -599,14 +605,14 @@ __device__ __forceinline__ void serve_queue_wide(const ngl_model& md, const Trac
           NGL_FINISH_W(NGL_RAY_INVALID, -1);
         } else {
           if (p != cp) {
-            ancestor_chain(md, v, Lpair, Lp, cp >= 0, vox, cell);
+            ancestor_chain(md, v, Lpair, Lp, cp >= 0, vox, &cLc);
             cp = p;
           }
 #pragma unroll
           for (int l = 1; l <= NGL_MAX_LODS; ++l)
             if (l <= lod)
-              interp_level_slice<M, FT, D>(md, l, vox[l - 1], cell_x(cell[l - 1]), cell_y(cell[l - 1]),
-                                           cell_z(cell[l - 1]), x, g * D, acc);
+              interp_level_slice<M, FT, D>(md, l, vox[l - 1], cell_x(cell_at(cLc, Lc, l)),
+                                           cell_y(cell_at(cLc, Lc, l)), cell_z(cell_at(cLc, Lc, l)), x, g * D, acc);
           ok = true;
         }
       }
@@ -631,8 +637,8 @@ __device__ __forceinline__ void serve_queue_wide(const ngl_model& md, const Trac
       const uint64_t mixing = __ballot(mixs);
       if (blend && mixing) {
         if (ok && al > 0.0f)
-          interp_level_slice<M, FT, D>(md, lod + 1, vox[lod], cell_x(cell[lod]), cell_y(cell[lod]),
-                                       cell_z(cell[lod]), x, g * D, acc);
+          interp_level_slice<M, FT, D>(md, lod + 1, vox[lod], cell_x(cLc), cell_y(cLc),
+                                       cell_z(cLc), x, g * D, acc);
 #pragma unroll
         for (int i = 0; i < D; ++i) zbuf[slot * ZR + g * D + i] = acc[i];
         wave_lds_sync();
