@@ -23,11 +23,11 @@
 
 namespace ngl {
 
-constexpr int kSortGrid = 512;  // most blocks of the radix-sort passes
+constexpr int kSortGrid = 256;  // most blocks of the radix-sort passes
 constexpr int kDecGrid = 204;   // most blocks per LOD of the decoder-gradient pass (5 LODs fill 256 CUs x 4)
 
 // Grids sized to the batch (small batches of the fitting loop would
-// otherwise pay for the full grids): about 1024 keys per sort block and
+// otherwise pay for the full grids): at least 1024 keys per sort block and
 // 256 points per decoder-gradient block.  Deterministic for a given P.
 inline int sort_grid(int64_t P) { return int(std::min<int64_t>(kSortGrid, std::max<int64_t>(1, (P + 1023) / 1024))); }
 inline int dec_grid(int64_t P) { return int(std::min<int64_t>(kDecGrid, std::max<int64_t>(1, (P + 255) / 256))); }
@@ -474,7 +474,30 @@ __global__ __launch_bounds__(64) void k_vox_reduce(LevelArgs A, int64_t nv) {
   float acc[PER];
 #pragma unroll
   for (int s = 0; s < PER; ++s) acc[s] = 0.0f;
-  for (int64_t r = lo; r < nrec && A.rec_key[r] == v; ++r) {
+  // the voxel's records are [lo, hi); eight are loaded at a time and added
+  // in ascending order
+  hi = nrec;
+  {
+    int64_t a = lo;
+    while (a < hi) {
+      const int64_t mid = (a + hi) >> 1;
+      if (A.rec_key[mid] <= v) a = mid + 1;
+      else hi = mid;
+    }
+  }
+  int64_t r = lo;
+  for (; r + 8 <= hi; r += 8) {
+    float t[8][PER];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int s = 0; s < PER; ++s) t[k][s] = A.recs[(r + k) * 8 * M + s * 64 + threadIdx.x];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+      for (int s = 0; s < PER; ++s) acc[s] += t[k][s];
+  }
+  for (; r < hi; ++r) {
 #pragma unroll
     for (int s = 0; s < PER; ++s) acc[s] += A.recs[r * 8 * M + s * 64 + threadIdx.x];
   }
