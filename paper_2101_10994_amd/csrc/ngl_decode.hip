@@ -21,19 +21,6 @@ struct DecodeArgs {
   float* sdf;      // [P]
 };
 
-// Eight consecutive features f0..f0+7 of row p as BF16 bits: BF16 rows as
-// stored (lo = 0); FP32 rows split into high parts and residuals.
-template <int M, typename ZT>
-__device__ inline void load_z8(const void* z, int64_t p, int f0, uint4& hi, uint4& lo) {
-  if constexpr (std::is_same<ZT, BF16>::value) {
-    hi = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(z) + p * M + f0);
-    lo = make_uint4(0u, 0u, 0u, 0u);
-  } else {
-    const float4* r = reinterpret_cast<const float4*>(static_cast<const float*>(z) + p * M + f0);
-    split_bf16x8(r[0], r[1], hi, lo);
-  }
-}
-
 // Row p of z as FP32.
 template <int M, typename ZT>
 __device__ inline void load_row(const void* z, int64_t p, float* out) {
@@ -67,53 +54,84 @@ __device__ inline void load_row(const void* z, int64_t p, float* out) {
 // 32s + 8g..+7 of point j of a tile for every K-step s, which is exactly its
 // B fragment, and the lanes of g = 0 carry the tile's [x_hi, x_lo, 1, 1]
 // step.  FP32 rows take a second pass per feature step with their BF16
-// residuals (BF16 rows are exact and skip it).  All U tiles' inputs are
-// loaded before the first decode.  NH = hidden/16.
-template <int M, bool XYZ, int NH, typename ZT, int U, bool FULL>
-__device__ inline void decode_tiles(const DecodeArgs& A, int64_t p0, const bf16x8 (&fr)[NH][MfmaShape<M, XYZ>::KS],
-                                    const floatx4 (&w2v)[NH], float b2) {
+// residuals (BF16 rows are exact and skip it).  The raw inputs of the
+// wavefront's next U tiles are loaded before the current ones are decoded.
+// NH = hidden/16.
+template <int M, bool XYZ, typename ZT, int U>
+struct RawTiles {
+  static constexpr int KZ = MfmaShape<M, XYZ>::KZ;
+  static constexpr int W = std::is_same<ZT, BF16>::value ? 1 : 2;  // 16-byte vectors per K-step and lane
+  uint4 z[U][KZ][W];
+  float x[U][3];
+};
+
+template <int M, bool XYZ, typename ZT, int U>
+__device__ inline void load_tiles(const DecodeArgs& A, int64_t p0, RawTiles<M, XYZ, ZT, U>& R) {
+  using RT = RawTiles<M, XYZ, ZT, U>;
+  const int g = (threadIdx.x & 63) >> 4;
+  const int64_t P = A.P;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t p = p0 + 16 * u;
+    const int64_t pc = p < P ? p : P - 1;
+#pragma unroll
+    for (int s = 0; s < RT::KZ; ++s) {
+      const int f0 = 32 * s + 8 * g;
+#pragma unroll
+      for (int w = 0; w < RT::W; ++w) R.z[u][s][w] = make_uint4(0u, 0u, 0u, 0u);
+      if (f0 < M) {
+        if constexpr (RT::W == 1) {
+          R.z[u][s][0] = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(A.z) + pc * M + f0);
+        } else {
+          const uint4* r = reinterpret_cast<const uint4*>(static_cast<const float*>(A.z) + pc * M + f0);
+          R.z[u][s][0] = r[0];
+          R.z[u][s][1] = r[1];
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) R.x[u][a] = XYZ ? A.x[a * P + pc] : 0.0f;
+  }
+}
+
+template <int M, bool XYZ, int NH, typename ZT, int U>
+__device__ inline void decode_tiles(const DecodeArgs& A, int64_t p0, const RawTiles<M, XYZ, ZT, U>& R,
+                                    const bf16x8 (&fr)[NH][MfmaShape<M, XYZ>::KS], const floatx4 (&w2v)[NH],
+                                    float b2) {
   using S = MfmaShape<M, XYZ>;
   constexpr bool SPLIT = !std::is_same<ZT, BF16>::value;
   constexpr int NL = SPLIT ? S::KZ : 1;
   const int lane = threadIdx.x & 63, g = lane >> 4;
   const int64_t P = A.P;
-  bf16x8 b[U][S::KS];
-  bf16x8 bl[U][NL];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const int64_t p = p0 + 16 * u;
-    const bool in = FULL || p < P;
-    const int64_t pc = in ? p : P - 1;
+    bf16x8 b[S::KS];
+    bf16x8 bl[NL];
 #pragma unroll
     for (int s = 0; s < S::KZ; ++s) {
-      const int f0 = 32 * s + 8 * g;
-      uint4 hi = make_uint4(0u, 0u, 0u, 0u), lo = hi;
-      if (f0 < M) load_z8<M, ZT>(A.z, pc, f0, hi, lo);
-      b[u][s] = __builtin_bit_cast(bf16x8, hi);
-      if constexpr (SPLIT) bl[u][s] = __builtin_bit_cast(bf16x8, lo);
+      if constexpr (SPLIT) {
+        uint4 hi, lo;
+        split_bf16x8(__builtin_bit_cast(float4, R.z[u][s][0]), __builtin_bit_cast(float4, R.z[u][s][1]), hi, lo);
+        b[s] = __builtin_bit_cast(bf16x8, hi);
+        bl[s] = __builtin_bit_cast(bf16x8, lo);
+      } else {
+        b[s] = __builtin_bit_cast(bf16x8, R.z[u][s][0]);
+      }
     }
-    float x[3] = {0.0f, 0.0f, 0.0f};
-    if constexpr (XYZ) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) x[a] = A.x[a * P + pc];
-    }
-    const uint4 t = pos_bias_row<XYZ>(x);
+    const uint4 t = pos_bias_row<XYZ>(R.x[u]);
     const bool keep = g == 0;
-    b[u][S::KZ] = __builtin_bit_cast(bf16x8, make_uint4(keep ? t.x : 0u, keep ? t.y : 0u, keep ? t.z : 0u,
-                                                        keep ? t.w : 0u));
-  }
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
+    b[S::KZ] = __builtin_bit_cast(bf16x8, make_uint4(keep ? t.x : 0u, keep ? t.y : 0u, keep ? t.z : 0u,
+                                                     keep ? t.w : 0u));
     floatx4 acc[NH];
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
       acc[h] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
       for (int s = 0; s < S::KZ; ++s) {
-        acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[h][s], b[u][s], acc[h], 0, 0, 0);
-        if constexpr (SPLIT) acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[h][s], bl[u][s], acc[h], 0, 0, 0);
+        acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[h][s], b[s], acc[h], 0, 0, 0);
+        if constexpr (SPLIT) acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[h][s], bl[s], acc[h], 0, 0, 0);
       }
-      acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[h][S::KZ], b[u][S::KZ], acc[h], 0, 0, 0);
+      acc[h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fr[h][S::KZ], b[S::KZ], acc[h], 0, 0, 0);
     }
     float part = 0.0f;
 #pragma unroll
@@ -124,7 +142,7 @@ __device__ inline void decode_tiles(const DecodeArgs& A, int64_t p0, const bf16x
     part += __shfl_xor(part, 16, 64);
     part += __shfl_xor(part, 32, 64);
     const int64_t p = p0 + 16 * u;
-    if (g == 0 && (FULL || p < P)) A.sdf[p] = b2 + part;
+    if (g == 0 && p < P) A.sdf[p] = b2 + part;
   }
 }
 
@@ -156,15 +174,15 @@ __global__ __launch_bounds__(256) void k_decode_rf(ngl_model md, DecodeArgs A) {
     for (int r = 0; r < 4; ++r) w2v[h][r] = w2l[16 * h + 4 * g + r];
   }
   const float b2 = md.b2[A.lod - 1];
-  const int64_t P = A.P;
-  const int64_t chunks = (P + 16 * U - 1) / (16 * U);
+  const int64_t chunks = (A.P + 16 * U - 1) / (16 * U);
   const int64_t nw = int64_t(gridDim.x) * (blockDim.x >> 6);
-  for (int64_t c = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6); c < chunks; c += nw) {
-    const int64_t p0 = c * (16 * U) + j;
-    if ((c + 1) * (16 * U) <= P)
-      decode_tiles<M, XYZ, NH, ZT, U, true>(A, p0, fr, w2v, b2);
-    else
-      decode_tiles<M, XYZ, NH, ZT, U, false>(A, p0, fr, w2v, b2);
+  int64_t c = int64_t(blockIdx.x) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  RawTiles<M, XYZ, ZT, U> next;
+  if (c < chunks) load_tiles<M, XYZ, ZT, U>(A, c * (16 * U) + j, next);
+  for (; c < chunks; c += nw) {
+    const RawTiles<M, XYZ, ZT, U> cur = next;
+    if (c + nw < chunks) load_tiles<M, XYZ, ZT, U>(A, (c + nw) * (16 * U) + j, next);
+    decode_tiles<M, XYZ, NH, ZT, U>(A, c * (16 * U) + j, cur, fr, w2v, b2);
   }
 }
 
@@ -209,7 +227,7 @@ __global__ __launch_bounds__(64 * NW) void k_decode_lds(ngl_model md, DecodeArgs
 }
 
 #ifndef NGL_DECODE_TILES
-#define NGL_DECODE_TILES 8
+#define NGL_DECODE_TILES 4
 #endif
 constexpr int kDecodeU = NGL_DECODE_TILES;  // 16-point tiles per wavefront iteration
 
