@@ -53,14 +53,14 @@ TRAVERSAL_BYTES = 16
 COUNTERS = {
     # both launches of the phased FP32 trace (first 24 evaluations, then the wide kernel)
     "k_sphere_trace": {"sources": ["ngl_trace_impl.h", "ngl_device.h", "ngl_mfma.h"],
-                       "sha256": "dbb305cd3160276fbb0af4f12b894dfa8156fec8c7d3839fd7543c88f5a94a72",
-                       "fetch_kib": 220557.8 + 24146.3, "write_kib": 39035.5 + 3650.4},
+                       "sha256": "a58ebe4e45f1827b11545b3e9c0b553759d61be8f26085741455c77cf73e294f",
+                       "fetch_kib": 317654.2 + 22781.2, "write_kib": 33583.1 + 3481.4},
     # k_query_coop, FP32 features and matrix-core decoder
     "k_query": {"sources": ["ngl_query_impl.h", "ngl_device.h", "ngl_mfma.h"],
-                "sha256": "dd5e8fa38a0019245989e6beb3fa0ce339ccc11869176e0a478ae329f4b965a2",
-                "fetch_kib": 114020.2, "write_kib": 4096.0},
+                "sha256": "92db70ae7d26195fdf4ad207264c04a5f21e847981bce0751da9611dcc62a3ff",
+                "fetch_kib": 105941.0, "write_kib": 4096.0},
 }
-FETCH_SCALE = (256 << 10) / 131088.1
+FETCH_SCALE = (256 << 10) / 131087.8
 WRITE_SCALE = (256 << 10) / 262144.0
 
 
