@@ -55,6 +55,11 @@ COUNTERS = {
     "k_sphere_trace": {"sources": ["ngl_trace_impl.h", "ngl_device.h", "ngl_mfma.h"],
                        "sha256": "a58ebe4e45f1827b11545b3e9c0b553759d61be8f26085741455c77cf73e294f",
                        "fetch_kib": 317654.2 + 22781.2, "write_kib": 33583.1 + 3481.4},
+    # every launch of one traversal to depth 6 (root and six child passes,
+    # ray inverses, segment offsets)
+    "traverse": {"sources": ["ngl_traverse.hip", "ngl_device.h"],
+                 "sha256": "d1c4196cc585dd988bfdc7542ad8170f78014f558a7bdd22b721f7c9ab6091b1",
+                 "fetch_kib": 347790.0, "write_kib": 380745.0},
     # k_query_coop, FP32 features and matrix-core decoder
     "k_query": {"sources": ["ngl_query_impl.h", "ngl_device.h", "ngl_mfma.h"],
                 "sha256": "92db70ae7d26195fdf4ad207264c04a5f21e847981bce0751da9611dcc62a3ff",
@@ -373,6 +378,10 @@ def main():
             "measured_hbm_frac": traffic / (tms * 1e6) / HBM_PEAK_GBS if traffic else None}
         comp["frame"]["trace_algorithmic_GBps"] = TRACE_STEP_BYTES * ev / (tms * 1e6)
         comp["frame"]["trace_hbm_traffic_bytes"] = traffic
+        ttr = measured_traffic("traverse")
+        trms = comp["frame"]["traverse_ms"]
+        comp["frame"]["traverse_hbm_traffic_bytes"] = ttr
+        comp["frame"]["traverse_measured_hbm_frac"] = ttr / (trms * 1e6) / HBM_PEAK_GBS if ttr else None
 
     if args.calibrate_copy:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE readings
