@@ -161,7 +161,7 @@ def main():
                     help="skip the decoder-alone, LOD-selection, fitting and octree-build components")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, run one plain 256 MiB device copy (counter calibration)")
-    ap.add_argument("--only", choices=["query", "frame", "train", "half", "decoder", "precision"], default=None,
+    ap.add_argument("--only", choices=["query", "frame", "train", "half", "decoder", "precision", "fit"], default=None,
                     help="run a single component (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -400,8 +400,9 @@ def main():
         comp["frame_lod_select"] = run_lod_select(model, cfg, o, d, buf, args.steps, args.warmup)
     if args.only == "precision" or (args.only is None and not args.no_extras):
         comp["precision"] = run_precision(dev, max(3, args.steps // 2), 1)
-    if args.only is None and not args.no_extras:
+    if args.only == "fit" or (args.only is None and not args.no_extras):
         comp["fit"] = run_fit(S, dev)
+    if args.only is None and not args.no_extras:
         comp["octree_build"] = run_octree_build(dev, args.steps)
         if do_h:
             hq = comp["bf16_form"]["queries_per_s"] * DEC_MFMA_FLOPS / 1e12
@@ -604,9 +605,9 @@ def run_fit(S, dev):
         last = f.run_epoch()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
-        out["batch_%d" % batch] = {"epoch_ms": ms, "points_per_s": f.N / (ms * 1e-3), "steps": f.N // batch,
-                                   "loss_epoch1": first, "loss_epoch2": last,
-                                   "surface_samples": int(f.sampler["count"].item())}
+        out["batch_%d" % batch] = {
+            "epoch_ms": ms, "points_per_s": f.N / (ms * 1e-3), "steps": f.N // batch, "loss_epoch1": first,
+            "loss_epoch2": last, "surface_samples": int(f.sampler["count"].item())}
     return out
 
 

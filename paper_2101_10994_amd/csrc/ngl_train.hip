@@ -28,10 +28,15 @@ constexpr int kDecGrid = 204;   // most blocks per LOD of the decoder-gradient p
 
 // Grids sized to the batch (small batches of the fitting loop would
 // otherwise pay for the full grids): at least 1024 keys per sort block and
-// 256 points per decoder-gradient block.  Deterministic for a given P.
+// 64 points (one tile) per decoder-gradient block.  Deterministic for a
+// given P.
 inline int sort_grid(int64_t P) { return int(std::min<int64_t>(kSortGrid, std::max<int64_t>(1, (P + 1023) / 1024))); }
-inline int dec_grid(int64_t P) { return int(std::min<int64_t>(kDecGrid, std::max<int64_t>(1, (P + 255) / 256))); }
+inline int dec_grid(int64_t P) { return int(std::min<int64_t>(kDecGrid, std::max<int64_t>(1, (P + 63) / 64))); }
 constexpr int kTile = 64;       // sorted points per record tile (one wavefront)
+// Batches below this many points run the per-point stage with a wavefront
+// per point (k_point_wave): a lane per point would leave most of the chip
+// idle and each lane's serial decoder work would set the step time.
+constexpr int64_t kPointWaveMax = 16384;
 
 __device__ inline uint32_t spread3_10(uint32_t v) {
   v &= 0x3ffu;
@@ -221,6 +226,157 @@ __global__ __launch_bounds__(kBlock) void k_point(ngl_model md, PointArgs A) {
   }
 }
 
+// Small batches (fewer points than lanes to keep busy): one wavefront per
+// sorted point, the same quantities as k_point.  Lanes split each level's
+// gather (lane = corner j * 8 + slice: 8 corners x M/8 features), the
+// decoders' hidden units (unit k = lane + 64 u) and the adjoint
+// (lane = output i + M * part, parts summing strided unit ranges); the
+// partial sums are combined by fixed butterflies, so results are
+// deterministic.  The squared residual of each point goes to loss_part[p].
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int M, bool XYZ, bool TRAIN>
+__global__ __launch_bounds__(kBlock) void k_point_wave(ngl_model md, PointArgs A) {
+  constexpr int OFF = XYZ ? 3 : 0;
+  constexpr int DIN = M + OFF;
+  constexpr int FE = M / 8;        // gather: features per lane (8 lanes per corner row)
+  constexpr int KP = 64 / M;       // adjoint: lanes per output
+  constexpr int UMAX = NGL_MAX_HIDDEN / 64;
+  __shared__ float zsh[kBlock / 64][M];
+  __shared__ float gash[kBlock / 64][NGL_MAX_HIDDEN];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t p = int64_t(blockIdx.x) * (kBlock / 64) + w;
+  const int64_t P = A.P;
+  if (p >= P) return;  // wave-uniform: no block-wide barrier below
+  const int64_t id = A.sidx[p];
+  const float x[3] = {A.xs[id], A.xs[P + id], A.xs[2 * P + id]};
+  const int Lm = md.num_lods;
+  const int H = md.hidden;
+  int vox[NGL_MAX_LODS];
+  int cx = 0, cy = 0, cz = 0;
+  if (in_box(x[0], x[1], x[2])) {
+    const int r = 1 << (Lm + 1);
+    cx = cell_of(x[0], r);
+    cy = cell_of(x[1], r);
+    cz = cell_of(x[2], r);
+    descend<NGL_MAX_LODS>(md, cx, cy, cz, Lm + 1, vox);
+  } else {
+#pragma unroll
+    for (int l = 0; l < NGL_MAX_LODS; ++l) vox[l] = -1;
+  }
+  const float tgt = TRAIN ? A.target[id] : 0.0f;
+  const int j = lane >> 3, sl = lane & 7;        // gather: corner, slice
+  const int oi = lane % M, part = lane / M;      // adjoint: output, part
+  float zl[FE];                                  // this lane's slice of z_L
+#pragma unroll
+  for (int e = 0; e < FE; ++e) zl[e] = 0.0f;
+  float dzl[NGL_MAX_LODS];                       // dz_L[oi] (part 0 lanes)
+  float lossacc = 0.0f;
+#pragma unroll
+  for (int l = 1; l <= NGL_MAX_LODS; ++l) {
+    dzl[l - 1] = 0.0f;
+    if (l > Lm) continue;
+    const int s = Lm - l;
+    // psi_l: corner j's slice weighted, summed over the 8 corners
+    if (vox[l - 1] >= 0) {
+      float u[3];
+      cell_local(l, cx >> s, cy >> s, cz >> s, x, u);
+      const int c = md.corners[l - 1][int64_t(vox[l - 1]) * 8 + j];
+      const float wj = corner_weight(u, j);
+      const float* row = static_cast<const float*>(md.feat[l - 1]) + int64_t(c) * M + sl * FE;
+      float t[FE];
+#pragma unroll
+      for (int e = 0; e < FE; ++e) t[e] = wj * row[e];
+#pragma unroll
+      for (int off = 8; off < 64; off <<= 1)
+#pragma unroll
+        for (int e = 0; e < FE; ++e) t[e] += __shfl_xor(t[e], off, 64);
+#pragma unroll
+      for (int e = 0; e < FE; ++e) zl[e] += t[e];
+    }
+    if (lane == 0) A.vox_s[int64_t(l - 1) * P + p] = vox[l - 1];
+    if (lane < 8) {
+#pragma unroll
+      for (int e = 0; e < FE; ++e) zsh[w][sl * FE + e] = zl[e];
+    }
+    wave_sync_lds();
+    float z[M];
+#pragma unroll
+    for (int q = 0; q < M; ++q) z[q] = zsh[w][q];
+    if (lane < M) A.zrows[(int64_t(l - 1) * P + p) * M + lane] = zsh[w][lane];
+    // decoder L = l, units k = lane + 64 u
+    const float* W1 = static_cast<const float*>(md.W1[l - 1]);
+    const float* b1 = md.b1[l - 1];
+    const float* w2 = md.w2[l - 1];
+    float part_out = 0.0f;
+    float ga[UMAX];
+#pragma unroll
+    for (int uu = 0; uu < UMAX; ++uu) {
+      ga[uu] = 0.0f;
+      const int k = lane + 64 * uu;
+      if (k < H) {
+        const float* rw = W1 + k * DIN;
+        float a = b1[k];
+        if constexpr (XYZ) {
+          a = fmaf(rw[0], x[0], a);
+          a = fmaf(rw[1], x[1], a);
+          a = fmaf(rw[2], x[2], a);
+        }
+#pragma unroll
+        for (int i = 0; i < M; ++i) a = fmaf(rw[OFF + i], z[i], a);
+        part_out = fmaf(w2[k], fmaxf(a, 0.0f), part_out);
+        ga[uu] = a > 0.0f ? w2[k] : 0.0f;  // times g below
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) part_out += __shfl_xor(part_out, off, 64);
+    const float out = md.b2[l - 1] + part_out;
+    float g;
+    if constexpr (TRAIN) {
+      const float wres = A.lod_w[l - 1] * (out - tgt);
+      lossacc = fmaf(wres, out - tgt, lossacc);
+      g = 2.0f * wres * A.inv_p;
+    } else {
+      g = A.grad[int64_t(l - 1) * P + id];
+    }
+    if (lane == 0) {
+      if (A.sdf_all) A.sdf_all[int64_t(l - 1) * P + id] = out;
+      A.gs[int64_t(l - 1) * P + p] = g;
+    }
+    // dz = W1_z^T (g w2 . 1[a > 0]): ga to LDS, lane (oi, part) sums units
+    // part, part + KP, ...
+#pragma unroll
+    for (int uu = 0; uu < UMAX; ++uu) {
+      const int k = lane + 64 * uu;
+      if (k < H) gash[w][k] = g * ga[uu];
+    }
+    wave_sync_lds();
+    float d = 0.0f;
+    for (int k = part; k < H; k += KP) d = fmaf(W1[k * DIN + OFF + oi], gash[w][k], d);
+#pragma unroll
+    for (int off = M; off < 64; off <<= 1) d += __shfl_xor(d, off, 64);
+    dzl[l - 1] = d;
+    wave_sync_lds();  // zsh and gash are rewritten by the next level
+  }
+  // dpsi_l = sum_{L >= l} dz_L, from the finest level down
+  if (lane < M) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int l = NGL_MAX_LODS; l >= 1; --l) {
+      if (l > Lm) continue;
+      acc = l == Lm ? dzl[l - 1] : acc + dzl[l - 1];
+      A.drows[(int64_t(l - 1) * P + p) * M + lane] = acc;
+    }
+  }
+  if constexpr (TRAIN) {
+    if (lane == 0) A.loss_part[p] = lossacc;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_loss_reduce(const float* __restrict__ part, int n, float inv_p,
                                                         float* __restrict__ loss) {
   __shared__ float sp[kBlock];
@@ -393,11 +549,14 @@ __global__ __launch_bounds__(64) void k_rec_count(LevelArgs A) {
   if (threadIdx.x == 0) A.rec_cnt[blockIdx.x] = uint32_t(__popcll(heads));
 }
 
-template <int M>
+// STAGE (small batches, few tiles in flight): the tile's dpsi rows are
+// loaded into LDS together before the sequential pass.
+template <int M, bool STAGE>
 __global__ __launch_bounds__(64) void k_rec_write(ngl_model md, LevelArgs A) {
   __shared__ float w_s[kTile][8];
   __shared__ int32_t v_s[kTile];
   __shared__ uint32_t r_s[kTile];
+  __shared__ float d_s[STAGE ? kTile * M : 1];
   const int lane = threadIdx.x;
   const int64_t p = int64_t(blockIdx.x) * kTile + lane;
   const int lvl = A.lvl;
@@ -429,6 +588,15 @@ __global__ __launch_bounds__(64) void k_rec_write(ngl_model md, LevelArgs A) {
   for (int j = 0; j < 8; ++j) w_s[lane][j] = wj[j];
   v_s[lane] = v;
   r_s[lane] = rec;
+  const int n = int(A.P - int64_t(blockIdx.x) * kTile < kTile ? A.P - int64_t(blockIdx.x) * kTile : kTile);
+  if constexpr (STAGE) {
+    const float* src = A.drows + int64_t(blockIdx.x) * kTile * M;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+      const int e = lane + 64 * q;
+      if (e < n * M) d_s[e] = src[e];
+    }
+  }
   __syncthreads();
   // phase B, lane = (channel, slot group): sequential over the tile's points
   constexpr int SG = 64 / M;      // slot groups
@@ -438,11 +606,10 @@ __global__ __launch_bounds__(64) void k_rec_write(ngl_model md, LevelArgs A) {
   float acc[SPL];
 #pragma unroll
   for (int s = 0; s < SPL; ++s) acc[s] = 0.0f;
-  const int n = int(A.P - int64_t(blockIdx.x) * kTile < kTile ? A.P - int64_t(blockIdx.x) * kTile : kTile);
   for (int i = 0; i < n; ++i) {
     const int32_t vi = v_s[i];
     if (vi < 0) continue;
-    const float row = A.drows[(int64_t(blockIdx.x) * kTile + i) * M + ch];
+    const float row = STAGE ? d_s[i * M + ch] : A.drows[(int64_t(blockIdx.x) * kTile + i) * M + ch];
 #pragma unroll
     for (int s = 0; s < SPL; ++s) acc[s] = fmaf(w_s[i][sg * SPL + s], row, acc[s]);
     if (i == n - 1 || v_s[i + 1] != vi) {
@@ -575,7 +742,7 @@ static TrainWS carve(const ngl_model& m, int64_t P, void* base) {
   w.drows = reinterpret_cast<float*>(take(4 * size_t(L) * size_t(P) * size_t(M)));
   w.gs = reinterpret_cast<float*>(take(4 * size_t(L) * size_t(P)));
   w.vox_s = reinterpret_cast<int32_t*>(take(4 * size_t(L) * size_t(P)));
-  w.loss_part = reinterpret_cast<float*>(take(4 * size_t((P + kBlock - 1) / kBlock + 1)));
+  w.loss_part = reinterpret_cast<float*>(take(4 * size_t(P < kPointWaveMax ? P + 1 : (P + kBlock - 1) / kBlock + 1)));
   w.dec_part = reinterpret_cast<float*>(take(4 * size_t(L) * kDecGrid * PH * size_t(H) * size_t(din + 2)));
   w.dec_b2 = reinterpret_cast<float*>(take(4 * size_t(L) * kDecGrid));
   w.rec_cnt = reinterpret_cast<uint32_t*>(take(4 * size_t(w.ntiles + 1)));
@@ -636,7 +803,16 @@ static int run_train(const ngl_model& md, const float* x, const float* target, c
   A.gs = w.gs;
   A.vox_s = w.vox_s;
   A.loss_part = w.loss_part;
-  if (target) {
+  if (P < kPointWaveMax) {
+    // small batches: one wavefront per point
+    const unsigned wgrid = unsigned((P + kBlock / 64 - 1) / (kBlock / 64));
+    if (target) {
+      k_point_wave<M, XYZ, true><<<wgrid, kBlock, 0, s>>>(md, A);
+      if (loss) k_loss_reduce<<<1, kBlock, 0, s>>>(w.loss_part, int(P), 1.0f / float(P), loss);
+    } else {
+      k_point_wave<M, XYZ, false><<<wgrid, kBlock, 0, s>>>(md, A);
+    }
+  } else if (target) {
     k_point<M, XYZ, true><<<pgrid, kBlock, 0, s>>>(md, A);
     if (loss) k_loss_reduce<<<1, kBlock, 0, s>>>(w.loss_part, int(pgrid), 1.0f / float(P), loss);
   } else {
@@ -678,7 +854,8 @@ static int run_train(const ngl_model& md, const float* x, const float* target, c
     C.vpart = w.vpart;
     k_rec_count<<<unsigned(w.ntiles), 64, 0, s>>>(C);
     k_scan_inplace<<<1, 1024, 0, s>>>(w.rec_cnt, w.ntiles, w.rec_total);
-    k_rec_write<M><<<unsigned(w.ntiles), 64, 0, s>>>(md, C);
+    if (P < kPointWaveMax) k_rec_write<M, true><<<unsigned(w.ntiles), 64, 0, s>>>(md, C);
+    else k_rec_write<M, false><<<unsigned(w.ntiles), 64, 0, s>>>(md, C);
     k_vox_reduce<M><<<unsigned(nv), 64, 0, s>>>(C, nv);
     k_corner<M><<<unsigned((nc * M + kBlock - 1) / kBlock), kBlock, 0, s>>>(md.corner_adj_off[l - 1],
                                                                             md.corner_adj[l - 1], w.vpart, nc,
