@@ -577,20 +577,76 @@ struct TileShape {
   static constexpr int D = M / 4;  // feature elements per lane
 };
 
+// Level 1 (resolution 4, at most 5^3 corners) can be staged in LDS by the
+// block: its corner rows are then read through the LDS, off the vector
+// memory path that the other levels' rows load through.  Used with FP32
+// features (measured slower with 16-bit features: l1_bytes is 0 for them).
+constexpr int kL1MaxCorners = 125;
+template <int M, typename FT>
+constexpr size_t l1_bytes() {
+  return std::is_same<FT, F32>::value ? size_t(kL1MaxCorners) * M * 4 : 0;
+}
+// Whole block; the caller synchronises before use.  Needs ncorner[0] <=
+// kL1MaxCorners (l1_fits).
+template <int M, typename FT>
+__device__ inline void stage_l1(const ngl_model& md, void* dst) {
+  const int n = int(md.ncorner[0] * int64_t(M) * (std::is_same<FT, F32>::value ? 4 : 2) / 16);
+  const uint4* src = static_cast<const uint4*>(md.feat[0]);
+  uint4* d = static_cast<uint4*>(dst);
+  for (int e = threadIdx.x; e < n; e += blockDim.x) d[e] = src[e];
+}
+inline bool l1_fits(const ngl_model& md) { return md.ncorner[0] <= kL1MaxCorners && md.nvox[2] > 0; }
+
+// load_slice from the LDS copy (read as LDS, not through a generic address).
+template <int M, typename FT, int D>
+__device__ __forceinline__ void load_slice_lds(const void* base, int c, int off, float* v) {
+  typedef const __attribute__((address_space(3))) char* lptr;
+  constexpr int ES = std::is_same<FT, F32>::value ? 4 : 2;
+  constexpr int BYTES = D * ES;  // 4 to 32, a power of two
+  constexpr int W = BYTES >= 16 ? 4 : BYTES / 4;  // 32-bit words per load
+  constexpr int NL = BYTES >= 16 ? BYTES / 16 : 1;
+  typedef uint32_t uvw __attribute__((ext_vector_type(W)));
+  const lptr r = (lptr)(base) + uint32_t(c) * uint32_t(M * ES) + uint32_t(off * ES);
+  uint32_t wv[NL * W];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const uvw f = *(const __attribute__((address_space(3))) uvw*)(r + 16 * q);
+#pragma unroll
+    for (int e = 0; e < W; ++e) wv[q * W + e] = f[e];
+  }
+  if constexpr (std::is_same<FT, F32>::value) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) v[i] = __uint_as_float(wv[i]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < D / 2; ++e) {
+      const uint32_t lo = wv[e] & 0xffffu, hi = wv[e] >> 16;
+      v[2 * e] = std::is_same<FT, BF16>::value ? bf16_to_f32(lo) : f16_to_f32(lo);
+      v[2 * e + 1] = std::is_same<FT, BF16>::value ? bf16_to_f32(hi) : f16_to_f32(hi);
+    }
+  }
+}
+
 // One level for this lane's group: voxel vq, cell (qx, qy, qz) at level l
 // and position xq of the group's point; the slice of each corner row is
 // accumulated in the order of interp_level.  A point without a voxel at the
-// level (vq < 0) loads voxel 0's rows and keeps its accumulator.
+// level (vq < 0) loads voxel 0's rows and keeps its accumulator.  With l1
+// (wave-uniform), level 1's rows come from l1s, the LDS copy of stage_l1.
 template <int M, typename FT>
 __device__ __forceinline__ void tile_level(const ngl_model& md, int l, int vq, const float xq[3], int qx, int qy,
-                                           int qz, int g, float* acc) {
+                                           int qz, int g, float* acc, const void* l1s = nullptr, bool l1 = false) {
   constexpr int D = TileShape<M>::D;
   const int4* cp = reinterpret_cast<const int4*>(md.corners[l - 1] + size_t(vq >= 0 ? vq : 0) * 8);
   const int4 c0 = cp[0], c1 = cp[1];
   const int cs[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
   float fv[8][D];
+  if (l1_bytes<M, FT>() > 0 && l == 1 && l1) {
 #pragma unroll
-  for (int j = 0; j < 8; ++j) load_slice<M, FT, D>(md.feat[l - 1], cs[j], g * D, fv[j]);
+    for (int j = 0; j < 8; ++j) load_slice_lds<M, FT, D>(l1s, cs[j], g * D, fv[j]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) load_slice<M, FT, D>(md.feat[l - 1], cs[j], g * D, fv[j]);
+  }
   float u[3];
   cell_local(l, qx, qy, qz, xq, u);
   float t[D];

@@ -176,7 +176,8 @@ __global__ __launch_bounds__(64 * NW) void k_query_mfma(ngl_model md, const floa
 template <int M, typename FT, class DEC>
 __device__ __forceinline__ float coop_eval(const ngl_model& md, const DecLds<DEC>& S, const float x[3],
                                            const int* vox, int cx, int cy, int cz, int vn, bool act, int lod, int Lp,
-                                           bool blend, float a, float b2a, float b2b) {
+                                           bool blend, float a, float b2a, float b2b, const void* l1s = nullptr,
+                                           bool l1 = false) {
   const uint64_t live = __ballot(act);  // tiles without an active point are skipped
   constexpr int D = TileShape<M>::D;
   const int lane = threadIdx.x & 63, r = lane >> 2, g = lane & 3;
@@ -198,7 +199,8 @@ __device__ __forceinline__ float coop_eval(const ngl_model& md, const DecLds<DEC
     for (int l = 1; l <= NGL_MAX_LODS; ++l)
       if (l <= lod && md.nvox[l + 1] > 0) {
         const int sh = Lp - l;
-        tile_level<M, FT>(md, l, __shfl(act ? vox[l - 1] : -1, q, 64), xq, qx >> sh, qy >> sh, qz >> sh, g, acc);
+        tile_level<M, FT>(md, l, __shfl(act ? vox[l - 1] : -1, q, 64), xq, qx >> sh, qy >> sh, qz >> sh, g, acc,
+                          l1s, l1);
       }
     DEC::template tile_slice<D>(rows, r, g * D, acc);
     if (g == 0) DEC::tile_rest(rows, r, xq);
@@ -224,13 +226,16 @@ template <int M, typename FT, bool XYZ, int NW, class DEC>
 __global__ __launch_bounds__(64 * NW) void k_query_coop(ngl_model md, const float* __restrict__ xs, int64_t P,
                                                         int lod, float alpha, const float* __restrict__ alpha_pp,
                                                         float* __restrict__ sdf, uint8_t* __restrict__ valid,
-                                                        int32_t* __restrict__ vox_out) {
+                                                        int32_t* __restrict__ vox_out, bool l1) {
   extern __shared__ __align__(16) char smem[];
   const int H = md.hidden;
   const bool blend = alpha_pp != nullptr || alpha > 0.0f;
   DecLds<DEC> S(smem, H, blend, DEC::TILE_ELEMS);
+  // level 1's table after the staging rows (when the launch reserved it)
+  char* l1s = smem + DecLds<DEC>::fixed_bytes(H, blend) + NW * size_t(DEC::TILE_BYTES);
   DEC::load(md, lod, S.frag0, S.w2s0);
   if (blend) DEC::load(md, lod + 1, S.frag1, S.w2s1);
+  if (l1) stage_l1<M, FT>(md, l1s);
   __syncthreads();
   const float b2a = md.b2[lod - 1];
   const float b2b = blend ? md.b2[lod] : 0.0f;
@@ -253,7 +258,8 @@ __global__ __launch_bounds__(64 * NW) void k_query_coop(ngl_model md, const floa
       vlast = vn = -1;
     }
     const float a = act ? (alpha_pp ? alpha_pp[p] : alpha) : 0.0f;
-    const float out = coop_eval<M, FT, DEC>(md, S, x, vox, cx, cy, cz, vn, act, lod, Lp, blend, a, b2a, b2b);
+    const float out = coop_eval<M, FT, DEC>(md, S, x, vox, cx, cy, cz, vn, act, lod, Lp, blend, a, b2a, b2b, l1s,
+                                            l1);
     if (act) {
       sdf[p] = out;
       if (valid) valid[p] = vlast >= 0 ? 1 : 0;
@@ -277,10 +283,14 @@ static int launch_query_coop_nw(const ngl_model& md, const float* x, int64_t P, 
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 256;
+  // level 1's rows in LDS when the table fits beside the decoder
+  const bool l1 = l1_bytes<M, FT>() > 0 && l1_fits(md) && lds + l1_bytes<M, FT>() <= 65536;
+  if (l1) lds += l1_bytes<M, FT>();
   int64_t grid = (P + 64 * NW - 1) / (64 * NW);
   const int64_t cap = bpc > 0 ? int64_t(cus) * bpc : resident_grid(kern, 64 * NW, lds, 0);
   if (grid > cap) grid = cap;
-  k_query_coop<M, FT, XYZ, NW, DEC><<<unsigned(grid), 64 * NW, lds, s>>>(md, x, P, lod, alpha, app, sdf, valid, vox);
+  k_query_coop<M, FT, XYZ, NW, DEC><<<unsigned(grid), 64 * NW, lds, s>>>(md, x, P, lod, alpha, app, sdf, valid, vox,
+                                                                          l1);
   NGL_LAUNCHED();
   return NGL_OK;
 }
@@ -339,6 +349,7 @@ struct NormalArgs {
   float alpha;
   float h;
   float* normals;       // [3][P]
+  bool l1;              // level 1's table staged in LDS (k_normals_coop)
 };
 
 template <int M, typename FT, bool XYZ>
@@ -459,8 +470,10 @@ __global__ __launch_bounds__(64 * NW) void k_normals_coop(ngl_model md, NormalAr
   const bool blend = A.alpha > 0.0f;
   const int Lp = blend ? lod + 1 : lod;
   DecLds<DEC> S(smem, H, blend, DEC::TILE_ELEMS);
+  char* l1s = smem + DecLds<DEC>::fixed_bytes(H, blend) + NW * size_t(DEC::TILE_BYTES);
   DEC::load(md, lod, S.frag0, S.w2s0);
   if (blend) DEC::load(md, lod + 1, S.frag1, S.w2s1);
+  if (A.l1) stage_l1<M, FT>(md, l1s);
   if (threadIdx.x == 0) qn = 0;
   __syncthreads();
   const float b2a = md.b2[lod - 1];
@@ -523,7 +536,8 @@ __global__ __launch_bounds__(64 * NW) void k_normals_coop(ngl_model md, NormalAr
         for (int l = 0; l < NGL_MAX_LODS; ++l) vox[l] = -1;
         vn = -1;
       }
-      const float f = coop_eval<M, FT, DEC>(md, S, x, vox, cx, cy, cz, vn, act, lod, Lp, blend, A.alpha, b2a, b2b);
+      const float f = coop_eval<M, FT, DEC>(md, S, x, vox, cx, cy, cz, vn, act, lod, Lp, blend, A.alpha, b2a, b2b,
+                                            l1s, A.l1);
       g[a] += sgn * f;
     }
     if (act) {
@@ -569,12 +583,15 @@ static int launch_normals(const ngl_model& md, const NormalArgs& A, hipStream_t 
     return launch_normals_nw<M, FT, XYZ, DEC, false, 2>(md, A, s, 0);
   } else {
     constexpr int NW = 4;
-    const size_t lds = DecLds<DEC>::fixed_bytes(md.hidden, blend) + NW * size_t(DEC::TILE_BYTES);
+    size_t lds = DecLds<DEC>::fixed_bytes(md.hidden, blend) + NW * size_t(DEC::TILE_BYTES);
+    NormalArgs B = A;
+    B.l1 = l1_bytes<M, FT>() > 0 && l1_fits(md) && lds + l1_bytes<M, FT>() <= 65536;
+    if (B.l1) lds += l1_bytes<M, FT>();
     const void* kern = reinterpret_cast<const void*>(&k_normals_coop<M, FT, XYZ, NW, DEC>);
     int64_t grid = (A.P + 64 * NW - 1) / (64 * NW);
     const int64_t cap = resident_grid(kern, 64 * NW, lds, 0);
     if (grid > cap) grid = cap;
-    k_normals_coop<M, FT, XYZ, NW, DEC><<<unsigned(grid), 64 * NW, lds, s>>>(md, A);
+    k_normals_coop<M, FT, XYZ, NW, DEC><<<unsigned(grid), 64 * NW, lds, s>>>(md, B);
     NGL_LAUNCHED();
     return NGL_OK;
   }

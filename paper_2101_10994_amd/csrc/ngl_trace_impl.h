@@ -50,6 +50,7 @@ struct TraceArgs {
   int32_t* parked;
   unsigned int* parked_n;
   bool wide;  // host side: serve the queue with the wide (lanes-per-ray) kernel
+  bool l1;    // level 1's table staged in LDS (k_sphere_trace, set by its launcher)
 };
 
 // The launch evaluates decoders lod and lod+1.
@@ -151,7 +152,8 @@ constexpr int trace_stage_bytes() {
 // so the loop ends.  All lanes of the wavefront reach the matrix-core decode
 // together (idle lanes stage zeros).
 template <int M, typename FT, bool XYZ, bool ANALYTIC, bool MFMA, class DEC>
-__device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLds<DEC>& S, float b2a, float b2b) {
+__device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs& A, const DecLds<DEC>& S, float b2a,
+                                            float b2b, const void* l1s = nullptr, bool l1 = false) {
   const int lane = threadIdx.x & 63;
   const bool blend = trace_blend(A);
   const int lod = A.lod;
@@ -339,7 +341,7 @@ __device__ __forceinline__ void serve_queue(const ngl_model& md, const TraceArgs
                 if (l <= lod) {
                   const uint32_t cq = cell_at(cq_lc, Lc, l);
                   tile_level<M, FT>(md, l, __shfl(ok ? vox[l - 1] : -1, q, 64), xq, cell_x(cq), cell_y(cq), cell_z(cq),
-                                    g, acc);
+                                    g, acc, l1s, l1);
                 }
               DEC::template tile_slice<D>(rows, r, g * D, acc);
               if (g == 0) DEC::tile_rest(rows, r, xq);
@@ -430,15 +432,18 @@ void k_sphere_trace(ngl_model md, TraceArgs A) {
   const bool blend = trace_blend(A);
   const int H = md.hidden;
   DecLds<DEC> S(smem, H, blend && MFMA, trace_stage_bytes<FT, ANALYTIC, MFMA, DEC>() / 4);
+  // level 1's table after the staging rows (when the launch reserved it)
+  char* l1s = smem + DecLds<DEC>::fixed_bytes(H, blend && MFMA) + NW * size_t(trace_stage_bytes<FT, ANALYTIC, MFMA, DEC>());
   float b2a = 0.0f, b2b = 0.0f;
   if constexpr (MFMA) {
     DEC::load(md, A.lod, S.frag0, S.w2s0);
     if (blend) DEC::load(md, A.lod + 1, S.frag1, S.w2s1);
+    if (A.l1) stage_l1<M, FT>(md, l1s);
     __syncthreads();
     b2a = md.b2[A.lod - 1];
     b2b = blend ? md.b2[A.lod] : 0.0f;
   }
-  serve_queue<M, FT, XYZ, ANALYTIC, MFMA, DEC>(md, A, S, b2a, b2b);
+  serve_queue<M, FT, XYZ, ANALYTIC, MFMA, DEC>(md, A, S, b2a, b2b, l1s, A.l1);
 }
 
 // Lanes per ray of the wide tracer (a divisor of the feature width M).
@@ -998,11 +1003,20 @@ static int launch_trace_mfma(const ngl_model& md, const TraceArgs& A, hipStream_
   const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, trace_blend(A));
   const int want = option(NGL_OPT_TRACE_WAVES);
   constexpr size_t SB = trace_stage_bytes<FT, false, true, DEC>();
+  // level 1's rows in LDS (cooperative gather) when the table fits beside the decoder
+  constexpr size_t L1B = trace_coop<FT, false, true>() ? l1_bytes<M, FT>() : 0;
+  TraceArgs B = A;
+  auto go = [&](int nw, auto launch) {
+    size_t lds = fixed + nw * SB;
+    B.l1 = L1B > 0 && l1_fits(md) && lds + L1B <= 65536;
+    if (B.l1) lds += L1B;
+    return launch(lds);
+  };
   if ((want == 0 || want >= 4) && fixed + 4 * SB <= 65536)
-    return launch_trace_nw<M, FT, XYZ, false, true, 4, DEC>(md, A, s, fixed + 4 * SB);
+    return go(4, [&](size_t lds) { return launch_trace_nw<M, FT, XYZ, false, true, 4, DEC>(md, B, s, lds); });
   if ((want == 0 || want >= 2) && fixed + 2 * SB <= 65536)
-    return launch_trace_nw<M, FT, XYZ, false, true, 2, DEC>(md, A, s, fixed + 2 * SB);
-  return launch_trace_nw<M, FT, XYZ, false, true, 1, DEC>(md, A, s, fixed + SB);
+    return go(2, [&](size_t lds) { return launch_trace_nw<M, FT, XYZ, false, true, 2, DEC>(md, B, s, lds); });
+  return go(1, [&](size_t lds) { return launch_trace_nw<M, FT, XYZ, false, true, 1, DEC>(md, B, s, lds); });
 }
 
 template <int M, typename FT, bool XYZ, bool ANALYTIC>
