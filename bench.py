@@ -53,19 +53,19 @@ TRAVERSAL_BYTES = 16
 COUNTERS = {
     # both launches of the phased FP32 trace (first 24 evaluations, then the wide kernel)
     "k_sphere_trace": {"sources": ["ngl_trace_impl.h", "ngl_device.h", "ngl_mfma.h"],
-                       "sha256": "a58ebe4e45f1827b11545b3e9c0b553759d61be8f26085741455c77cf73e294f",
-                       "fetch_kib": 317654.2 + 22781.2, "write_kib": 33583.1 + 3481.4},
+                       "sha256": "f3eea318163c0b52781a9996e82e8ca1242b8c3f5a5dbe11ab5de26d506966ef",
+                       "fetch_kib": 315489.8 + 22951.6, "write_kib": 33466.1 + 3499.2},
     # every launch of one traversal to depth 6 (root and six child passes,
     # ray inverses, segment offsets)
     "traverse": {"sources": ["ngl_traverse.hip", "ngl_device.h"],
                  "sha256": "d1c4196cc585dd988bfdc7542ad8170f78014f558a7bdd22b721f7c9ab6091b1",
-                 "fetch_kib": 347790.0, "write_kib": 380745.0},
+                 "fetch_kib": 347901.8, "write_kib": 380743.9},
     # k_query_coop, FP32 features and matrix-core decoder
     "k_query": {"sources": ["ngl_query_impl.h", "ngl_device.h", "ngl_mfma.h"],
-                "sha256": "92db70ae7d26195fdf4ad207264c04a5f21e847981bce0751da9611dcc62a3ff",
-                "fetch_kib": 105941.0, "write_kib": 4096.0},
+                "sha256": "e5a08bc0f3e8718179c083885def3b666023362acd64a95eb77e60007dd3ac49",
+                "fetch_kib": 105024.9, "write_kib": 4096.0},
 }
-FETCH_SCALE = (256 << 10) / 131087.8
+FETCH_SCALE = (256 << 10) / 131088.1
 WRITE_SCALE = (256 << 10) / 262144.0
 
 

@@ -188,8 +188,8 @@ typedef struct {
   const uint8_t* child_mask[NGL_MAX_DEPTH];  /* device, depths 0..L */
   const int32_t* first_child[NGL_MAX_DEPTH]; /* device, depths 0..L */
   const int32_t* parent[NGL_MAX_DEPTH];      /* device, depths 1..L+1 */
-  const int32_t* corners[NGL_MAX_LODS];      /* device, [nvox[l+1]][8] */
-  const void* feat[NGL_MAX_LODS];            /* device, [ncorner[l-1]][m], feat_dtype; below 4 GiB per level */
+  const int32_t* corners[NGL_MAX_LODS];      /* device, [nvox[l+1]][8], 16-byte aligned */
+  const void* feat[NGL_MAX_LODS];            /* device, [ncorner[l-1]][m], feat_dtype; 16-byte aligned, below 4 GiB per level */
   const void* W1[NGL_MAX_LODS];              /* device, [h][din] row-major, w_dtype */
   const float* b1[NGL_MAX_LODS];             /* device, [h] */
   const float* w2[NGL_MAX_LODS];             /* device, [h] */

@@ -79,6 +79,9 @@ int check_model(const ngl_model* m, bool need_features) {
       NGL_REQUIRE(m->corners[l - 1] && m->feat[l - 1], "corner table or features of level %d are null", l);
     const uint64_t row = uint64_t(m->feat_dim) * (m->feat_dtype == NGL_F32 ? 4u : 2u);
     NGL_REQUIRE(uint64_t(m->ncorner[l - 1]) * row < (uint64_t(1) << 32), "features of level %d exceed 4 GiB", l);
+    NGL_REQUIRE((reinterpret_cast<uintptr_t>(m->feat[l - 1]) & 15u) == 0 &&
+                    (reinterpret_cast<uintptr_t>(m->corners[l - 1]) & 15u) == 0,
+                "features and corner table of level %d must be 16-byte aligned", l);
     NGL_REQUIRE(m->W1[l - 1] && m->b1[l - 1] && m->w2[l - 1], "decoder %d is null", l);
   }
   return NGL_OK;
