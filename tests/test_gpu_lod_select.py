@@ -11,6 +11,7 @@ import oracle
 from paper_2101_10994_amd import workloads as W
 
 from cases import make_case, paper_case, tiny_case
+from tracecmp import report, summary
 
 pytestmark = pytest.mark.gpu
 
@@ -68,7 +69,9 @@ def test_tiny_embedded_model_hits(f32_decoder):
 def test_paper_scale_lod_select():
     case = paper_case(embedded=True)
     g, r = run_both(case, W.PAPER.eye, 160, 128, (1.6, 3.2, 5.0, 2.0), 6, 100, 1e-4)
-    assert check(g, r, 2 / 64, max_marginal=0.03) > 5000
+    nhit = check(g, r, 2 / 64, max_marginal=0.03)
+    report("lod_select_paper_160x128", summary(g, r, 2 / 64))
+    assert nhit > 5000
 
 
 def test_bf16_decoder_lod_select():

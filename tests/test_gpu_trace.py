@@ -47,7 +47,7 @@ def test_paper_scale_embedded_sampled(f32_decoder):
     # ~10 steps per ray across 1/32-wide voxels: about 1-2% of rays have a
     # step within 1e-5 of a voxel bound
     nhit, nmarg = check(g, r, 2 / 64, max_marginal=0.03)
-    print("paper-scale trace: %d common hits, %d marginal of %d rays" % (nhit, nmarg, len(idx)))
+    report("trace_paper_embedded_f32_%s" % ["valu", "mfma"][f32_decoder], summary(g, r, 2 / 64))
     assert nhit > 10000
 
 
@@ -107,7 +107,7 @@ def test_bf16_decoder_embedded_trace():
     idx = np.random.default_rng(3).choice(1024 * 1024, 16384, replace=False)
     g, r = trace_both(case, W.PAPER.eye, 1024, 1024, 5, 0.0, 100, 1e-4, sample=idx)
     nhit, nmarg = check(g, r, 2 / 64, max_marginal=0.03)
-    print("bf16 paper-scale trace: %d common hits, %d marginal of %d rays" % (nhit, nmarg, len(idx)))
+    report("trace_paper_embedded_bf16_lod5", summary(g, r, 2 / 64))
 
 
 PHASE_CASES = {
