@@ -161,7 +161,7 @@ def main():
                     help="skip the decoder-alone, LOD-selection, fitting and octree-build components")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, run one plain 256 MiB device copy (counter calibration)")
-    ap.add_argument("--only", choices=["query", "frame", "train", "half", "decoder", "precision", "fit"], default=None,
+    ap.add_argument("--only", choices=["query", "frame", "train", "half", "decoder", "precision", "fit", "batch"], default=None,
                     help="run a single component (profiling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -392,7 +392,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.only is None and not args.no_batch:
+    if args.only == "batch" or (args.only is None and not args.no_batch):
         comp["batch"] = run_batch(dev, args.steps, args.warmup)
     if args.only == "decoder" or (args.only is None and not args.no_extras):
         comp["decoder_bf16"] = run_decoder(S, dev, args.steps, args.warmup)
@@ -668,6 +668,7 @@ def run_batch(dev, steps, warmup):
         br.render(cfg.max_steps, cfg.delta)
         torch.cuda.synchronize()
     log("batch setup %.1fs, pair capacity %d" % (setup_s, cap))
+    untuned = autotune.current()
     tuned = autotune.tune("batch16x512-f16-bf16", lambda: br.render(cfg.max_steps, cfg.delta), fp32_model=False,
                           repeats=3, use_cache=False)
     log("autotuned batch launch: %s (%.3f ms)" % (tuned["config"], tuned["ms"]))
@@ -701,7 +702,7 @@ def run_batch(dev, steps, warmup):
            "visible_px": int((status == ngl.HIT).sum()), "sdf_evals": int(steps_arr.sum()),
            "graph": True, "tuned": tuned["config"], "tuned_ms": tuned["ms"],
            "untuned_ms": tuned.get("default_ms"), "setup_s": setup_s}
-    autotune.apply({"waves": 0, "blocks_per_cu": 0, "f32_decoder": 1})
+    autotune.apply(untuned)
     return out
 
 

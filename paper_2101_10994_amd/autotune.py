@@ -5,6 +5,10 @@ persistent tracers are launched, never what they compute:
   * NGL_OPT_TRACE_WAVES          wavefronts per block (4, 2, 1);
   * NGL_OPT_TRACE_BLOCKS_PER_CU  resident blocks per compute unit (0 = the
                                  occupancy limit, or a smaller cap);
+  * NGL_OPT_TRACE_PAUSE1         evaluation count at which the phased tracer
+                                 parks the rays still running and finishes
+                                 them with a group of lanes per ray (24, 12,
+                                 48; 0 = one phase);
   * NGL_OPT_F32_DECODER          FP32 decoder on the vector ALUs or the matrix
                                  cores (FP32 models only).
 Each candidate is timed with HIP events on the current stream (median of a
@@ -23,7 +27,7 @@ import torch
 from . import ngl
 
 _KEYS = {"waves": ngl.OPT_TRACE_WAVES, "blocks_per_cu": ngl.OPT_TRACE_BLOCKS_PER_CU,
-         "f32_decoder": ngl.OPT_F32_DECODER}
+         "pause": ngl.OPT_TRACE_PAUSE1, "f32_decoder": ngl.OPT_F32_DECODER}
 
 
 def cache_path() -> str:
@@ -41,8 +45,8 @@ def apply(config: Dict[str, int]) -> None:
 
 def candidates(fp32_model: bool) -> Iterable[Dict[str, int]]:
     dec = (1, 0) if fp32_model else (1,)
-    for w, b, f in itertools.product((0, 2, 1), (0, 4, 2), dec):
-        yield {"waves": w, "blocks_per_cu": b, "f32_decoder": f}
+    for w, b, p, f in itertools.product((0, 2, 1), (0, 4, 2), (24, 12, 48, 0), dec):
+        yield {"waves": w, "blocks_per_cu": b, "pause": p, "f32_decoder": f}
 
 
 def time_ms(fn: Callable[[], None], repeats: int = 3) -> float:

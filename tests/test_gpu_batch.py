@@ -148,16 +148,22 @@ def test_autotuner_applies_a_valid_config(tmp_path):
     views = [ngl.make_view((0.3, 0.2, 2.6), 64, 64, c.L) for c in cases]
     br = ngl.BatchRenderer(models, views, pair_capacity=1 << 18)
     saved = autotune.current()
+    br.render(40, 1e-4)
+    torch.cuda.synchronize()
+    ref = [x.clone() for x in (br.t, br.status, br.steps, br.hit_vox)]
     try:
         res = autotune.tune("test-batch", lambda: br.render(40, 1e-4), fp32_model=False, repeats=1,
                             path=str(tmp_path / "tune.json"))
         assert res["config"] == autotune.current()
-        assert len(res["trials"]) >= 9 and res["ms"] > 0
+        assert len(res["trials"]) >= 36 and res["ms"] > 0
         again = autotune.tune("test-batch", lambda: br.render(40, 1e-4), fp32_model=False,
                               path=str(tmp_path / "tune.json"))
         assert again["cached"] and again["config"] == res["config"]
         br.render(40, 1e-4)
         torch.cuda.synchronize()
+        # the options change the launch schedule only: same bits as before
+        for a, b in zip(ref, (br.t, br.status, br.steps, br.hit_vox)):
+            assert torch.equal(a, b)
     finally:
         autotune.apply(saved)
 
