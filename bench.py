@@ -54,18 +54,18 @@ COUNTERS = {
     # both launches of the phased FP32 trace (first 24 evaluations, then the wide kernel)
     "k_sphere_trace": {"sources": ["ngl_trace_impl.h", "ngl_device.h", "ngl_mfma.h"],
                        "sha256": "f3eea318163c0b52781a9996e82e8ca1242b8c3f5a5dbe11ab5de26d506966ef",
-                       "fetch_kib": 315489.8 + 22951.6, "write_kib": 33466.1 + 3499.2},
+                       "fetch_kib": 312591.9 + 22987.4, "write_kib": 33450.7 + 3516.8},
     # every launch of one traversal to depth 6 (root and six child passes,
     # ray inverses, segment offsets)
     "traverse": {"sources": ["ngl_traverse.hip", "ngl_device.h"],
                  "sha256": "d1c4196cc585dd988bfdc7542ad8170f78014f558a7bdd22b721f7c9ab6091b1",
-                 "fetch_kib": 347901.8, "write_kib": 380743.9},
+                 "fetch_kib": 348071.9, "write_kib": 380740.2},
     # k_query_coop, FP32 features and matrix-core decoder
     "k_query": {"sources": ["ngl_query_impl.h", "ngl_device.h", "ngl_mfma.h"],
-                "sha256": "e5a08bc0f3e8718179c083885def3b666023362acd64a95eb77e60007dd3ac49",
-                "fetch_kib": 105024.9, "write_kib": 4096.0},
+                "sha256": "3cfbe96b6ca4fb74ed93a90f236ee5dcc1c33da45d08b2c9b227385948328b9c",
+                "fetch_kib": 105003.0, "write_kib": 4096.0},
 }
-FETCH_SCALE = (256 << 10) / 131088.1
+FETCH_SCALE = (256 << 10) / 131087.9
 WRITE_SCALE = (256 << 10) / 262144.0
 
 

@@ -89,9 +89,9 @@ int ngl_version(void);
  *  NGL_OPT_TRACE_WIDE: 1 (default) = the last phase of a phased trace
  *    serves each ray with a group of lanes (matrix-core decoders only),
  *    0 = one lane per ray throughout.
- *  NGL_OPT_COOP_GATHER: 1 (default) = the matrix-core query kernel
- *    gathers each feature row with M/8 lanes holding 8 elements each,
- *    0 = one lane per point reads whole rows (same results).
+ *  NGL_OPT_COOP_GATHER: 1 (default) = the matrix-core query and normal
+ *    kernels gather each feature row with a group of lanes, each holding a
+ *    slice of it, 0 = one lane per point reads whole rows (same results).
  *  NGL_OPT_QUERY_BLOCKS_PER_CU: blocks per compute unit of the
  *    cooperative query kernel, whose blocks loop over the points (0..64;
  *    0 = as many as are resident at once, default).

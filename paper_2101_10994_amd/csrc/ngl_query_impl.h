@@ -582,6 +582,15 @@ static int launch_normals(const ngl_model& md, const NormalArgs& A, hipStream_t 
   if constexpr (!MFMA) {
     return launch_normals_nw<M, FT, XYZ, DEC, false, 2>(md, A, s, 0);
   } else {
+    if (option(NGL_OPT_COOP_GATHER) == 0) {
+      // one lane per point and probe (same results as the cooperative form)
+      const size_t fixed = DecLds<DEC>::fixed_bytes(md.hidden, blend);
+      if (fixed + 4 * DEC::STAGE_BYTES <= 65536)
+        return launch_normals_nw<M, FT, XYZ, DEC, true, 4>(md, A, s, fixed + 4 * DEC::STAGE_BYTES);
+      if (fixed + 2 * DEC::STAGE_BYTES <= 65536)
+        return launch_normals_nw<M, FT, XYZ, DEC, true, 2>(md, A, s, fixed + 2 * DEC::STAGE_BYTES);
+      return launch_normals_nw<M, FT, XYZ, DEC, true, 1>(md, A, s, fixed + DEC::STAGE_BYTES);
+    }
     constexpr int NW = 4;
     size_t lds = DecLds<DEC>::fixed_bytes(md.hidden, blend) + NW * size_t(DEC::TILE_BYTES);
     NormalArgs B = A;

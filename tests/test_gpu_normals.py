@@ -122,3 +122,43 @@ def test_empty_and_argument_errors():
     n = ngl.sdf_normals(gm, 2, x=x)
     assert torch.isfinite(n).all()
 
+
+
+NORMAL_CASES = {
+    "m32-f32-spread": lambda: make_case(W.paper_shape(0), 64, 5, 32, 128, spread=True),
+    "m32-bf16-spread": lambda: make_case(W.paper_shape(0), 64, 5, 32, 128, spread=True, feat_dtype="f16",
+                                         w_dtype="bf16"),
+    "m8": lambda: make_case(W.paper_shape(0), 32, 4, 8, 32, embedded=True),
+    "m64": lambda: make_case(W.paper_shape(0), 32, 4, 64, 64, embedded=True, with_xyz=False),
+}
+
+
+@pytest.mark.parametrize("name", list(NORMAL_CASES))
+def test_cooperative_normals_are_the_one_lane_bits(name, f32_decoder):
+    """The cooperative normal kernel (each probe gathered tile-wise, four
+    lanes per point) gives the bits of the one-lane-per-point kernel: hit
+    points of a frame and scattered points (some outside the box), steps
+    from far below to above a finest cell, discrete and blended LODs."""
+    import torch
+    from paper_2101_10994_amd import ngl
+    gm = NORMAL_CASES[name]().gpu_model()
+    L = gm.num_lods
+    o, d = ngl.camera_rays(W.PAPER.eye, (0, 0, 0), (0, 1, 0), 45.0, 256, 192)
+    rng = np.random.default_rng(11)
+    x = torch.from_numpy(rng.uniform(-1.1, 1.1, (3, 20011)).astype(np.float32)).cuda()
+    old = ngl.get_option(ngl.OPT_COOP_GATHER)
+    try:
+        for lod, alpha in ((L, 0.0), (L - 2, 0.4)):
+            hits = ngl.trace_octree(gm, o, d, (lod + 1 if alpha > 0 else lod) + 1)
+            tr = ngl.sphere_trace(gm, o, d, lod, alpha, hits, 100, 1e-4)
+            assert int((tr["status"] == ngl.HIT).sum()) > 2000
+            rays = (o, d, tr["t"], tr["status"])
+            for h in (2.0 ** -14, 2.0 ** -9, 2.0 ** -5):
+                got = {}
+                for coop in (1, 0):
+                    ngl.set_option(ngl.OPT_COOP_GATHER, coop)
+                    got[coop] = (ngl.sdf_normals(gm, lod, alpha, h, rays=rays), ngl.sdf_normals(gm, lod, alpha, h, x=x))
+                for a, b in zip(got[1], got[0]):
+                    assert torch.equal(a, b), (lod, alpha, h)
+    finally:
+        ngl.set_option(ngl.OPT_COOP_GATHER, old)
