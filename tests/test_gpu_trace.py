@@ -156,39 +156,6 @@ def test_phased_trace_is_bitwise_the_single_launch(name, f32_decoder):
             ngl.set_option(k, v)
 
 
-@pytest.mark.parametrize("name", ["m32-f32", "m32-spread-bf16", "m8", "m64", "m16-bf16"])
-def test_trace_normals_is_the_trace_then_the_normals(name, f32_decoder):
-    """ngl_trace_normals (the normals of the rays that end in the first
-    phase computed on a second stream while the parked rays finish) gives
-    the bits of ngl_sphere_trace followed by ngl_sdf_normals at the hits,
-    for several pause counts (0: no phases, the two calls in sequence),
-    blended LODs, tile order and repeated calls on the same buffers."""
-    import torch
-    from paper_2101_10994_amd import ngl
-    gm = PHASE_CASES[name]().gpu_model()
-    L = gm.num_lods
-    o, d = ngl.camera_rays(W.PAPER.eye, (0, 0, 0), (0, 1, 0), 45.0, 384, 256)
-    keys = (ngl.OPT_TRACE_PAUSE1, ngl.OPT_TRACE_PAUSE2)
-    old = [ngl.get_option(k) for k in keys]
-    h = ngl.default_normal_step(gm)
-    try:
-        for lod, alpha in ((L, 0.0), (L - 2, 0.4)):
-            hits = ngl.trace_octree(gm, o, d, (lod + 1 if alpha > 0 else lod) + 1)
-            ref = ngl.sphere_trace(gm, o, d, lod, alpha, hits, 100, 1e-4)
-            nref = ngl.sdf_normals(gm, lod, alpha, h, rays=(o, d, ref["t"], ref["status"]))
-            assert int((ref["status"] == ngl.HIT).sum()) > 1000
-            out = None
-            for p1, width in ((24, 0), (24, 384), (8, 0), (0, 0), (24, 0)):
-                ngl.set_option(ngl.OPT_TRACE_PAUSE1, p1)
-                out = ngl.trace_normals(gm, o, d, lod, alpha, hits, 100, 1e-4, h=h, out=out, image_width=width)
-                for key in ("t", "status", "steps", "hit_vox"):
-                    assert torch.equal(out[key], ref[key]), (lod, alpha, p1, key)
-                assert torch.equal(out["normals"], nref), (lod, alpha, p1)
-    finally:
-        for k, v in zip(keys, old):
-            ngl.set_option(k, v)
-
-
 @pytest.mark.parametrize("name", ["m32-f32", "m32-spread-bf16", "m8"])
 def test_tile_order_is_bitwise_the_ray_order(name, f32_decoder):
     """Serving an image's rays in 8x8 pixel tiles (image_width > 0) changes
